@@ -1,0 +1,119 @@
+"""Pins of the checker's dilated binning (Sec. 4.1 Eq. 3-4) and (tile | depth)
+sort: brute-force tile membership, interval-intersection tile rectangles,
+invariants of the sorted list and ranges, offset independence."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import binning as bn
+from oracle import preprocess as pre
+from paper_2412_13547_amd import scenes
+
+CASES = [(1, 0, 0, 16), (2, 0, 0, 16), (2, 1, 1, 16), (2, 1, 0, 8), (3, 2, 1, 8), (4, 3, 2, 8),
+         (1, 0, 0, 32)]
+
+
+def _records(seed, n=40, w=96, h=80):
+    sc, cam = scenes.small_scene(seed, n, w, h, sh_degree=0)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    return r, cam
+
+
+@pytest.mark.parametrize("d,ox,oy,T", CASES)
+def test_sorted_lists_match_bruteforce(d, ox, oy, T):
+    r, cam = _records(d * 10 + ox)
+    g = bn.grid(cam.width, cam.height, d, ox, oy, T)
+    b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+    lists = bn.tile_lists_bruteforce(b["rects"], b["zbits"], g)
+    for t in range(g.num_tiles):
+        s, e = b["ranges"][t].tolist()
+        assert b["vals"][s:e].tolist() == lists[t]
+        assert all(int(k) >> 32 == t for k in b["keys"][s:e])
+
+
+@pytest.mark.parametrize("d,ox,oy,T", CASES)
+def test_invariants(d, ox, oy, T):
+    r, cam = _records(100 + d, n=60)
+    g = bn.grid(cam.width, cam.height, d, ox, oy, T)
+    b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+    P = b["keys"].numel()
+    assert int(b["tiles_touched"].sum()) == P
+    assert bool((b["keys"][1:] >= b["keys"][:-1]).all())
+    rg = b["ranges"]
+    lens = rg[:, 1] - rg[:, 0]
+    assert int(lens.sum()) == P
+    nz = lens > 0
+    starts = rg[nz, 0]
+    assert bool((starts[1:] == rg[nz, 1][:-1]).all()) and (P == 0 or int(starts[0]) == 0)
+
+
+def test_rect_is_interval_intersection():
+    """A tile is occupied iff its downsampled pixel span meets [c - r_ds, c + r_ds]."""
+    rng = np.random.default_rng(3)
+    for d, T in [(1, 16), (2, 16), (3, 8), (4, 8)]:
+        g = bn.grid(500, 300, d, 0, 0, T)
+        n = 300
+        u = torch.as_tensor(rng.uniform(-60, 560, n))
+        v = torch.as_tensor(rng.uniform(-60, 360, n))
+        rad = torch.as_tensor(rng.integers(1, 90, n))
+        xlo, xhi, ylo, yhi = bn.tile_rects(u, v, rad, torch.zeros(n, dtype=torch.bool), g)
+        for i in range(n):
+            cu = (float(u[i]) - (d - 1) / 2) / d
+            cv = (float(v[i]) - (d - 1) / 2) / d
+            rd = float(rad[i]) / d
+            xs = [tx for tx in range(g.gx) if tx * T <= cu + rd and (tx + 1) * T > cu - rd]
+            ys = [ty for ty in range(g.gy) if ty * T <= cv + rd and (ty + 1) * T > cv - rd]
+            got_x = list(range(int(xlo[i]), int(xhi[i])))
+            got_y = list(range(int(ylo[i]), int(yhi[i])))
+            assert got_x == xs and got_y == ys, (i, d, T)
+
+
+def test_eq5_roundtrip_places_centre_in_its_tile():
+    """A splat centred on full-res pixel (d i + o) is binned to the ds tile of i."""
+    for d in (2, 3, 4):
+        g = bn.grid(640, 480, d, 0, 0, 16)
+        for o in range(d):
+            i = np.arange(0, g.w_ds, 7)
+            u = torch.as_tensor(d * i + o, dtype=torch.float64)
+            # a radius smaller than the distance to the tile border keeps one tile
+            rad = torch.zeros_like(u, dtype=torch.int64)
+            xlo, xhi, _, _ = bn.tile_rects(u, u.clone().fill_(50.0), rad,
+                                           torch.zeros(len(u), dtype=torch.bool), g)
+            cu = (d * i + o - (d - 1) / 2) / d
+            exp_tile = np.floor(cu / 16).astype(int)
+            assert (xlo.numpy() == np.clip(exp_tile, 0, g.gx)).all()
+            assert (np.abs(cu - i) <= (d - 1) / (2 * d) + 1e-12).all()
+
+
+def test_binning_independent_of_offsets_when_divisible():
+    r, cam = _records(7, n=50, w=96, h=64)
+    ref = None
+    for ox in range(2):
+        for oy in range(2):
+            g = bn.grid(cam.width, cam.height, 2, ox, oy, 16)
+            b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+            cur = (b["keys"].tolist(), b["vals"].tolist())
+            ref = ref or cur
+            assert cur == ref
+
+
+def test_depth_key_is_float32_bits_and_ties_keep_index_order():
+    g = bn.grid(64, 64, 1, 0, 0, 16)
+    u = torch.tensor([30.0, 31.0, 32.0, 20.0], dtype=torch.float64)
+    z = torch.tensor([2.0, 1.5, 2.0, 1.0 + 1e-9], dtype=torch.float64)   # 1+1e-9 -> 1.0f
+    rad = torch.tensor([3, 3, 3, 3])
+    b = bn.bin_gaussians(u, u.clone(), z, rad, torch.zeros(4, dtype=torch.bool), g)
+    assert b["zbits"].tolist() == [int(np.float32(x).view(np.uint32)) for x in z.tolist()]
+    t = (1 * g.gx + 1)
+    s, e = b["ranges"][t].tolist()
+    assert b["vals"][s:e].tolist() == [3, 1, 0, 2]
+
+
+def test_ragged_grid_sizes():
+    g = bn.grid(101, 37, 2, 1, 0, 16)
+    assert (g.w_ds, g.h_ds) == (50, 19) and (g.gx, g.gy) == (4, 2)
+    g = bn.grid(101, 37, 3, 0, 2, 8)
+    assert (g.w_ds, g.h_ds) == (34, 12) and (g.gx, g.gy) == (5, 2)
+    assert bn.expected_key_bits(bn.grid(3840, 2160, 2, 0, 0, 16)) == math.ceil(math.log2(120 * 68))

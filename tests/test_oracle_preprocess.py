@@ -1,0 +1,161 @@
+"""Pins of the checker's preprocess (Sec. 3 Eq. 1, Sec. 4.1 covariance at the
+original focal length with the low-pass term) to library routines, closed
+forms, Monte-Carlo projection and invariants."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+from oracle import preprocess as pre
+from paper_2412_13547_amd import scenes
+
+
+def _scene(means, scales, quats, opac, sh=None, degree=0):
+    means = np.asarray(means, np.float32).reshape(3, -1)
+    n = means.shape[1]
+    if sh is None:
+        sh = np.zeros(((degree + 1) ** 2, 3, n), np.float32)
+    return scenes.Scene(means, np.asarray(scales, np.float32).reshape(3, n),
+                        np.asarray(quats, np.float32).reshape(4, n),
+                        np.asarray(opac, np.float32).reshape(n), np.asarray(sh, np.float32), degree)
+
+
+def test_rotation_matches_scipy():
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=(64, 4)) * rng.uniform(0.1, 3.0, size=(64, 1))   # not unit on purpose
+    ours = pre.rotation(torch.as_tensor(q)).numpy()
+    ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()            # scipy is scalar-last
+    np.testing.assert_allclose(ours, ref, atol=1e-13)
+
+
+def test_covariance_spectrum_and_quaternion_invariance():
+    rng = np.random.default_rng(1)
+    s = rng.uniform(0.01, 0.3, size=(32, 3))
+    q = rng.normal(size=(32, 4))
+    S = pre.covariance_3d(torch.as_tensor(s), torch.as_tensor(q)).numpy()
+    np.testing.assert_allclose(S, np.transpose(S, (0, 2, 1)), atol=1e-16)
+    ev = np.sort(np.linalg.eigvalsh(S), 1)
+    np.testing.assert_allclose(ev, np.sort(s ** 2, 1), rtol=1e-10, atol=1e-16)
+    S2 = pre.covariance_3d(torch.as_tensor(s), torch.as_tensor(-2.5 * q)).numpy()
+    np.testing.assert_allclose(S2, S, atol=1e-15)
+    # principal axes are the columns of R: Sigma R e_k = s_k^2 R e_k
+    R = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    for k in range(3):
+        np.testing.assert_allclose(np.einsum("nij,nj->ni", S, R[:, :, k]),
+                                   (s[:, k] ** 2)[:, None] * R[:, :, k], atol=1e-14)
+
+
+def test_on_axis_isotropic_closed_form():
+    f, z, s = 300.0, 3.0, 0.05
+    cam = scenes.identity_camera(201, 151, f)
+    sc = _scene([0, 0, z], [s, s, s], [1, 0, 0, 0], [0.5])
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    s32 = float(np.float32(s))
+    a = (f * s32 / float(np.float32(z))) ** 2 + 0.3
+    assert abs(float(r["a"][0]) - a) < 1e-9 * a and abs(float(r["c"][0]) - a) < 1e-9 * a
+    assert abs(float(r["b"][0])) < 1e-12
+    assert abs(float(r["A"][0]) - 1 / a) < 1e-12 and abs(float(r["B"][0])) < 1e-12
+    assert int(r["radius"][0]) == math.ceil(3 * math.sqrt(a))
+    assert float(r["u"][0]) == 100.0 and float(r["v"][0]) == 75.0
+
+
+def test_projection_matches_homogeneous_pinhole():
+    sc, cam = scenes.small_scene(3, 200, 96, 64)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    K = np.array([[cam.fx, 0, cam.cx], [0, cam.fy, cam.cy], [0, 0, 1.0]])
+    X = np.vstack([sc.means.astype(np.float64), np.ones((1, sc.n))])
+    h = K @ cam.w2c.astype(np.float64) @ X
+    np.testing.assert_allclose(r["u"].numpy(), h[0] / h[2], atol=1e-9)
+    np.testing.assert_allclose(r["v"].numpy(), h[1] / h[2], atol=1e-9)
+    np.testing.assert_allclose(r["z"].numpy(), h[2], atol=1e-12)
+
+
+def test_projected_covariance_matches_monte_carlo():
+    """Sample 3D points, project each through the pinhole, compare covariances."""
+    rng = np.random.default_rng(5)
+    cam = scenes.look_at_camera(640, 480, 500.0, eye=(0.7, -0.4, -4.0), target=(0.2, 0.1, 0.0))
+    R = cam.w2c[:, :3].astype(np.float64)
+    t = cam.w2c[:, 3].astype(np.float64)
+    means = np.array([[0.3, -0.2, 0.4], [-0.5, 0.35, -0.2], [0.1, 0.1, 0.1]]).T
+    scales = np.array([[0.02, 0.004, 0.009], [0.006, 0.015, 0.003], [0.01, 0.01, 0.002]]).T
+    quats = rng.normal(size=(4, 3))
+    sc = _scene(means, scales, quats, [0.5] * 3)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    m64 = sc.means.astype(np.float64)
+    rot = Rotation.from_quat(sc.quats.astype(np.float64).T[:, [1, 2, 3, 0]]).as_matrix()
+    for i in range(3):
+        z = rng.normal(size=(400_000, 3))
+        pts = m64[:, i] + (z * sc.scales[:, i].astype(np.float64)) @ rot[i].T
+        pc = pts @ R.T + t
+        uv = np.stack([cam.fx * pc[:, 0] / pc[:, 2] + cam.cx, cam.fy * pc[:, 1] / pc[:, 2] + cam.cy])
+        emp = np.cov(uv)
+        ours = np.array([[float(r["a"][i]) - 0.3, float(r["b"][i])],
+                         [float(r["b"][i]), float(r["c"][i]) - 0.3]])
+        scale = np.abs(ours).max()
+        assert np.abs(emp - ours).max() < 0.01 * scale, (i, emp, ours)
+
+
+def test_fov_guard_freezes_jacobian_outside():
+    cam = scenes.identity_camera(100, 100, 100.0)
+    lim = 1.3 * 100 / (2 * 100.0)
+    z = 2.0
+    xs = [lim * z * 1.5, lim * z * 2.0, lim * z * 3.0]
+    sc = _scene([xs, [0.1] * 3, [z] * 3], [[0.05] * 3, [0.02] * 3, [0.03] * 3],
+                [[0.9] * 3, [0.1] * 3, [0.3] * 3, [-0.2] * 3], [0.5] * 3)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    assert bool(r["fovx"].all()) and not bool(r["fovy"].any())
+    for k in ("a", "b", "c"):
+        np.testing.assert_allclose(r[k].numpy(), r[k].numpy()[0], rtol=1e-12)
+
+
+def test_near_plane_and_non_finite_cull():
+    cam = scenes.identity_camera(64, 64, 64.0)
+    means = [[0, 0, 0, 0], [0, 0, 0, 0], [0.19, 0.21, 3.0, 3.0]]
+    scales = [[0.05] * 4] * 3
+    quats = [[1] * 4, [0] * 4, [0] * 4, [0] * 4]
+    sc = _scene(means, scales, quats, [0.5, 0.5, 0.5, np.nan])
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    assert r["culled"].tolist() == [True, False, False, True]
+    assert int(r["radius"][0]) == 0 and int(r["radius"][3]) == 0
+
+
+def test_colour_degree0_and_clamp():
+    cam = scenes.identity_camera(64, 64, 64.0)
+    k0 = np.array([[[1.0, -3.0], [0.0, 0.2], [-1.0, 0.5]]], np.float32)   # (1, 3, 2)
+    sc = _scene([[0, 0.1], [0, 0], [3, 3]], [[0.05] * 2] * 3, [[1, 1], [0, 0], [0, 0], [0, 0]],
+                [0.5, 0.5], sh=k0, degree=0)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    y00 = 0.5 / math.sqrt(math.pi)
+    raw = k0[0].T.astype(np.float64) * y00 + 0.5
+    np.testing.assert_allclose(r["rgb_raw"].numpy(), raw, atol=1e-15)
+    np.testing.assert_allclose(r["rgb"].numpy(), np.maximum(raw, 0), atol=1e-15)
+    assert r["clamp"].numpy().tolist() == (raw < 0).tolist()
+
+
+def test_colour_direction_is_camera_to_mean():
+    # camera at (0, 0, -5) looking at the origin; a Gaussian at the origin is
+    # seen along +z world.  Degree-1 coefficient on m = 0 (z) only.
+    cam = scenes.look_at_camera(64, 64, 64.0, eye=(0, 0, -5.0))
+    sh = np.zeros((4, 3, 1), np.float32)
+    sh[2, :, 0] = 1.0
+    sc = _scene([0, 0, 0], [0.05] * 3, [1, 0, 0, 0], [0.5], sh=sh, degree=1)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    np.testing.assert_allclose(r["rgb"].numpy()[0], 0.5 + math.sqrt(3 / (4 * math.pi)), atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_degree_uses_leading_coefficients_only(seed):
+    sc, cam = scenes.small_scene(seed, 30, 64, 48, sh_degree=3)
+    a = pre.preprocess(pre.params(sc), pre.camera(cam))
+    sc2 = sc.copy()
+    sc2.sh_degree = 1
+    sc2.sh[4:] = 1e3      # ignored at degree 1
+    b = pre.preprocess(pre.params(sc2), pre.camera(cam))
+    sc3 = sc.copy()
+    sc3.sh_degree = 1
+    sc3.sh[4:] = 0
+    c = pre.preprocess(pre.params(sc3), pre.camera(cam))
+    np.testing.assert_allclose(b["rgb_raw"].numpy(), c["rgb_raw"].numpy(), atol=0)
+    assert not np.allclose(a["rgb_raw"].numpy(), c["rgb_raw"].numpy())

@@ -1,0 +1,197 @@
+"""Pins of the checker's compositing (Sec. 3 Eq. 2 on the dilated pixel set of
+Sec. 4.1): hand-derived closed forms (tests/golden), a plain per-pixel loop over
+all Gaussians, invariants, and the full-render special cases."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import binning as bn
+from oracle import pipeline
+from oracle import preprocess as pre
+from oracle import raster as rs
+from paper_2412_13547_amd import scenes
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                     "compositing_closed_forms.json")))
+F64 = torch.float64
+
+
+def _rec(u, v, A, B, C, o, rgb):
+    t = lambda x: torch.as_tensor(np.asarray(x, np.float64))
+    return dict(u=t(u), v=t(v), A=t(A), B=t(B), C=t(C), opacity=t(o), rgb=t(rgb).reshape(-1, 3))
+
+
+def _render_records(rec, z, radius, g, bg=(0.0, 0.0, 0.0)):
+    n = rec["u"].numel()
+    b = bn.bin_gaussians(rec["u"], rec["v"], torch.as_tensor(z, dtype=F64),
+                         torch.as_tensor(radius), torch.zeros(n, dtype=torch.bool), g)
+    return rs.raster_forward(rec, b["vals"], b["ranges"], g, bg=bg), b
+
+
+def _coincident(opacities, colours, X=20, Y=12):
+    n = len(opacities)
+    rec = _rec([X] * n, [Y] * n, [0.05] * n, [0.0] * n, [0.05] * n, opacities, colours)
+    g = bn.grid(48, 32, 1, 0, 0, 16)
+    out, _ = _render_records(rec, z=np.arange(1, n + 1, dtype=np.float64), radius=[10] * n, g=g)
+    return out, (Y, X)
+
+
+def test_saturation_four_coincident():
+    gd = GOLDEN["saturation_four_coincident"]
+    cols = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0], [1.0, 1.0, 1.0]])
+    out, (y, x) = _coincident([gd["opacity"]] * 4, cols)
+    want = np.array(gd["colour_weights"]) @ cols
+    np.testing.assert_allclose(out["image"][:, y, x].numpy(), want, atol=1e-15)
+    assert abs(float(out["t_final"][y, x]) - gd["t_final"]) < 1e-15
+    assert int(out["last_contrib"][y, x]) == gd["last_contrib"]
+    assert int(out["n_eval"][y, x]) == gd["n_eval"]
+
+
+def test_two_splats_and_clamp_and_skip():
+    gd = GOLDEN["two_splats"]
+    cols = np.array([[0.2, 0.4, 0.8], [0.9, 0.1, 0.5]])
+    out, (y, x) = _coincident([gd["o1"], gd["o2"]], cols)
+    np.testing.assert_allclose(out["image"][:, y, x].numpy(), np.array(gd["colour_weights"]) @ cols,
+                               atol=1e-15)
+    assert abs(float(out["t_final"][y, x]) - gd["t_final"]) < 1e-15
+    gd = GOLDEN["opacity_above_clamp"]
+    out, (y, x) = _coincident([gd["opacity"]], [[0.3, 0.6, 0.9]])
+    np.testing.assert_allclose(out["image"][:, y, x].numpy(),
+                               gd["colour_weight"] * np.array([0.3, 0.6, 0.9]), atol=1e-15)
+    assert abs(float(out["t_final"][y, x]) - gd["t_final"]) < 1e-15
+    gd = GOLDEN["below_skip_threshold"]
+    out, (y, x) = _coincident([gd["opacity"]], [[0.3, 0.6, 0.9]])
+    assert float(out["t_final"][y, x]) == gd["t_final"]
+    assert int(out["last_contrib"][y, x]) == gd["last_contrib"]
+    assert float(out["image"][:, y, x].abs().max()) == 0.0
+
+
+def test_single_gaussian_at_offset():
+    A, B, C, o = 0.02, 0.007, 0.05, 0.8
+    rgb = np.array([0.3, 0.5, 0.7])
+    rec = _rec([20.3], [13.6], [A], [B], [C], [o], rgb)
+    g = bn.grid(48, 32, 1, 0, 0, 16)
+    out, _ = _render_records(rec, [2.0], [40], g)
+    for (x, y) in [(20, 13), (25, 10), (14, 20), (30, 30)]:
+        dx, dy = 20.3 - x, 13.6 - y
+        a = o * math.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)
+        want = a * rgb if a >= 1 / 255 else 0 * rgb
+        np.testing.assert_allclose(out["image"][:, y, x].numpy(), want, atol=1e-15)
+
+
+def test_dilated_pixel_position_and_background():
+    """Downsampled pixel (i, j) is blended at (d i + o_x, d j + o_y); bg fills T."""
+    A, C, o = 0.03, 0.03, 0.7
+    rgb = np.array([0.2, 0.9, 0.4])
+    rec = _rec([21.0], [11.0], [A], [0.0], [C], [o], rgb)
+    bgc = (0.1, 0.2, 0.3)
+    for d, ox, oy in [(2, 1, 1), (3, 0, 2), (2, 0, 1)]:
+        g = bn.grid(48, 40, d, ox, oy, 8)
+        out, _ = _render_records(rec, [2.0], [60], g, bg=bgc)
+        for (i, j) in [(0, 0), (5, 3), (10, 5)]:
+            X, Y = d * i + ox, d * j + oy
+            a = o * math.exp(-0.5 * (A * (21 - X) ** 2 + C * (11 - Y) ** 2))
+            a = a if a >= 1 / 255 else 0.0
+            want = a * rgb + (1 - a) * np.array(bgc)
+            np.testing.assert_allclose(out["image"][:, j, i].numpy(), want, atol=1e-15)
+
+
+CASES = [(1, 0, 0, 16), (2, 0, 0, 16), (2, 1, 1, 8), (3, 1, 2, 8), (4, 3, 0, 8), (1, 0, 0, 8)]
+
+
+@pytest.mark.parametrize("d,ox,oy,T", CASES)
+def test_tile_path_equals_per_pixel_loop(d, ox, oy, T):
+    sc, cam = scenes.small_scene(40 + d + ox, 48, 64, 48, sh_degree=1)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    g = bn.grid(cam.width, cam.height, d, ox, oy, T)
+    b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+    bgc = (0.05, 0.1, 0.0)
+    out = rs.raster_forward(r, b["vals"], b["ranges"], g, bg=bgc)
+    order = sorted(range(sc.n), key=lambda i: (int(b["zbits"][i]), i))
+    rects = b["rects"].tolist()
+    for j in range(g.h_ds):
+        for i in range(g.w_ds):
+            tx, ty = i // T, j // T
+            member = lambda k: (rects[k][0] <= tx < rects[k][1] and rects[k][2] <= ty < rects[k][3])
+            col, Tf, last = rs.render_pixel_loop(r, order, member, d * i + ox, d * j + oy, bgc)
+            np.testing.assert_allclose(out["image"][:, j, i].numpy(), col, rtol=0, atol=1e-13)
+            assert abs(float(out["t_final"][j, i]) - Tf) <= 1e-15
+            assert int(out["last_contrib"][j, i]) == last
+
+
+def test_chunking_does_not_change_results():
+    sc, cam = scenes.small_scene(9, 64, 64, 64, sh_degree=0)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    g = bn.grid(cam.width, cam.height, 2, 1, 0, 8)
+    b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+    a = rs.raster_forward(r, b["vals"], b["ranges"], g, chunk=1024)
+    c = rs.raster_forward(r, b["vals"], b["ranges"], g, chunk=3)
+    for k in ("last_contrib", "n_eval", "n_blend"):
+        assert torch.equal(a[k], c[k])
+    np.testing.assert_allclose(a["image"].numpy(), c["image"].numpy(), atol=1e-14)
+    assert torch.equal(a["t_final"], c["t_final"])
+
+
+def test_zero_opacity_gives_background():
+    sc, cam = scenes.small_scene(2, 30, 64, 48, sh_degree=0)
+    sc.opacities[:] = 0.0
+    bgc = (0.25, 0.5, 0.75)
+    f = pipeline.forward(sc, cam, 2, 1, 0, 16, bg=bgc)
+    for ch in range(3):
+        assert float((f["image"][ch] - bgc[ch]).abs().max()) == 0.0
+    sc.opacities[:] = 0.9 / 255.0
+    f = pipeline.forward(sc, cam, 1, 0, 0, 16, bg=bgc)
+    assert float((f["image"][1] - bgc[1]).abs().max()) == 0.0
+    assert int(f["last_contrib"].max()) == 0
+
+
+def test_permuting_gaussians_permutes_nothing_in_the_image():
+    sc, cam = scenes.small_scene(11, 50, 64, 48, sh_degree=2)
+    f0 = pipeline.forward(sc, cam, 2, 0, 1, 8)
+    perm = np.random.default_rng(0).permutation(sc.n)
+    f1 = pipeline.forward(sc.subset(perm), cam, 2, 0, 1, 8)
+    assert len(set(f0["bins"]["zbits"].tolist())) == sc.n      # distinct depths
+    np.testing.assert_allclose(f1["image"].numpy(), f0["image"].numpy(), atol=1e-14)
+    assert torch.equal(f1["n_eval"], f0["n_eval"])
+
+
+def _large_gaussian_scene(seed, n, W, H):
+    """Splats whose rectangles cover the whole image in every tile grid."""
+    sc, cam = scenes.small_scene(seed, n, W, H, sh_degree=1, scale_mean=-0.4, depth=(3.0, 5.0),
+                                 spread=0.2)
+    return sc, cam
+
+
+def test_dilated_equals_subsampled_full_render_for_image_covering_splats():
+    sc, cam = _large_gaussian_scene(5, 12, 64, 48)
+    full = pipeline.forward(sc, cam, 1, 0, 0, 16)
+    assert int(full["bins"]["tiles_touched"].min()) == full["grid"].num_tiles
+    for d in (2, 3):
+        for ox in range(d):
+            for oy in range(d):
+                f = pipeline.forward(sc, cam, d, ox, oy, 16)
+                assert int(f["bins"]["tiles_touched"].min()) == f["grid"].num_tiles
+                sub = full["image"][:, oy::d, ox::d][:, :f["grid"].h_ds, :f["grid"].w_ds]
+                np.testing.assert_allclose(f["image"].numpy(), sub.numpy(), atol=1e-14)
+                assert torch.equal(f["last_contrib"],
+                                   full["last_contrib"][oy::d, ox::d][:f["grid"].h_ds, :f["grid"].w_ds])
+
+
+def test_merged_phases_close_to_full_render_reported():
+    """Merging the 4 offsets at d = 2 reproduces the full render up to tile-edge
+    differences (Sec. 4.1 reports > 70 dB on trained scenes).  Reported, with a
+    loose floor, since the synthetic splats differ from trained ones."""
+    sc, cam = scenes.small_scene(21, 400, 128, 96, sh_degree=0, scale_mean=-2.8)
+    full = pipeline.forward(sc, cam, 1, 0, 0, 16)["image"].numpy()
+    merged = np.zeros_like(full)
+    for ox in range(2):
+        for oy in range(2):
+            merged[:, oy::2, ox::2] = pipeline.forward(sc, cam, 2, ox, oy, 16)["image"].numpy()
+    mse = float(((merged - full) ** 2).mean())
+    psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    print(f"merged-phase PSNR vs full render: {psnr:.1f} dB")
+    assert 0 < mse and psnr > 60.0
