@@ -159,3 +159,42 @@ def test_degree_uses_leading_coefficients_only(seed):
     c = pre.preprocess(pre.params(sc3), pre.camera(cam))
     np.testing.assert_allclose(b["rgb_raw"].numpy(), c["rgb_raw"].numpy(), atol=0)
     assert not np.allclose(a["rgb_raw"].numpy(), c["rgb_raw"].numpy())
+
+
+def test_fov_guard_uses_each_axis_own_limit():
+    cam = scenes.identity_camera(200, 80, 100.0)      # limx = 1.3, limy = 0.52
+    z = 2.0
+    ys = [0.6 * z, 0.9 * z, 1.2 * z]                   # beyond limy, inside limx
+    sc = _scene([[0.1] * 3, ys, [z] * 3], [[0.05] * 3, [0.02] * 3, [0.03] * 3],
+                [[0.9] * 3, [0.1] * 3, [0.3] * 3, [-0.2] * 3], [0.5] * 3)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    assert bool(r["fovy"].all()) and not bool(r["fovx"].any())
+    for k in ("a", "b", "c"):
+        np.testing.assert_allclose(r[k].numpy(), r[k].numpy()[0], rtol=1e-12)
+    xs = [1.0 * z, 1.2 * z]                            # inside limx: Jacobian must change
+    sc = _scene([xs, [0.1] * 2, [z] * 2], [[0.05] * 2, [0.02] * 2, [0.03] * 2],
+                [[0.9] * 2, [0.1] * 2, [0.3] * 2, [-0.2] * 2], [0.5] * 2)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    assert not bool(r["fovx"].any()) and abs(float(r["a"][0] - r["a"][1])) > 1e-3
+
+
+def test_conic_is_inverse_of_low_passed_covariance():
+    sc, cam = scenes.small_scene(8, 100, 96, 64, sh_degree=0)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    Q = torch.stack([torch.stack([r["A"], r["B"]], 1), torch.stack([r["B"], r["C"]], 1)], 1)
+    S = torch.stack([torch.stack([r["a"], r["b"]], 1), torch.stack([r["b"], r["c"]], 1)], 1)
+    eye = torch.eye(2, dtype=torch.float64).expand(sc.n, 2, 2)
+    ok = ~r["culled"]
+    np.testing.assert_allclose((Q @ S)[ok].numpy(), eye[ok].numpy(), atol=1e-10)
+
+
+def test_rendered_splat_is_elongated_along_its_long_axis():
+    """A Gaussian stretched along world x, seen head-on, falls off slower in x."""
+    from oracle import pipeline
+    cam = scenes.identity_camera(64, 64, 64.0)
+    sh = np.zeros((1, 3, 1), np.float32)
+    sc = _scene([0, 0, 3.0], [0.3, 0.08, 0.05], [1, 0, 0, 0], [0.9], sh=sh, degree=0)
+    f = pipeline.forward(sc, cam, 1, 0, 0, 16)
+    img = f["image"][0].numpy()
+    c = 31
+    assert img[c, c + 8] > 0.1 and img[c, c + 8] > 2 * img[c + 8, c]
