@@ -1,0 +1,246 @@
+"""Benchmark: forward + backward ms/iter and Gaussian-pixel evals/s of the
+dilated rasterizer at 4K (3M Gaussians, SH degree 3, stride 2, offsets
+cycling through the 4 phases), against the plain full-resolution path on the
+same view.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-plain]
+
+One step = preprocess -> pairs + sort + ranges -> dilated blend -> L1 loss
+gradient against the full-resolution target -> blend backward -> preprocess
+backward with densification statistics, on inputs already resident in HBM.
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_VALU = 256 * 4 * 16 * 2.4e9   # FP32 lane-ops/s (256 CU x 4 SIMD x 16 lanes x 2.4 GHz)
+# op model (FP32 VALU lane-operations per Gaussian-pixel evaluation)
+OPS_FWD = 21
+OPS_BWD = 55
+STAGES = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd", "preprocess_bwd")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+class Runner:
+    """One view of one scene: every buffer allocated once, steps reuse them."""
+
+    def __init__(self, api, torch, dev, cam, target, stride, tile=16):
+        self.api, self.torch, self.dev = api, torch, dev
+        self.stride = stride
+        self.ctx = api.Context(0)
+        self.view = api.View(self.ctx, dev.n, cam, stride, 0, 0, tile)
+        self.target = target
+        n = dev.n
+        self.grads = dev.zeros_like()
+        self.pos = torch.empty(n, dtype=torch.float32, device="cuda")
+        self.col = torch.empty(n, dtype=torch.float32, device="cuda")
+        self.vis = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self.images = {}
+        self.loss = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def _bufs(self):
+        shape = self.view.image_shape
+        if shape not in self.images:
+            t = self.torch
+            self.images[shape] = (t.empty(shape, dtype=t.float32, device="cuda"),
+                                  t.empty(shape, dtype=t.float32, device="cuda"))
+        return self.images[shape]
+
+    def step(self, k, events=None):
+        from paper_2412_13547_amd import scenes
+        ox, oy = scenes.phase_offsets(k, self.stride)
+        v = self.view
+        if (int(v.dil.off_x), int(v.dil.off_y)) != (ox, oy):
+            v.set_offsets(ox, oy)
+        img, dL = self._bufs()
+        rec = (lambda i: events[i].record()) if events else (lambda i: None)
+        rec(0)
+        v.preprocess_fwd(self.dev)
+        rec(1)
+        v.bin_sort(self.dev)
+        rec(2)
+        v.raster_fwd(img)
+        rec(3)
+        v.l1_grad(img, self.target, dL, self.loss)
+        rec(4)
+        v.raster_bwd(img, dL)
+        rec(5)
+        v.preprocess_bwd(self.dev, self.grads, self.pos, self.col, self.vis)
+        rec(6)
+
+    def evals(self, k):
+        """Gaussian-pixel evaluations of step k: entries examined per pixel in
+        the forward plus entries blended (walked back) in the backward."""
+        t = self.torch
+        from paper_2412_13547_amd import scenes
+        ox, oy = scenes.phase_offsets(k, self.stride)
+        self.view.set_offsets(ox, oy)
+        img, _ = self._bufs()
+        shape = self.view.image_shape
+        last = t.empty(shape[1:], dtype=t.int32, device="cuda")
+        neval = t.empty(shape[1:], dtype=t.int32, device="cuda")
+        self.view.forward(self.dev, img, last_contrib=last, n_eval=neval)
+        t.cuda.synchronize()
+        return int(neval.sum(dtype=t.int64)), int(last.sum(dtype=t.int64))
+
+    def timed(self, steps, warmup):
+        t = self.torch
+        for k in range(warmup):
+            self.step(k)
+        t.cuda.synchronize()
+        ev = [[t.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
+        t.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            self.step(warmup + k, ev[k])
+        t.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_step = [e[0].elapsed_time(e[6]) for e in ev]
+        stage = {s: statistics.median([e[i].elapsed_time(e[i + 1]) for e in ev])
+                 for i, s in enumerate(STAGES)}
+        return wall, per_step, stage
+
+
+def cpu_baseline(runner, seconds):
+    """The CPU checker timed on a bounded sample of tiles of the same view:
+    forward + backward of randomly drawn tiles until ~`seconds` elapse."""
+    import numpy as np
+    import torch
+    from oracle import backward as obw
+    from oracle import binning as obn
+    from oracle import raster as ors
+    v = runner.view
+    v.set_offsets(0, 0)
+    v.forward(runner.dev, runner._bufs()[0])
+    torch.cuda.synchronize()
+    r32 = v.records().cpu()
+    r = r32.to(torch.float64)
+    rec = dict(u=r[:, 0], v=r[:, 1], A=r[:, 2], B=r[:, 3], C=r[:, 4], opacity=r[:, 5],
+               rgb=r[:, 6:9].clone())
+    vals = v.pair_vals().cpu().to(torch.int64)
+    ranges = v.ranges().cpu().to(torch.int64)
+    cam = v.cam
+    g = obn.grid(cam.width, cam.height, v.dil.stride, 0, 0, v.opt.tile)
+    rng = np.random.default_rng(0)
+    nonempty = np.nonzero((ranges[:, 1] - ranges[:, 0]).numpy() > 0)[0]
+    evals = 0
+    tiles = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and tiles < len(nonempty):
+        t = int(rng.choice(nonempty))
+        o = ors.raster_forward(rec, vals, ranges, g, tiles=[t])
+        dl = torch.zeros(3, g.h_ds, g.w_ds, dtype=torch.float64)
+        ii, jj, _, _ = ors.pixel_grid(g, t)
+        dl[:, jj, ii] = 1.0 / dl.numel()
+        obw.raster_backward(rec, vals, ranges, g, dl, tiles=[t])
+        evals += int(o["n_eval"].sum()) + int(o["last_contrib"].sum())
+        tiles += 1
+    el = time.perf_counter() - t0
+    return {"value": evals / el, "unit": "Gaussian-pixel evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{tiles} random non-empty tiles of phase (0,0), blend forward + backward "
+                      f"in float64 ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2412_13547_amd import api, scenes
+
+    sc, cam, tgt = scenes.workload(args.workload, n=args.n)
+    w = scenes.WORKLOADS[args.workload]
+    stride = w.get("stride", 1)
+    dev = api.DeviceScene.from_scene(sc)
+    target = torch.as_tensor(tgt).cuda()
+    del tgt
+    print(f"# scene ready: n={sc.n} {cam.width}x{cam.height} stride={stride}", file=sys.stderr,
+          flush=True)
+
+    dil = Runner(api, torch, dev, cam, target, stride)
+    wall, per_step, stage = dil.timed(args.steps, args.warmup)
+    ms = 1000.0 * wall / args.steps
+    ev = [dil.evals(k) for k in range(stride * stride)]
+    fwd_evals = float(np.mean([e[0] for e in ev]))
+    bwd_evals = float(np.mean([e[1] for e in ev]))
+    pairs = int(dil.view.state.pair_count)
+    print(f"# dilated: {ms:.3f} ms/step, pairs {pairs}, stages {stage}", file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain and stride > 1:
+        pr = Runner(api, torch, dev, cam, target, 1)
+        pwall, pper, pstage = pr.timed(max(3, args.steps // 2), 2)
+        pe = pr.evals(0)
+        pms = 1000.0 * pwall / max(3, args.steps // 2)
+        plain = {"ms_per_step": pms, "evals_per_s": (pe[0] + pe[1]) / (pms / 1000.0),
+                 "pairs": int(pr.view.state.pair_count), "stages_ms": pstage,
+                 "fwd_evals": pe[0], "bwd_evals": pe[1]}
+        print(f"# plain: {pms:.3f} ms/step, stages {pstage}", file=sys.stderr, flush=True)
+        del pr
+
+    # roofline of the dominant kernel (the stage taking the most time)
+    dom = max(("raster_fwd", "raster_bwd", "bin_sort", "preprocess_fwd", "preprocess_bwd"),
+              key=lambda s: stage[s])
+    n = sc.n
+    if dom in ("raster_fwd", "raster_bwd"):
+        ops = fwd_evals * OPS_FWD if dom == "raster_fwd" else bwd_evals * OPS_BWD
+        achieved = ops / (stage[dom] / 1000.0) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_VALU / 1e12,
+                "unit": "T lane-ops/s", "frac": achieved / (PEAK_VALU / 1e12), "traffic": None}
+    else:
+        per = {"bin_sort": pairs * 44.0, "preprocess_fwd": n * 296.0, "preprocess_bwd": n * 520.0}[dom]
+        achieved = per / (stage[dom] / 1000.0) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9), "traffic": None}
+
+    out = {
+        "metric": "fwd+bwd ms/iter & Gaussian-pixel evals/s, 4K dilated batched vs plain",
+        "value": (fwd_evals + bwd_evals) / (ms / 1000.0),
+        "unit": "Gaussian-pixel evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "ms_p10": float(np.percentile(per_step, 10)), "ms_p50": float(np.median(per_step)),
+        "ms_p90": float(np.percentile(per_step, 90)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["name"], "gaussians": n, "sh_degree": sc.sh_degree,
+                   "width": cam.width, "height": cam.height, "stride": stride, "tile": 16,
+                   "phases": "cycle (0,0),(1,0),(0,1),(1,1)" if stride == 2 else "single"},
+        "pairs": pairs, "fwd_evals": fwd_evals, "bwd_evals": bwd_evals,
+        "stages_ms": stage,
+        "plain": plain,
+        "speedup_vs_plain": (plain["ms_per_step"] / ms) if plain else None,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(dil, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

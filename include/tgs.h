@@ -1,0 +1,241 @@
+/*
+ * tgs.h - C ABI of libtgs, the dilated differentiable Gaussian-splat rasterizer
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the hot path of one fitting iteration of Turbo-GS
+ * (arXiv 2412.13547): Gaussian parameters (Sec. 3, Eq. 1 and the SH colour
+ * model), a pinhole camera with its ORIGINAL focal length (Sec. 4.1) and a
+ * dilation pattern (stride d, offsets o_x, o_y; Sec. 4.1 and Fig. 2) go in;
+ * the downsampled image of that pattern (Sec. 4.1, Eq. 3-5) and the
+ * gradients of a loss with respect to every Gaussian attribute, with the
+ * per-Gaussian densification statistics of Sec. 4.3, come out.
+ *
+ * Conventions shared by every call
+ *  - Pointers named "device" point to HIP device memory; everything else is
+ *    host memory.  The caller allocates every device buffer and keeps
+ *    ownership; the library never frees caller memory.
+ *  - All float data is IEEE float32, structure-of-arrays:
+ *      means[3][n], scales[3][n] (positive, already exponentiated),
+ *      quats[4][n] (w, x, y, z; normalised inside), opacities[n] (in [0,1],
+ *      already passed through a sigmoid), sh[sh_coeffs][3][n].
+ *    Images are planar: image[3][H_ds][W_ds], row-major per channel.
+ *  - The dilated image of (d, o_x, o_y) has W_ds = ceil((W - o_x) / d),
+ *    H_ds = ceil((H - o_y) / d) pixels; downsampled pixel (i, j) is rendered
+ *    at full-resolution pixel (d i + o_x, d j + o_y), whose centre is at those
+ *    integer coordinates.
+ *  - Device work is enqueued on the given stream; calls return before it
+ *    finishes, except tgs_forward / tgs_bin_sort, which read the pair count
+ *    back to the host once (see tgs_bin_sort).
+ *  - Arguments are validated on the host before any HIP call; a failing call
+ *    has enqueued nothing.  No C++ exception crosses this interface.
+ *    tgs_last_error() returns a thread-local description of the last failure.
+ *  - Not thread-safe per context: calls that share a context or a workspace
+ *    must be ordered by the caller.
+ */
+#ifndef TGS_H
+#define TGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tgs_status {
+    TGS_OK = 0,
+    TGS_ERR_INVALID_ARG = 1, /* a pointer, size or option is out of range      */
+    TGS_ERR_CAPACITY = 2,    /* the workspace holds fewer pairs than required  */
+    TGS_ERR_HIP = 3,         /* a HIP runtime call failed                      */
+    TGS_ERR_NO_DEVICE = 4,   /* no HIP device with the requested ordinal       */
+    TGS_ERR_UNSUPPORTED = 5  /* a valid request this build does not implement  */
+} tgs_status;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward). */
+typedef struct tgs_camera {
+    int32_t width, height;   /* full-resolution image size in pixels (> 0)     */
+    float fx, fy, cx, cy;    /* focal lengths and principal point, full-res px */
+    float world_to_cam[12];  /* row-major 3x4 [R | t]: x_cam = R x_world + t    */
+    float near_z;            /* Gaussians with camera depth <= near_z are culled */
+} tgs_camera;
+
+/* Dilation pattern of Sec. 4.1: stride d >= 1, 0 <= off_x, off_y < d.
+ * d = 1, offsets 0 is the plain full-resolution renderer. */
+typedef struct tgs_dilation {
+    int32_t stride, off_x, off_y;
+} tgs_dilation;
+
+typedef struct tgs_gaussians {
+    int64_t n;               /* number of Gaussians, >= 0                        */
+    int32_t sh_degree;       /* active SH degree, 0..3                            */
+    int32_t sh_coeffs;       /* coefficients allocated per channel, >= (deg+1)^2  */
+    const float* means;      /* device [3][n]                                     */
+    const float* scales;     /* device [3][n]                                     */
+    const float* quats;      /* device [4][n]                                     */
+    const float* opacities;  /* device [n]                                        */
+    const float* sh;         /* device [sh_coeffs][3][n]                          */
+} tgs_gaussians;
+
+typedef struct tgs_options {
+    int32_t tile;            /* tile edge T in downsampled pixels: 8, 16 or 32.
+                                The paper fixes 16 (Sec. 4.1); T changes which
+                                Gaussians a pixel considers, hence the result.  */
+    int32_t reserved;        /* must be 0                                        */
+    float bg[3];             /* background colour added with the final T         */
+    uint32_t flags;          /* must be 0                                        */
+} tgs_options;
+
+/* Gradients, same layout as the parameters; every array is overwritten. */
+typedef struct tgs_grads {
+    float* means;            /* device [3][n]          */
+    float* scales;           /* device [3][n]          */
+    float* quats;            /* device [4][n]          */
+    float* opacities;        /* device [n]             */
+    float* sh;               /* device [sh_coeffs][3][n]; rows >= (deg+1)^2 are 0 */
+} tgs_grads;
+
+/* Sizes of one view, filled by tgs_query_sizes (host only). */
+typedef struct tgs_sizes {
+    int32_t w_ds, h_ds;      /* downsampled image size                           */
+    int32_t grid_x, grid_y;  /* tile grid of the downsampled image               */
+    int64_t num_tiles;
+    int64_t pixels;          /* w_ds * h_ds                                      */
+    uint64_t pair_capacity;  /* capacity the workspace size below is for        */
+    uint64_t workspace_bytes;
+} tgs_sizes;
+
+/* Device layout of the per-Gaussian record written by the preprocess and read
+ * by the other stages (48 bytes, 16-byte aligned):
+ *   u, v      splat centre in full-resolution pixels
+ *   A, B, C   conic: inverse of the low-passed 2D covariance
+ *   opacity   the Gaussian's opacity
+ *   r, g, b   colour after the clamp at 0
+ *   z         camera-space depth
+ *   radius    ceil(3 sqrt(lambda_max)) in full-resolution pixels, 0 if culled
+ *   flags     bit 0..2: colour channel clamped; bit 3: culled;
+ *             bit 4 / 5: x / y FoV guard active                              */
+typedef struct tgs_record {
+    float u, v, A, B;
+    float C, opacity, r, g;
+    float b, z;
+    int32_t radius;
+    uint32_t flags;
+} tgs_record;
+
+/* Per-view state inside a caller-allocated workspace.  The caller sets the
+ * three input fields; tgs_forward / tgs_bin_sort fill the rest.  The byte
+ * offsets locate results inside the workspace for inspection. */
+typedef struct tgs_state {
+    void* workspace;             /* in: device, >= tgs_sizes.workspace_bytes, 256-aligned */
+    uint64_t workspace_bytes;    /* in */
+    uint64_t pair_capacity;      /* in: the capacity passed to tgs_query_sizes           */
+    uint64_t pair_count;         /* out: tile-Gaussian pairs of the last bin/sort        */
+    uint32_t key_bits;           /* out: tile-id bits sorted                             */
+    uint32_t reserved;
+    uint64_t off_records;        /* out: tgs_record[n]                                    */
+    uint64_t off_tiles_touched;  /* out: uint32[n], ds tiles each Gaussian overlaps       */
+    uint64_t off_depth_order;    /* out: uint32[n], Gaussian ids sorted by depth key      */
+    uint64_t off_pair_tiles;     /* out: uint32[pair_count], sorted tile ids              */
+    uint64_t off_pair_vals;      /* out: uint32[pair_count], Gaussian id of each pair     */
+    uint64_t off_ranges;         /* out: uint32[num_tiles][2], [start, end) per tile      */
+    uint64_t off_grad2d;         /* out: float[n][9], dL/d(u,v,A,B,C,o,r,g,b) (backward)  */
+} tgs_state;
+
+typedef struct tgs_context tgs_context;
+
+const char* tgs_status_str(tgs_status s);
+/* Thread-local text of the last failure in this thread ("" if none). */
+const char* tgs_last_error(void);
+/* Library version string. */
+const char* tgs_version(void);
+
+/* Create a context bound to HIP device `device`.  Returns TGS_ERR_NO_DEVICE
+ * when the device does not exist.  The context owns a small pinned host
+ * buffer; release with tgs_destroy. */
+tgs_status tgs_create(int device, tgs_context** out);
+void tgs_destroy(tgs_context* ctx);
+
+/* Host only, no device needed.  Sizes of one view: downsampled image, tile
+ * grid (Sec. 4.1: T x T tiles of the downsampled image) and the workspace
+ * bytes needed for n Gaussians and up to pair_capacity tile-Gaussian pairs. */
+tgs_status tgs_query_sizes(int64_t n, const tgs_camera* cam, const tgs_dilation* dil,
+                           const tgs_options* opt, uint64_t pair_capacity, tgs_sizes* out);
+
+/* Stage (a), Sec. 3 and Sec. 4.1: per Gaussian, view transform, near cull,
+ * Sigma = R S S^T R^T, EWA projection with the full-resolution focal length
+ * plus a 0.3 px^2 low-pass, conic, radius, SH colour, and the number of
+ * tiles of the DOWNSAMPLED grid its box [u_ds +- r/d] x [v_ds +- r/d]
+ * overlaps, with u_ds = (u - (d-1)/2) / d (Eq. 3-4 read as the inverse of
+ * Eq. 5).  Writes records and tiles_touched into the workspace. */
+tgs_status tgs_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                              const tgs_dilation* dil, const tgs_options* opt, tgs_state* st,
+                              void* stream);
+
+/* Stage (b), Sec. 4.1 and Sec. 3 ("sorted by depth ... tile-based
+ * rasterizer"): one pair per (Gaussian, overlapped tile), sorted by the key
+ * (tile id, float32 depth bits), equal keys in ascending Gaussian index, and
+ * the [start, end) range of every tile.  Requires tgs_preprocess_fwd on the
+ * same state.  Reads the pair count back to the host (one stream
+ * synchronisation); if it exceeds pair_capacity nothing more is enqueued,
+ * st->pair_count holds the required count and TGS_ERR_CAPACITY is returned. */
+tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                        const tgs_dilation* dil, const tgs_options* opt, tgs_state* st,
+                        void* stream);
+
+/* Stage (c), Sec. 3 Eq. 2 on the dilated pixels of Sec. 4.1 (Eq. 5, Fig. 2):
+ * each downsampled pixel walks its tile's list front to back with
+ * alpha = min(0.99, o exp(-1/2 d^T Sigma^-1 d)), skips alpha < 1/255, stops
+ * before the entry that would take T below 1e-4, and outputs C + T bg.
+ * image: device [3][H_ds][W_ds].  Optional (may be NULL) device outputs per
+ * downsampled pixel: t_final float, last_contrib uint32 (1-based index of the
+ * last blended list entry), n_eval uint32 (entries examined, stop included). */
+tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
+                          const tgs_options* opt, const tgs_state* st, int64_t n, float* image,
+                          float* t_final, uint32_t* last_contrib, uint32_t* n_eval, void* stream);
+
+/* Stages (a)-(c) in order.  Same arguments and outputs as the three calls. */
+tgs_status tgs_forward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                       const tgs_dilation* dil, const tgs_options* opt, tgs_state* st,
+                       float* image, void* stream);
+
+/* L1 photometric loss of Sec. 4.1 / Fig. 2: each rendered pixel against the
+ * full-resolution target pixel it was rendered at.  L = mean over rendered
+ * pixels and channels of |image - target|; dL_dimage = sign(.) / (3 W_ds H_ds)
+ * with sign(0) = 0.  target: device [3][H][W]; dL_dimage: device
+ * [3][H_ds][W_ds]; loss: device double[1], overwritten (may be NULL). */
+tgs_status tgs_l1_grad(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
+                       const float* image, const float* target, float* dL_dimage, double* loss,
+                       void* stream);
+
+/* Stage (d1): the derivative of the forward (Sec. 3 Eq. 2; the paper's
+ * backward follows prior work) with respect to every splat's
+ * (u, v, A, B, C, o, r, g, b), summed over the rendered pixels, into the
+ * workspace's float[n][9] grad2d.  image is the tgs_raster_fwd output of the
+ * same state; the walk is replayed front to back, so no per-pixel state is
+ * kept between forward and backward. */
+tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
+                          const tgs_options* opt, const tgs_state* st, int64_t n,
+                          const float* image, const float* dL_dimage, void* stream);
+
+/* Stage (d2): chain rule from grad2d to the parameters, and the
+ * densification statistics of Sec. 4.3: pos_stat = ||(dL/du W/2, dL/dv H/2)||
+ * (view-space positional gradient in NDC units of the full-resolution image),
+ * col_stat = ||dL/d(r,g,b)|| (appearance gradient), visible = 1 where the
+ * Gaussian overlapped at least one tile.  pos_stat, col_stat: device float[n];
+ * visible: device uint8[n]; each may be NULL. */
+tgs_status tgs_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                              const tgs_dilation* dil, const tgs_options* opt, const tgs_state* st,
+                              const tgs_grads* out, float* pos_stat, float* col_stat,
+                              uint8_t* visible, void* stream);
+
+/* Stages (d1) and (d2) in order. */
+tgs_status tgs_backward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                        const tgs_dilation* dil, const tgs_options* opt, const tgs_state* st,
+                        const float* image, const float* dL_dimage, const tgs_grads* out,
+                        float* pos_stat, float* col_stat, uint8_t* visible, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TGS_H */

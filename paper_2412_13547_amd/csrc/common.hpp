@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP kernels and the C ABI of libtgs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "tgs.h"
+
+namespace tgs {
+
+constexpr float kNearDefault = 0.2f;
+constexpr float kLowPass = 0.3f;       // px^2 added to the 2D covariance diagonal
+constexpr float kFovGuard = 1.3f;      // x/z, y/z clamp, in units of W/(2 fx), H/(2 fy)
+constexpr int kRecordBytes = 48;       // sizeof(tgs_record)
+constexpr int kGrad2d = 9;             // dL/d(u, v, A, B, C, o, r, g, b)
+
+// radix sort / scan tiling
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // keys per block and pass
+constexpr int kRadixBits = 8;
+constexpr int kRadixBuckets = 1 << kRadixBits;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+enum RecordFlags : uint32_t {
+    kClampR = 1u, kClampG = 2u, kClampB = 4u, kCulled = 8u, kFovX = 16u, kFovY = 32u
+};
+
+struct Grid {
+    int width, height;        // full resolution
+    int stride, off_x, off_y;
+    int tile;
+    int w_ds, h_ds, gx, gy;
+    int64_t num_tiles() const { return int64_t(gx) * gy; }
+};
+
+Grid make_grid(const tgs_camera& cam, const tgs_dilation& dil, int tile);
+
+// Byte offsets of the sub-buffers of one view's workspace.
+struct Layout {
+    uint64_t records, tiles_touched;
+    uint64_t depth_key[2], depth_val[2];
+    uint64_t offsets;          // uint64[n + 1]
+    uint64_t pair_tile[2], pair_val[2];
+    uint64_t ranges;           // uint32[num_tiles][2]
+    uint64_t grad2d;           // float[n][9]
+    uint64_t sort_counts;      // uint32, radix digit counts
+    uint64_t scan_partials;    // uint64, scan block sums
+    uint64_t misc;             // small counters
+    uint64_t total;
+};
+
+Layout make_layout(int64_t n, uint64_t pair_capacity, int64_t num_tiles);
+
+// Device kernel launchers (stream-ordered, no synchronisation).
+struct CamDev {
+    float R[9], t[3];
+    float campos[3];          // -R^T t, camera centre in world space
+    float fx, fy, cx, cy;
+    float near_z;
+    int width, height;
+};
+CamDev make_cam(const tgs_camera& c);
+
+hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const CamDev& cam, const Grid& grid,
+                                 uint8_t* ws, const Layout& L, hipStream_t s);
+hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const CamDev& cam, const uint8_t* ws,
+                                 const Layout& L, const tgs_grads& out, float* pos_stat,
+                                 float* col_stat, uint8_t* visible, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs on bits [0, bits).
+// Returns the index (0 or 1) of the buffer pair holding the result.
+int radix_sort_passes(int bits);
+hipError_t radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint64_t count, int bits,
+                      uint32_t* counts, uint64_t* partials, int* result, hipStream_t s);
+uint64_t radix_counts_elems(uint64_t count);
+
+// Exclusive scan of uint32 values into uint64 (out has count + 1 entries;
+// out[count] is the total).  If gather != nullptr the i-th input is
+// in[gather[i]].
+hipError_t exclusive_scan_u64(const uint32_t* in, const uint32_t* gather, uint64_t* out,
+                              uint64_t count, uint64_t* partials, hipStream_t s);
+uint64_t scan_partials_elems(uint64_t count);
+
+hipError_t launch_emit_pairs(const uint8_t* ws, const Layout& L, const uint32_t* order,
+                             int64_t n, const Grid& grid, uint32_t* tiles, uint32_t* vals,
+                             hipStream_t s);
+hipError_t launch_ranges(const uint32_t* tiles, uint64_t count, uint32_t* ranges,
+                         int64_t num_tiles, hipStream_t s);
+
+hipError_t launch_raster_fwd(const Grid& grid, const float bg[3], const uint8_t* ws,
+                             const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
+                             float* image,
+                             float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
+                             hipStream_t s);
+hipError_t launch_raster_bwd(const Grid& grid, const float bg[3], const uint8_t* ws,
+                             const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
+                             const float* image,
+                             const float* dL_dimage, float* grad2d, hipStream_t s);
+hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,
+                          float* dL_dimage, double* loss, hipStream_t s);
+
+hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Downsampled tile rectangle [xlo, xhi) x [ylo, yhi) of a splat centred at
+// full-resolution (u, v) with integer radius r (Sec. 4.1 Eq. 3-4, read as the
+// inverse of Eq. 5): u_ds = (u - (d-1)/2) / d, r_ds = r / d, and the tiles
+// holding a downsampled pixel in [u_ds - r_ds, u_ds + r_ds].  Evaluated in
+// IEEE double in a fixed order so every stage gets the same integers.
+struct Rect { int xlo, xhi, ylo, yhi; };
+__host__ __device__ inline Rect tile_rect(float u, float v, int radius, const Grid& g) {
+    const double d = double(g.stride), T = double(g.tile);
+    const double half = 0.5 * double(g.stride - 1);
+    const double ud = (double(u) - half) / d;
+    const double vd = (double(v) - half) / d;
+    const double rd = double(radius) / d;
+    const double gx = double(g.gx), gy = double(g.gy);
+    Rect r;
+    r.xlo = int(fmin(fmax(floor((ud - rd) / T), 0.0), gx));
+    r.xhi = int(fmin(fmax(floor((ud + rd) / T) + 1.0, 0.0), gx));
+    r.ylo = int(fmin(fmax(floor((vd - rd) / T), 0.0), gy));
+    r.yhi = int(fmin(fmax(floor((vd + rd) / T) + 1.0, 0.0), gy));
+    return r;
+}
+
+}  // namespace tgs

@@ -1,0 +1,437 @@
+// Per-Gaussian preprocess, forward and backward (stage (a) and (d2)).
+//
+// Forward (Sec. 3 Eq. 1, Sec. 4.1): view transform, near cull,
+// Sigma = R S S^T R^T, EWA projection with the full-resolution focal length
+// plus a 0.3 px^2 low-pass, conic, 3-sigma radius, SH colour, and the tiles
+// of the downsampled grid the splat's box overlaps (Eq. 3-4).
+// Backward: the chain rule from dL/d(u, v, A, B, C, o, r, g, b) to the
+// parameters, and the densification statistics of Sec. 4.3.
+//
+// One thread per Gaussian; parameters are read structure-of-arrays so that
+// every load instruction of a wavefront touches 64 consecutive floats.
+#include "common.hpp"
+
+namespace tgs {
+namespace {
+
+// Real SH basis (Condon-Shortley phase, m = -l..l), Cartesian form on the
+// unit sphere.  Constants are the closed forms in the comments.
+constexpr float kC0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+constexpr float kC1 = 0.4886025119029199f;    // sqrt(3/(4 pi))
+constexpr float kC2a = 1.0925484305920792f;   // sqrt(15/(4 pi))
+constexpr float kC2b = 0.31539156525252005f;  // sqrt(5/(16 pi))
+constexpr float kC2c = 0.5462742152960396f;   // sqrt(15/(16 pi))
+constexpr float kC3a = 0.5900435899266435f;   // sqrt(35/(32 pi))
+constexpr float kC3b = 2.890611442640554f;    // sqrt(105/(4 pi))
+constexpr float kC3c = 0.4570457994644658f;   // sqrt(21/(32 pi))
+constexpr float kC3d = 0.3731763325901154f;   // sqrt(7/(16 pi))
+constexpr float kC3e = 1.445305721320277f;    // sqrt(105/(16 pi))
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+    Y[0] = kC0;
+    if constexpr (DEG >= 1) {
+        Y[1] = -kC1 * y;
+        Y[2] = kC1 * z;
+        Y[3] = -kC1 * x;
+    }
+    if constexpr (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kC2a * (x * y);
+        Y[5] = -kC2a * (y * z);
+        Y[6] = kC2b * (3.0f * zz - 1.0f);
+        Y[7] = -kC2a * (x * z);
+        Y[8] = kC2c * (xx - yy);
+        if constexpr (DEG >= 3) {
+            Y[9] = -kC3a * (y * (3.0f * xx - yy));
+            Y[10] = kC3b * (x * y * z);
+            Y[11] = -kC3c * (y * (5.0f * zz - 1.0f));
+            Y[12] = kC3d * (z * (5.0f * zz - 3.0f));
+            Y[13] = -kC3c * (x * (5.0f * zz - 1.0f));
+            Y[14] = kC3e * (z * (xx - yy));
+            Y[15] = -kC3a * (x * (xx - 3.0f * yy));
+        }
+    }
+}
+
+// sum_k w[k] * grad Y_k(x, y, z)  (gradient in R^3 of the polynomial forms)
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const float* w,
+                                              float& gx, float& gy, float& gz) {
+    gx = gy = gz = 0.0f;
+    if constexpr (DEG >= 1) {
+        gy += -kC1 * w[1];
+        gz += kC1 * w[2];
+        gx += -kC1 * w[3];
+    }
+    if constexpr (DEG >= 2) {
+        gx += kC2a * y * w[4];
+        gy += kC2a * x * w[4];
+        gy += -kC2a * z * w[5];
+        gz += -kC2a * y * w[5];
+        gz += kC2b * 6.0f * z * w[6];
+        gx += -kC2a * z * w[7];
+        gz += -kC2a * x * w[7];
+        gx += kC2c * 2.0f * x * w[8];
+        gy += -kC2c * 2.0f * y * w[8];
+        if constexpr (DEG >= 3) {
+            const float xx = x * x, yy = y * y, zz = z * z;
+            gx += -kC3a * 6.0f * x * y * w[9];
+            gy += -kC3a * 3.0f * (xx - yy) * w[9];
+            gx += kC3b * y * z * w[10];
+            gy += kC3b * x * z * w[10];
+            gz += kC3b * x * y * w[10];
+            gy += -kC3c * (5.0f * zz - 1.0f) * w[11];
+            gz += -kC3c * 10.0f * y * z * w[11];
+            gz += kC3d * (15.0f * zz - 3.0f) * w[12];
+            gx += -kC3c * (5.0f * zz - 1.0f) * w[13];
+            gz += -kC3c * 10.0f * x * z * w[13];
+            gx += kC3e * 2.0f * x * z * w[14];
+            gy += -kC3e * 2.0f * y * z * w[14];
+            gz += kC3e * (xx - yy) * w[14];
+            gx += -kC3a * 3.0f * (xx - yy) * w[15];
+            gy += kC3a * 6.0f * x * y * w[15];
+        }
+    }
+}
+
+// Rotation matrix (row-major) of the normalised quaternion (w, x, y, z).
+__device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R) {
+    R[0] = 1.0f - 2.0f * (y * y + z * z);
+    R[1] = 2.0f * (x * y - w * z);
+    R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z);
+    R[4] = 1.0f - 2.0f * (x * x + z * z);
+    R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y);
+    R[7] = 2.0f * (y * z + w * x);
+    R[8] = 1.0f - 2.0f * (x * x + y * y);
+}
+
+struct Proj {
+    float tx, ty, tz;
+    float u, v;
+    float cxr, cyr;      // FoV-guarded x/z, y/z
+    bool fovx, fovy;
+    float Tm[6];         // J R, 2x3 row-major
+    float Sig[6];        // 3D covariance (xx, xy, xz, yy, yz, zz)
+    float M[9];          // R_q diag(s)
+    float Rq[9];
+    float qn[4];         // normalised quaternion
+    float qlen;
+    float a, b, c;       // low-passed 2D covariance
+};
+
+// Everything of the forward up to the conic that the backward re-derives.
+__device__ __forceinline__ bool project(const CamDev& cam, const float m[3], const float s[3],
+                                        const float q[4], Proj& p) {
+    p.tx = cam.R[0] * m[0] + cam.R[1] * m[1] + cam.R[2] * m[2] + cam.t[0];
+    p.ty = cam.R[3] * m[0] + cam.R[4] * m[1] + cam.R[5] * m[2] + cam.t[1];
+    p.tz = cam.R[6] * m[0] + cam.R[7] * m[1] + cam.R[8] * m[2] + cam.t[2];
+    if (!(p.tz > cam.near_z)) return false;
+    p.u = cam.fx * p.tx / p.tz + cam.cx;
+    p.v = cam.fy * p.ty / p.tz + cam.cy;
+    const float limx = kFovGuard * float(cam.width) / (2.0f * cam.fx);
+    const float limy = kFovGuard * float(cam.height) / (2.0f * cam.fy);
+    const float rx = p.tx / p.tz, ry = p.ty / p.tz;
+    p.fovx = rx < -limx || rx > limx;
+    p.fovy = ry < -limy || ry > limy;
+    p.cxr = fminf(fmaxf(rx, -limx), limx);
+    p.cyr = fminf(fmaxf(ry, -limy), limy);
+    const float j00 = cam.fx / p.tz, j02 = -cam.fx * p.cxr / p.tz;
+    const float j11 = cam.fy / p.tz, j12 = -cam.fy * p.cyr / p.tz;
+    for (int k = 0; k < 3; ++k) {
+        p.Tm[k] = j00 * cam.R[k] + j02 * cam.R[6 + k];
+        p.Tm[3 + k] = j11 * cam.R[3 + k] + j12 * cam.R[6 + k];
+    }
+    p.qlen = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!(p.qlen > 0.0f)) return false;
+    for (int k = 0; k < 4; ++k) p.qn[k] = q[k] / p.qlen;
+    quat_to_rot(p.qn[0], p.qn[1], p.qn[2], p.qn[3], p.Rq);
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) p.M[r * 3 + k] = p.Rq[r * 3 + k] * s[k];
+    // Sigma = M M^T
+    p.Sig[0] = p.M[0] * p.M[0] + p.M[1] * p.M[1] + p.M[2] * p.M[2];
+    p.Sig[1] = p.M[0] * p.M[3] + p.M[1] * p.M[4] + p.M[2] * p.M[5];
+    p.Sig[2] = p.M[0] * p.M[6] + p.M[1] * p.M[7] + p.M[2] * p.M[8];
+    p.Sig[3] = p.M[3] * p.M[3] + p.M[4] * p.M[4] + p.M[5] * p.M[5];
+    p.Sig[4] = p.M[3] * p.M[6] + p.M[4] * p.M[7] + p.M[5] * p.M[8];
+    p.Sig[5] = p.M[6] * p.M[6] + p.M[7] * p.M[7] + p.M[8] * p.M[8];
+    // cov2 = Tm Sigma Tm^T
+    float TS[6];
+    for (int r = 0; r < 2; ++r) {
+        const float* t = p.Tm + 3 * r;
+        TS[3 * r + 0] = t[0] * p.Sig[0] + t[1] * p.Sig[1] + t[2] * p.Sig[2];
+        TS[3 * r + 1] = t[0] * p.Sig[1] + t[1] * p.Sig[3] + t[2] * p.Sig[4];
+        TS[3 * r + 2] = t[0] * p.Sig[2] + t[1] * p.Sig[4] + t[2] * p.Sig[5];
+    }
+    p.a = TS[0] * p.Tm[0] + TS[1] * p.Tm[1] + TS[2] * p.Tm[2] + kLowPass;
+    p.b = TS[0] * p.Tm[3] + TS[1] * p.Tm[4] + TS[2] * p.Tm[5];
+    p.c = TS[3] * p.Tm[3] + TS[4] * p.Tm[4] + TS[5] * p.Tm[5] + kLowPass;
+    return true;
+}
+
+__device__ __forceinline__ bool finite_all(const float* x, int k) {
+    bool ok = true;
+    for (int i = 0; i < k; ++i) ok = ok && isfinite(x[i]);
+    return ok;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, CamDev cam, Grid grid,
+                                                             tgs_record* __restrict__ rec,
+                                                             uint32_t* __restrict__ touched,
+                                                             uint32_t* __restrict__ depth_key,
+                                                             uint32_t* __restrict__ depth_val) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t n = g.n;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float m[3], s[3], q[4], sh[K * 3];
+    for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
+    for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
+    for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
+    const float op = g.opacities[i];
+    for (int k = 0; k < K * 3; ++k) sh[k] = g.sh[k * n + i];
+
+    Proj p;
+    bool ok = finite_all(m, 3) && finite_all(s, 3) && finite_all(q, 4) && isfinite(op) &&
+              finite_all(sh, K * 3);
+    ok = ok && project(cam, m, s, q, p);
+    float det = 0.0f;
+    if (ok) {
+        det = p.a * p.c - p.b * p.b;
+        ok = det > 0.0f;
+    }
+    int radius = 0;
+    if (ok) {
+        const float hd = 0.5f * (p.a - p.c);
+        const float lam = 0.5f * (p.a + p.c) + sqrtf(hd * hd + p.b * p.b);
+        radius = int(ceilf(3.0f * sqrtf(lam)));
+        ok = radius > 0;
+    }
+    tgs_record r;
+    uint32_t nt = 0;
+    if (!ok) {
+        r = tgs_record{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, kCulled};
+    } else {
+        const float A = p.c / det, B = -p.b / det, C = p.a / det;
+        // colour
+        float dx = m[0] - cam.campos[0], dy = m[1] - cam.campos[1], dz = m[2] - cam.campos[2];
+        const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+        dx /= len; dy /= len; dz /= len;
+        float Y[16];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        float rgb[3];
+        uint32_t flags = (p.fovx ? kFovX : 0u) | (p.fovy ? kFovY : 0u);
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.0f;
+            for (int k = 0; k < K; ++k) acc += sh[k * 3 + c] * Y[k];
+            acc += 0.5f;
+            if (acc < 0.0f) flags |= (1u << c);
+            rgb[c] = fmaxf(acc, 0.0f);
+        }
+        r = tgs_record{p.u, p.v, A, B, C, op, rgb[0], rgb[1], rgb[2], p.tz, radius, flags};
+        const Rect rc = tile_rect(p.u, p.v, radius, grid);
+        nt = uint32_t(rc.xhi - rc.xlo) * uint32_t(rc.yhi - rc.ylo);
+    }
+    float4* dst = reinterpret_cast<float4*>(rec + i);
+    dst[0] = make_float4(r.u, r.v, r.A, r.B);
+    dst[1] = make_float4(r.C, r.opacity, r.r, r.g);
+    dst[2] = make_float4(r.b, r.z, __int_as_float(r.radius), __uint_as_float(r.flags));
+    touched[i] = nt;
+    depth_key[i] = nt > 0 ? __float_as_uint(r.z) : 0xFFFFFFFFu;
+    depth_val[i] = uint32_t(i);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) preprocess_bwd_kernel(
+    tgs_gaussians g, CamDev cam, const tgs_record* __restrict__ rec,
+    const uint32_t* __restrict__ touched, const float* __restrict__ g2d, tgs_grads out,
+    float* __restrict__ pos_stat, float* __restrict__ col_stat, uint8_t* __restrict__ visible) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t n = g.n;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int kc = g.sh_coeffs;
+    const float4 r2 = reinterpret_cast<const float4*>(rec + i)[2];
+    const uint32_t flags = __float_as_uint(r2.w);
+    const bool vis = touched[i] > 0 && !(flags & kCulled);
+    if (!vis) {
+        for (int k = 0; k < 3; ++k) out.means[k * n + i] = 0.0f;
+        for (int k = 0; k < 3; ++k) out.scales[k * n + i] = 0.0f;
+        for (int k = 0; k < 4; ++k) out.quats[k * n + i] = 0.0f;
+        out.opacities[i] = 0.0f;
+        for (int k = 0; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
+        if (pos_stat) pos_stat[i] = 0.0f;
+        if (col_stat) col_stat[i] = 0.0f;
+        if (visible) visible[i] = 0;
+        return;
+    }
+    float gr[kGrad2d];
+    for (int k = 0; k < kGrad2d; ++k) gr[k] = g2d[i * kGrad2d + k];
+    const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
+
+    float m[3], s[3], q[4];
+    for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
+    for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
+    for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
+    Proj p;
+    project(cam, m, s, q, p);
+    float dm[3] = {0.0f, 0.0f, 0.0f};
+
+    // ---- colour: rgb = max(sum_k sh_k Y_k(dir) + 0.5, 0), dir = (m - campos)/|.|
+    {
+        float dx = m[0] - cam.campos[0], dy = m[1] - cam.campos[1], dz = m[2] - cam.campos[2];
+        const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+        dx /= len; dy /= len; dz /= len;
+        float Y[16];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        float graw[3];
+        for (int c = 0; c < 3; ++c) graw[c] = (flags & (1u << c)) ? 0.0f : gr[6 + c];
+        float w[16];
+        for (int k = 0; k < K; ++k) {
+            float acc = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                const float coef = g.sh[(k * 3 + c) * n + i];
+                out.sh[(k * 3 + c) * n + i] = Y[k] * graw[c];
+                acc += coef * graw[c];
+            }
+            w[k] = acc;
+        }
+        for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
+        float gdx, gdy, gdz;
+        sh_basis_grad<DEG>(dx, dy, dz, w, gdx, gdy, gdz);
+        // through the normalisation of dir
+        const float dot = gdx * dx + gdy * dy + gdz * dz;
+        dm[0] += (gdx - dx * dot) / len;
+        dm[1] += (gdy - dy * dot) / len;
+        dm[2] += (gdz - dz * dot) / len;
+    }
+
+    // ---- conic (A, B, C) = (c, -b, a) / det  ->  (a, b, c)
+    const float a = p.a, b = p.b, c = p.c;
+    const float det = a * c - b * b;
+    const float id2 = 1.0f / (det * det);
+    const float da = (-c * c * gA + b * c * gB - b * b * gC) * id2;
+    const float db = (2.0f * b * c * gA - (a * c + b * b) * gB + 2.0f * a * b * gC) * id2;
+    const float dc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+    // cov2 = Tm Sigma Tm^T with dcov2 = [[da, db/2], [db/2, dc]]
+    const float D[4] = {da, 0.5f * db, 0.5f * db, dc};
+    // dSigma = Tm^T D Tm (3x3 symmetric, full storage)
+    float DT[6];   // D Tm, 2x3
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) DT[3 * r + k] = D[2 * r] * p.Tm[k] + D[2 * r + 1] * p.Tm[3 + k];
+    float dS[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) dS[3 * r + k] = p.Tm[r] * DT[k] + p.Tm[3 + r] * DT[3 + k];
+    // dTm = 2 D Tm Sigma
+    const float S9[9] = {p.Sig[0], p.Sig[1], p.Sig[2], p.Sig[1], p.Sig[3],
+                         p.Sig[4], p.Sig[2], p.Sig[4], p.Sig[5]};
+    float dTm[6];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k)
+            dTm[3 * r + k] = 2.0f * (DT[3 * r] * S9[k] + DT[3 * r + 1] * S9[3 + k] +
+                                     DT[3 * r + 2] * S9[6 + k]);
+    // Tm = J R  ->  dJ = dTm R^T (only the non-zero entries of J matter)
+    const float dJ00 = dTm[0] * cam.R[0] + dTm[1] * cam.R[1] + dTm[2] * cam.R[2];
+    const float dJ02 = dTm[0] * cam.R[6] + dTm[1] * cam.R[7] + dTm[2] * cam.R[8];
+    const float dJ11 = dTm[3] * cam.R[3] + dTm[4] * cam.R[4] + dTm[5] * cam.R[5];
+    const float dJ12 = dTm[3] * cam.R[6] + dTm[4] * cam.R[7] + dTm[5] * cam.R[8];
+    const float tz = p.tz, iz = 1.0f / tz, iz2 = iz * iz;
+    float dtx = 0.0f, dty = 0.0f, dtz = 0.0f;
+    // J00 = fx/tz, J11 = fy/tz
+    dtz += -cam.fx * iz2 * dJ00 - cam.fy * iz2 * dJ11;
+    // J02 = -fx cxr / tz, cxr = clamp(tx / tz)
+    dtz += cam.fx * p.cxr * iz2 * dJ02;
+    if (!p.fovx) {
+        const float dcx = -cam.fx * iz * dJ02;
+        dtx += dcx * iz;
+        dtz += -dcx * p.tx * iz2;
+    }
+    dtz += cam.fy * p.cyr * iz2 * dJ12;
+    if (!p.fovy) {
+        const float dcy = -cam.fy * iz * dJ12;
+        dty += dcy * iz;
+        dtz += -dcy * p.ty * iz2;
+    }
+    // u = fx tx/tz + cx, v = fy ty/tz + cy
+    dtx += gu * cam.fx * iz;
+    dty += gv * cam.fy * iz;
+    dtz += -(gu * cam.fx * p.tx + gv * cam.fy * p.ty) * iz2;
+    // t = R m + t0
+    dm[0] += cam.R[0] * dtx + cam.R[3] * dty + cam.R[6] * dtz;
+    dm[1] += cam.R[1] * dtx + cam.R[4] * dty + cam.R[7] * dtz;
+    dm[2] += cam.R[2] * dtx + cam.R[5] * dty + cam.R[8] * dtz;
+
+    // ---- Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M
+    float dM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k)
+            dM[3 * r + k] = 2.0f * (dS[3 * r] * p.M[k] + dS[3 * r + 1] * p.M[3 + k] +
+                                    dS[3 * r + 2] * p.M[6 + k]);
+    float ds[3], dR[9];
+    for (int k = 0; k < 3; ++k) {
+        ds[k] = dM[k] * p.Rq[k] + dM[3 + k] * p.Rq[3 + k] + dM[6 + k] * p.Rq[6 + k];
+        for (int r = 0; r < 3; ++r) dR[3 * r + k] = dM[3 * r + k] * s[k];
+    }
+    const float w = p.qn[0], x = p.qn[1], y = p.qn[2], z = p.qn[3];
+    float dq[4];
+    dq[0] = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0f * x * dR[4] - w * dR[5] +
+                    z * dR[6] + w * dR[7] - 2.0f * x * dR[8]);
+    dq[2] = 2.0f * (-2.0f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] -
+                    w * dR[6] + z * dR[7] - 2.0f * y * dR[8]);
+    dq[3] = 2.0f * (-2.0f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0f * z * dR[4] +
+                    y * dR[5] + x * dR[6] + y * dR[7]);
+    // through q / |q|
+    const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    for (int k = 0; k < 4; ++k) out.quats[k * n + i] = (dq[k] - p.qn[k] * qd) / p.qlen;
+    for (int k = 0; k < 3; ++k) out.scales[k * n + i] = ds[k];
+    for (int k = 0; k < 3; ++k) out.means[k * n + i] = dm[k];
+    out.opacities[i] = gr[5];
+    if (pos_stat) {
+        const float px = gu * (0.5f * float(cam.width)), py = gv * (0.5f * float(cam.height));
+        pos_stat[i] = sqrtf(px * px + py * py);
+    }
+    if (col_stat) col_stat[i] = sqrtf(gr[6] * gr[6] + gr[7] * gr[7] + gr[8] * gr[8]);
+    if (visible) visible[i] = 1;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const CamDev& cam, const Grid& grid,
+                                 uint8_t* ws, const Layout& L, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
+    auto* rec = reinterpret_cast<tgs_record*>(ws + L.records);
+    auto* touched = reinterpret_cast<uint32_t*>(ws + L.tiles_touched);
+    auto* dk = reinterpret_cast<uint32_t*>(ws + L.depth_key[0]);
+    auto* dv = reinterpret_cast<uint32_t*>(ws + L.depth_val[0]);
+    switch (g.sh_degree) {
+        case 0: preprocess_fwd_kernel<0><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
+        case 1: preprocess_fwd_kernel<1><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
+        case 2: preprocess_fwd_kernel<2><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
+        default: preprocess_fwd_kernel<3><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const CamDev& cam, const uint8_t* ws,
+                                 const Layout& L, const tgs_grads& out, float* pos_stat,
+                                 float* col_stat, uint8_t* visible, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
+    auto* rec = reinterpret_cast<const tgs_record*>(ws + L.records);
+    auto* touched = reinterpret_cast<const uint32_t*>(ws + L.tiles_touched);
+    auto* g2d = reinterpret_cast<const float*>(ws + L.grad2d);
+    switch (g.sh_degree) {
+        case 0: preprocess_bwd_kernel<0><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
+        case 1: preprocess_bwd_kernel<1><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
+        case 2: preprocess_bwd_kernel<2><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
+        default: preprocess_bwd_kernel<3><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tgs

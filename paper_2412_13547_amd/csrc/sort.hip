@@ -1,0 +1,239 @@
+// Device-wide primitives: exclusive scan and stable LSD radix sort of
+// (uint32 key, uint32 value) pairs, written for wave64.
+//
+// Radix sort, per 8-bit digit pass:
+//   1. digit_counts : each block counts the digits of its 4096 keys in LDS
+//                     (one private histogram per wavefront, then summed) and
+//                     stores them digit-major, counts[digit][block];
+//   2. exclusive scan of counts -> first output slot of (digit, block);
+//   3. scatter      : the block walks its keys in input order, 256 at a time;
+//                     equal digits inside a wavefront are ranked with eight
+//                     ballots, wavefronts are ordered through LDS, so equal
+//                     keys keep their input order (stability).
+#include "common.hpp"
+
+namespace tgs {
+namespace {
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (uint64_t(1) << lane_id()) - 1;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+digit_counts(const uint32_t* __restrict__ keys, uint64_t count, int shift,
+             uint32_t* __restrict__ counts, uint32_t nblocks) {
+    __shared__ uint32_t hist[kSortThreads / 64][kRadixBuckets];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int w = 0; w < kSortThreads / 64; ++w) hist[w][tid] = 0;
+    __syncthreads();
+    const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+#pragma unroll 4
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
+        if (idx < count) atomicAdd(&hist[wave][(keys[idx] >> shift) & (kRadixBuckets - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t s = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w) s += hist[w][tid];
+    counts[uint64_t(tid) * nblocks + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+              uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, uint64_t count,
+              int shift, const uint32_t* __restrict__ offsets, uint32_t nblocks) {
+    constexpr int W = kSortThreads / 64;
+    __shared__ uint32_t run[kRadixBuckets];       // next output slot per digit
+    __shared__ uint32_t wcnt[W][kRadixBuckets];   // this round's count per wave and digit
+    const int tid = threadIdx.x, wave = tid >> 6;
+    run[tid] = offsets[uint64_t(tid) * nblocks + blockIdx.x];
+    for (int w = 0; w < W; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
+        const bool valid = idx < count;
+        const uint32_t k = valid ? keys_in[idx] : 0u;
+        const uint32_t v = valid ? vals_in[idx] : 0u;
+        const uint32_t d = (k >> shift) & (kRadixBuckets - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lanemask_lt());
+        const bool leader = valid && (peers & lanemask_lt()) == 0;
+        if (leader) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            keys_out[pos] = k;
+            vals_out[pos] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < W; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---- exclusive scan: reduce tiles, scan the tile sums, scan each tile -----
+
+template <typename In, typename Out>
+__device__ __forceinline__ Out load_in(const In* in, const uint32_t* gather, uint64_t i) {
+    return Out(gather ? in[gather[i]] : in[i]);
+}
+
+template <typename In, typename Out>
+__global__ void __launch_bounds__(kScanThreads)
+scan_reduce(const In* __restrict__ in, const uint32_t* __restrict__ gather, uint64_t count,
+            Out* __restrict__ partials) {
+    __shared__ Out wsum[kScanThreads / 64];
+    const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
+    Out s = 0;
+    for (int it = 0; it < kScanItems; ++it) {
+        const uint64_t idx = base + uint64_t(it) * kScanThreads + threadIdx.x;
+        if (idx < count) s += load_in<In, Out>(in, gather, idx);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Out t = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) t += wsum[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+template <typename T, int NT>
+__device__ __forceinline__ T block_exclusive_scan(T x, T& total) {
+    __shared__ T wsum[NT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    T before = 0;
+    total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    return before + incl - x;
+}
+
+// Exclusive scan, in place, of the tile sums (single block).
+template <typename T>
+__global__ void __launch_bounds__(1024) scan_partials(T* __restrict__ p, uint64_t count) {
+    T carry = 0;
+    for (uint64_t base = 0; base < count; base += 1024) {
+        const uint64_t idx = base + threadIdx.x;
+        const T x = idx < count ? p[idx] : T(0);
+        T total;
+        const T ex = block_exclusive_scan<T, 1024>(x, total);
+        if (idx < count) p[idx] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) p[count] = carry;
+}
+
+template <typename In, typename Out>
+__global__ void __launch_bounds__(kScanThreads)
+scan_down(const In* in, const uint32_t* __restrict__ gather, uint64_t count,
+          const Out* __restrict__ partials, Out* out, bool write_total) {
+    // blocked arrangement: thread t owns items [t*16, t*16 + 16) of the tile
+    const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
+    Out v[kScanItems];
+    Out s = 0;
+    for (int it = 0; it < kScanItems; ++it) {
+        const uint64_t idx = base + it;
+        v[it] = idx < count ? load_in<In, Out>(in, gather, idx) : Out(0);
+        s += v[it];
+    }
+    Out total;
+    Out run = partials[blockIdx.x] + block_exclusive_scan<Out, kScanThreads>(s, total);
+    for (int it = 0; it < kScanItems; ++it) {
+        const uint64_t idx = base + it;
+        if (idx < count) out[idx] = run;
+        run += v[it];
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        out[count] = partials[gridDim.x];
+}
+
+template <typename In, typename Out>
+hipError_t exclusive_scan(const In* in, const uint32_t* gather, Out* out, uint64_t count,
+                          Out* partials, bool write_total, hipStream_t s) {
+    const uint64_t nb = (count + kScanTile - 1) / kScanTile;
+    if (nb == 0) return hipSuccess;
+    scan_reduce<In, Out><<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, gather, count, partials);
+    scan_partials<Out><<<1, 1024, 0, s>>>(partials, nb);
+    scan_down<In, Out><<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, gather, count, partials,
+                                                                         out, write_total);
+    return hipGetLastError();
+}
+
+__global__ void fill_kernel(uint32_t* p, uint32_t value, uint64_t count) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+}  // namespace
+
+hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    fill_kernel<<<dim3(unsigned((count + 255) / 256)), dim3(256), 0, s>>>(p, value, count);
+    return hipGetLastError();
+}
+
+uint64_t scan_partials_elems(uint64_t count) { return (count + kScanTile - 1) / kScanTile + 1; }
+
+uint64_t radix_counts_elems(uint64_t count) {
+    return uint64_t(kRadixBuckets) * ((count + kSortTile - 1) / kSortTile);
+}
+
+int radix_sort_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
+
+hipError_t exclusive_scan_u64(const uint32_t* in, const uint32_t* gather, uint64_t* out,
+                              uint64_t count, uint64_t* partials, hipStream_t s) {
+    if (count == 0) return fill_u32(reinterpret_cast<uint32_t*>(out), 0u, 2, s);
+    return exclusive_scan<uint32_t, uint64_t>(in, gather, out, count, partials, true, s);
+}
+
+hipError_t radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint64_t count, int bits,
+                      uint32_t* counts, uint64_t* partials, int* result, hipStream_t s) {
+    int cur = 0;
+    const uint64_t nb = (count + kSortTile - 1) / kSortTile;
+    const int passes = radix_sort_passes(bits);
+    for (int p = 0; p < passes && count > 0; ++p) {
+        const int shift = p * kRadixBits;
+        digit_counts<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(keys[cur], count, shift,
+                                                                        counts, uint32_t(nb));
+        // digit counts fit in uint32; their scan is done in uint64 partials
+        hipError_t e = exclusive_scan<uint32_t, uint32_t>(
+            counts, nullptr, counts, nb * kRadixBuckets,
+            reinterpret_cast<uint32_t*>(partials), false, s);
+        if (e != hipSuccess) return e;
+        digit_scatter<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(
+            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], count, shift, counts, uint32_t(nb));
+        cur = 1 - cur;
+    }
+    *result = cur;
+    return hipGetLastError();
+}
+
+}  // namespace tgs

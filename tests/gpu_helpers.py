@@ -1,0 +1,105 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and compare each stage with the CPU checker fed the HIP path's own upstream
+outputs (stage isolation)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+from oracle import backward as obw
+from oracle import binning as obn
+from oracle import preprocess as opre
+from oracle import raster as ors
+from paper_2412_13547_amd import api
+
+F64 = torch.float64
+_CTX = None
+
+
+def ctx() -> api.Context:
+    global _CTX
+    if _CTX is None:
+        _CTX = api.Context(0)
+    return _CTX
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(scene, cam, stride=1, off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0), target=None,
+            dL_dimage=None, backward=True):
+    """Forward (+ loss + backward) on cuda:0; every result copied to the host."""
+    dev = api.DeviceScene.from_scene(scene)
+    view = api.View(ctx(), scene.n, cam, stride, off_x, off_y, tile, bg)
+    shape = view.image_shape
+    image = torch.empty(shape, dtype=torch.float32, device="cuda")
+    tfin = torch.empty(shape[1:], dtype=torch.float32, device="cuda")
+    last = torch.empty(shape[1:], dtype=torch.int32, device="cuda")
+    neval = torch.empty(shape[1:], dtype=torch.int32, device="cuda")
+    view.forward(dev, image, t_final=tfin, last_contrib=last, n_eval=neval)
+    out = dict(view=view, image=image, t_final=tfin, last_contrib=last, n_eval=neval)
+    if backward:
+        if dL_dimage is None:
+            tgt = torch.as_tensor(np.asarray(target, np.float32)).cuda()
+            dL, loss = view.l1_grad(image, tgt)
+            out["loss"] = loss
+        else:
+            dL = torch.as_tensor(np.asarray(dL_dimage, np.float32)).cuda().reshape(shape)
+        n = scene.n
+        pos = torch.empty(n, dtype=torch.float32, device="cuda")
+        col = torch.empty(n, dtype=torch.float32, device="cuda")
+        vis = torch.empty(n, dtype=torch.uint8, device="cuda")
+        grads = view.backward(dev, image, dL, pos_stat=pos, col_stat=col, visible=vis)
+        out.update(dL=dL, grads=grads, pos_stat=pos, col_stat=col, visible=vis)
+    torch.cuda.synchronize()
+    host = {}
+    for k, v in list(out.items()):
+        if isinstance(v, torch.Tensor):
+            host[k] = v.cpu()
+    host["records"] = view.records().cpu()
+    host["tiles_touched"] = view.tiles_touched().cpu()
+    host["pair_tiles"] = view.pair_tiles().cpu()
+    host["pair_vals"] = view.pair_vals().cpu()
+    host["ranges"] = view.ranges().cpu()
+    host["pair_count"] = int(view.state.pair_count)
+    host["grid"] = obn.grid(cam.width, cam.height, stride, off_x, off_y, tile)
+    host["_view"], host["_dev"], host["_image"] = view, dev, image
+    host["bg"] = bg
+    if backward:
+        host["grad2d"] = view.grad2d().cpu()
+        g = out["grads"]
+        host["grads"] = {k: getattr(g, k).cpu() for k in ("means", "scales", "quats", "opacities", "sh")}
+    return host
+
+
+def records_to_oracle(rec32: torch.Tensor) -> dict:
+    """GPU float32 records -> the checker's float64 record dict (exact upcast)."""
+    r = rec32.to(F64)
+    bits = rec32.view(torch.int32)
+    flags = bits[:, 11]
+    return dict(u=r[:, 0], v=r[:, 1], A=r[:, 2], B=r[:, 3], C=r[:, 4], opacity=r[:, 5],
+                rgb=r[:, 6:9].clone(), z=r[:, 9], radius=bits[:, 10].to(torch.int64),
+                culled=(flags & 8) != 0, clamp=torch.stack([(flags >> c) & 1 != 0 for c in range(3)], 1),
+                fovx=(flags & 16) != 0, fovy=(flags & 32) != 0)
+
+
+def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name=""):
+    """Per-tensor norm-relative error and elementwise bound of the
+    gradient contract: ||d|| / ||g|| <= rel and |d| <= rel (|g| + rel max|g|)."""
+    got = got.to(F64).flatten()
+    want = want.to(F64).flatten()
+    d = (got - want).abs()
+    gmax = float(want.abs().max()) if want.numel() else 0.0
+    if gmax == 0.0:
+        assert (float(got.abs().max()) if got.numel() else 0.0) == 0.0, name
+        return 0.0
+    nrel = float(torch.linalg.norm(got - want) / torch.linalg.norm(want))
+    bad = d > rel * (want.abs() + rel * gmax)
+    assert nrel <= rel, f"{name}: norm-relative error {nrel:.3e}"
+    assert not bool(bad.any()), (f"{name}: {int(bad.sum())} elements out of bound, worst "
+                                 f"{float((d / (want.abs() + rel * gmax)).max()):.3e}")
+    return nrel

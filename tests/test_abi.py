@@ -1,0 +1,139 @@
+"""The C ABI on the CPU: the library loads, exports every function declared in
+include/tgs.h, and rejects bad arguments on the host before any HIP call (so
+no GPU is needed here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2412_13547_amd import api, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "tgs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tgs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = api.lib()
+    names = _declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(api.EXPORTED) == set(names)
+
+
+def test_status_strings_and_version():
+    lib = api.lib()
+    assert lib.tgs_status_str(0) == b"ok"
+    assert lib.tgs_status_str(2) == b"pair capacity exceeded"
+    assert lib.tgs_version().startswith(b"tgs")
+
+
+def _cam(w=128, h=96):
+    return api.camera_struct(scenes.identity_camera(w, h, float(w)))
+
+
+def test_query_sizes_host_only():
+    cam = _cam(3840, 2160)
+    s = api.query_sizes(3_000_000, cam, api.dilation_struct(2, 1, 0), api.options_struct(16), 10_000)
+    assert (s.w_ds, s.h_ds, s.grid_x, s.grid_y) == (1920, 1080, 120, 68)
+    assert s.num_tiles == 8160 and s.pixels == 1920 * 1080
+    s2 = api.query_sizes(3_000_000, cam, api.dilation_struct(2, 1, 0), api.options_struct(16), 10_000_000)
+    assert s2.workspace_bytes > s.workspace_bytes + 4 * 4 * 9_000_000
+    s3 = api.query_sizes(5, _cam(101, 37), api.dilation_struct(3, 2, 1), api.options_struct(8), 0)
+    assert (s3.w_ds, s3.h_ds, s3.grid_x, s3.grid_y) == (33, 12, 5, 2)
+
+
+@pytest.mark.parametrize("field,value", [("stride", 0), ("off_x", 2), ("off_y", -1)])
+def test_bad_dilation_rejected(field, value):
+    dil = api.dilation_struct(2, 0, 0)
+    setattr(dil, field, value)
+    out = api.tgs_sizes()
+    st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(dil), C.byref(api.options_struct(16)),
+                                   0, C.byref(out))
+    assert st == api.TGS_ERR_INVALID_ARG
+    assert b"" != api.lib().tgs_last_error()
+
+
+@pytest.mark.parametrize("tile", [0, 4, 12, 64])
+def test_bad_tile_rejected(tile):
+    out = api.tgs_sizes()
+    st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()),
+                                   C.byref(api.options_struct(tile)), 0, C.byref(out))
+    assert st == api.TGS_ERR_INVALID_ARG
+
+
+def test_bad_camera_rejected():
+    out = api.tgs_sizes()
+    for mutate in (lambda c: setattr(c, "width", 0), lambda c: setattr(c, "fx", -1.0),
+                   lambda c: setattr(c, "fy", float("nan"))):
+        cam = _cam()
+        mutate(cam)
+        st = api.lib().tgs_query_sizes(10, C.byref(cam), C.byref(api.dilation_struct()),
+                                       C.byref(api.options_struct()), 0, C.byref(out))
+        assert st == api.TGS_ERR_INVALID_ARG
+
+
+def _gauss(n=10, deg=0, coeffs=1, ptr=1 << 20):
+    return api.tgs_gaussians(n, deg, coeffs, ptr, ptr, ptr, ptr, ptr)
+
+
+@pytest.mark.parametrize("g,status", [
+    (_gauss(deg=4, coeffs=25), api.TGS_ERR_INVALID_ARG),
+    (_gauss(deg=2, coeffs=4), api.TGS_ERR_INVALID_ARG),
+    (_gauss(n=-1), api.TGS_ERR_INVALID_ARG),
+    (api.tgs_gaussians(10, 0, 1, None, None, None, None, None), api.TGS_ERR_INVALID_ARG),
+])
+def test_bad_gaussians_rejected_before_any_device_call(g, status):
+    st = api.tgs_state()
+    r = api.lib().tgs_forward(None, C.byref(g), C.byref(_cam()), C.byref(api.dilation_struct()),
+                              C.byref(api.options_struct()), C.byref(st), 1 << 20, None)
+    assert r == status
+
+
+def test_workspace_checks_before_device():
+    g = _gauss()
+    st = api.tgs_state()
+    lib = api.lib()
+    r = lib.tgs_preprocess_fwd(None, C.byref(g), C.byref(_cam()), C.byref(api.dilation_struct()),
+                               C.byref(api.options_struct()), C.byref(st), None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"workspace" in lib.tgs_last_error()
+    st.workspace = 4096 + 8            # misaligned
+    st.workspace_bytes = 1 << 30
+    r = lib.tgs_preprocess_fwd(None, C.byref(g), C.byref(_cam()), C.byref(api.dilation_struct()),
+                               C.byref(api.options_struct()), C.byref(st), None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"aligned" in lib.tgs_last_error()
+    st.workspace = 4096
+    st.workspace_bytes = 16
+    r = lib.tgs_preprocess_fwd(None, C.byref(g), C.byref(_cam()), C.byref(api.dilation_struct()),
+                               C.byref(api.options_struct()), C.byref(st), None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"required" in lib.tgs_last_error()
+    st.workspace_bytes = 1 << 30
+    r = lib.tgs_preprocess_fwd(None, C.byref(g), C.byref(_cam()), C.byref(api.dilation_struct()),
+                               C.byref(api.options_struct()), C.byref(st), None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"context" in lib.tgs_last_error()
+
+
+def test_raster_refuses_unbinned_state():
+    st = api.tgs_state()
+    st.workspace = 4096
+    st.workspace_bytes = 1 << 30
+    lib = api.lib()
+    r = lib.tgs_raster_fwd(None, C.byref(_cam()), C.byref(api.dilation_struct()),
+                           C.byref(api.options_struct()), C.byref(st), 10, 1 << 20, None, None, None,
+                           None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"binned" in lib.tgs_last_error()
+    r = lib.tgs_raster_bwd(None, C.byref(_cam()), C.byref(api.dilation_struct()),
+                           C.byref(api.options_struct()), C.byref(st), 10, 1 << 20, 1 << 20, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"binned" in lib.tgs_last_error()
+
+
+def test_create_reports_missing_device():
+    h = C.c_void_p()
+    assert api.lib().tgs_create(10_000, C.byref(h)) == api.TGS_ERR_NO_DEVICE
+    assert not h.value

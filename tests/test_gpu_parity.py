@@ -1,0 +1,300 @@
+"""GPU parity of every stage against the CPU checker (stage isolation: each
+checker stage is fed the HIP path's own upstream outputs, upcast to float64).
+
+Bars: sort keys, pair lists, tile ranges, tiles_touched bit-exact;
+last_contrib / n_eval exact except at pixels whose float decision lies within
+a hair of its threshold (the checker flags them); images within 1e-4 absolute;
+gradients within 1e-3 relative (norm-wise and element-wise)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import grad_close, records_to_oracle, run_gpu, say
+from oracle import backward as obw
+from oracle import binning as obn
+from oracle import loss as ols
+from oracle import pipeline as opipe
+from oracle import preprocess as opre
+from oracle import raster as ors
+from paper_2412_13547_amd import scenes
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+
+
+def _tiny():
+    sc, cam, tgt = scenes.workload(0)
+    return sc, cam, tgt
+
+
+def _small(seed, n, w, h, deg):
+    sc, cam = scenes.small_scene(seed, n, w, h, sh_degree=deg)
+    return sc, cam, scenes.target_image(w, h, 500 + seed)
+
+
+CASES = {
+    "tiny128-d1-T16": (_tiny, 1, 0, 0, 16, (0.0, 0.0, 0.0)),
+    "sh3-160x120-d2-o10-T16": (lambda: _small(1, 300, 160, 120, 3), 2, 1, 0, 16, (0.0, 0.0, 0.0)),
+    "sh2-101x77-d3-o21-T8-bg": (lambda: _small(2, 200, 101, 77, 2), 3, 2, 1, 8, (0.1, 0.2, 0.3)),
+    "sh1-150x130-d4-o32-T32": (lambda: _small(3, 250, 150, 130, 1), 4, 3, 2, 32, (0.0, 0.0, 0.0)),
+    "sh3-96x64-d1-T8": (lambda: _small(4, 300, 96, 64, 3), 1, 0, 0, 8, (0.0, 0.5, 0.0)),
+    "sh0-333x200-d2-o11-T16": (lambda: _small(5, 600, 333, 200, 0), 2, 1, 1, 16, (0.0, 0.0, 0.0)),
+}
+_CACHE = {}
+
+
+def _case(name):
+    if name not in _CACHE:
+        make, d, ox, oy, T, bg = CASES[name]
+        sc, cam, tgt = make()
+        say(f"[gpu] case {name}: n={sc.n} {cam.width}x{cam.height} d={d} o=({ox},{oy}) T={T}")
+        g = run_gpu(sc, cam, d, ox, oy, T, bg, target=tgt)
+        _CACHE[name] = (sc, cam, tgt, g)
+    return _CACHE[name]
+
+
+def _oracle_raster(g):
+    rec = records_to_oracle(g["records"])
+    return rec, ors.raster_forward(rec, g["pair_vals"].to(torch.int64), g["ranges"].to(torch.int64),
+                                   g["grid"], bg=g["bg"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preprocess_matches_checker(name):
+    sc, cam, _, g = _case(name)
+    o = opre.preprocess(opre.params(sc), opre.camera(cam))
+    rec = records_to_oracle(g["records"])
+    assert torch.equal(rec["culled"], o["culled"])
+    ok = ~o["culled"]
+    # integer decisions taken from floats: radius, flagged where 3 sqrt(lambda)
+    # lies within 1e-5 (relative) of an integer
+    ts = o["three_sigma"]
+    near = (ts - torch.round(ts)).abs() < 1e-5 * ts.clamp(min=1.0)
+    same_r = rec["radius"] == o["radius"]
+    assert bool((same_r | near)[ok].all())
+    scale_u = o["u"].abs() + abs(cam.cx) + cam.width
+    assert float(((rec["u"] - o["u"]).abs() / scale_u)[ok].max()) < 2e-6
+    assert float(((rec["v"] - o["v"]).abs() / (o["v"].abs() + abs(cam.cy) + cam.height))[ok].max()) < 2e-6
+    qs = torch.maximum(o["A"].abs(), o["C"].abs())
+    for k in ("A", "B", "C"):
+        assert float(((rec[k] - o[k]).abs() / qs)[ok].max()) < 1e-4, k
+    assert float((rec["rgb"] - o["rgb"]).abs()[ok].max()) < 2e-6
+    assert float(((rec["z"] - o["z"]).abs() / o["z"].abs())[ok].max()) < 1e-6
+    assert torch.equal(rec["opacity"][ok], torch.as_tensor(sc.opacities, dtype=F64)[ok])
+    # colour clamp decisions: exact except where the raw colour is within 1e-6 of 0
+    near0 = o["rgb_raw"].abs() < 1e-6
+    assert bool(((rec["clamp"] == o["clamp"]) | near0)[ok].all())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_binning_sort_ranges_bit_exact(name):
+    sc, cam, _, g = _case(name)
+    rec = records_to_oracle(g["records"])
+    b = obn.bin_gaussians(rec["u"], rec["v"], rec["z"], rec["radius"], rec["culled"], g["grid"])
+    assert torch.equal(g["tiles_touched"].to(torch.int64), b["tiles_touched"])
+    assert g["pair_count"] == b["keys"].numel()
+    vals = g["pair_vals"].to(torch.int64)
+    tiles = g["pair_tiles"].to(torch.int64)
+    keys = tiles * (1 << 32) + b["zbits"][vals]
+    assert torch.equal(keys, b["keys"])
+    assert torch.equal(vals, b["vals"])
+    assert torch.equal(g["ranges"].to(torch.int64), b["ranges"])
+    say(f"[gpu] {name}: {g['pair_count']} pairs bit-exact")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_raster_forward_matches_checker(name):
+    sc, cam, _, g = _case(name)
+    _, o = _oracle_raster(g)
+    flag = o["flag"]
+    say(f"[gpu] {name}: flagged pixels {int(flag.sum())} of {flag.numel()}")
+    assert float(flag.float().mean()) < 0.01
+    err = (g["image"].to(F64) - o["image"]).abs()
+    assert float(err.max()) <= 1e-4, float(err.max())
+    keep = ~flag
+    assert torch.equal(g["last_contrib"].to(torch.int64)[keep], o["last_contrib"][keep])
+    assert torch.equal(g["n_eval"].to(torch.int64)[keep], o["n_eval"][keep])
+    assert float((g["t_final"].to(F64) - o["t_final"]).abs()[keep].max()) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_raster_backward_matches_checker(name):
+    sc, cam, _, g = _case(name)
+    rec, o = _oracle_raster(g)
+    dL = g["dL"].to(F64) * (~o["flag"]).to(F64)[None]
+    view = g["_view"]
+    view.raster_bwd(g["_image"], dL.to(torch.float32).cuda())
+    torch.cuda.synchronize()
+    got = view.grad2d().cpu()
+    want = obw.raster_backward(rec, g["pair_vals"].to(torch.int64), g["ranges"].to(torch.int64),
+                               g["grid"], dL, bg=g["bg"])
+    names = ("u", "v", "A", "B", "C", "opacity", "r", "g", "b")
+    for c, nm in enumerate(names):
+        grad_close(got[:, c], want[:, c], name=f"{name} d{nm}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preprocess_backward_matches_checker(name):
+    sc, cam, _, g = _case(name)
+    c = opre.camera(cam)
+    o = opre.preprocess(opre.params(sc), c)
+    # Gaussians whose colour clamp or FoV guard sits on its threshold are
+    # excluded: their derivative is discontinuous there
+    lim_x = 1.3 * cam.width / (2 * cam.fx)
+    lim_y = 1.3 * cam.height / (2 * cam.fy)
+    tz = torch.as_tensor(sc.means.T.astype(np.float64)) @ c.R.T + c.t
+    rx, ry = tz[:, 0] / tz[:, 2], tz[:, 1] / tz[:, 2]
+    bad = (o["rgb_raw"].abs() < 1e-5).any(1) | ((rx.abs() - lim_x).abs() < 1e-5) | \
+          ((ry.abs() - lim_y).abs() < 1e-5)
+    view = g["_view"]
+    g2d_dev = view.grad2d()
+    g2d_dev[bad.cuda()] = 0.0
+    grads = g["_dev"].zeros_like()
+    view.preprocess_bwd(g["_dev"], grads)
+    torch.cuda.synchronize()
+    g2d = g2d_dev.cpu().to(F64)
+    p = opre.params(sc, requires_grad=True)
+    want = obw.preprocess_backward(p, c, g2d)
+    got = {k: getattr(grads, k).cpu() for k in ("means", "scales", "quats", "opacities", "sh")}
+    grad_close(got["means"].T, want["means"], name=f"{name} means")
+    grad_close(got["scales"].T, want["scales"], name=f"{name} scales")
+    grad_close(got["quats"].T, want["quats"], name=f"{name} quats")
+    grad_close(got["opacities"], want["opacities"], name=f"{name} opacities")
+    grad_close(got["sh"].permute(2, 0, 1), want["sh"], name=f"{name} sh")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_statistics_match_checker(name):
+    sc, cam, _, g = _case(name)
+    g2d = g["grad2d"].to(F64)
+    vis = g["tiles_touched"] > 0
+    pos, col = obw.densification_stats(g2d, vis, cam.width, cam.height)
+    assert torch.equal(g["visible"].bool(), vis)
+    np.testing.assert_allclose(g["pos_stat"].numpy(), pos.numpy(), rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(g["col_stat"].numpy(), col.numpy(), rtol=1e-5, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["tiny128-d1-T16", "sh3-160x120-d2-o10-T16", "sh2-101x77-d3-o21-T8-bg"])
+def test_end_to_end_against_pure_checker(name):
+    """No stage isolation: the whole HIP path against the float64 checker."""
+    sc, cam, tgt, g = _case(name)
+    make, d, ox, oy, T, bg = CASES[name]
+    o = opipe.forward_backward(sc, cam, tgt, d, ox, oy, T, bg)
+    loss = float(g["loss"][0])
+    assert abs(loss - float(o["loss"])) <= 1e-5 * float(o["loss"]), (loss, float(o["loss"]))
+    keep = ~o["flag"]
+    err = (g["image"].to(F64) - o["image"].detach()).abs().amax(0)[keep]
+    assert float(err.max()) <= 1e-4
+    frac = float((g["last_contrib"].to(torch.int64) != o["last_contrib"]).float().mean())
+    say(f"[gpu] {name}: end-to-end last_contrib mismatch fraction {frac:.2e}")
+    assert frac < 1e-3
+    # gradients: same signs of the L1 residual are needed for comparability
+    sg_gpu = torch.sign(g["dL"])
+    sg_o = torch.sign(o["dL_dimage"])
+    if bool((sg_gpu == sg_o).all()) and frac == 0.0:
+        for k, shape_fn in (("means", lambda t: t.T), ("scales", lambda t: t.T),
+                            ("quats", lambda t: t.T), ("opacities", lambda t: t),
+                            ("sh", lambda t: t.permute(2, 0, 1))):
+            grad_close(shape_fn(g["grads"][k]), o["grads"][k], rel=2e-3, name=f"{name} {k}")
+
+
+# ---- closed forms and degenerate inputs through the whole HIP path --------
+
+def _scene(means, scales, quats, opac, rgb):
+    means = np.asarray(means, np.float32).reshape(3, -1)
+    n = means.shape[1]
+    rgb = np.asarray(rgb, np.float64).reshape(3, n)
+    sh = ((rgb - 0.5) * 2.0 * math.sqrt(math.pi))[None].astype(np.float32)
+    return scenes.Scene(means, np.asarray(scales, np.float32).reshape(3, n),
+                        np.asarray(quats, np.float32).reshape(4, n),
+                        np.asarray(opac, np.float32).reshape(n), sh, 0)
+
+
+def test_single_gaussian_peak_is_opacity_times_colour():
+    cam = scenes.identity_camera(65, 49, 65.0)           # centre pixel (32, 24)
+    sc = _scene([0, 0, 3.0], [0.05] * 3, [1, 0, 0, 0], [0.7], [0.2, 0.6, 0.9])
+    g = run_gpu(sc, cam, backward=False)
+    np.testing.assert_allclose(g["image"][:, 24, 32].numpy(), 0.7 * np.array([0.2, 0.6, 0.9]),
+                               atol=2e-6)
+    sc = _scene([0, 0, 3.0], [0.05] * 3, [1, 0, 0, 0], [1.0], [0.2, 0.6, 0.9])
+    g = run_gpu(sc, cam, backward=False)
+    np.testing.assert_allclose(g["image"][:, 24, 32].numpy(), 0.99 * np.array([0.2, 0.6, 0.9]),
+                               atol=2e-6)
+
+
+def test_saturation_stops_before_fourth_splat():
+    cam = scenes.identity_camera(65, 49, 65.0)
+    z = [2.0, 2.5, 3.0, 3.5]
+    cols = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0], [1.0, 1.0, 1.0]]).T
+    sc = _scene([[0] * 4, [0] * 4, z], [[0.05] * 4] * 3, [[1] * 4, [0] * 4, [0] * 4, [0] * 4],
+                [0.95] * 4, cols)
+    g = run_gpu(sc, cam, backward=False)
+    want = np.array([0.95, 0.0475, 0.002375])
+    np.testing.assert_allclose(g["image"][:, 24, 32].numpy(), want, atol=2e-6)
+    assert int(g["last_contrib"][24, 32]) == 3 and int(g["n_eval"][24, 32]) == 4
+    assert abs(float(g["t_final"][24, 32]) - 1.25e-4) < 1e-8
+
+
+def test_empty_scene_renders_background():
+    cam = scenes.identity_camera(40, 30, 40.0)
+    sc = _scene(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros((4, 0)), np.zeros(0), np.zeros((3, 0)))
+    bg = (0.25, 0.5, 0.75)
+    g = run_gpu(sc, cam, bg=bg, target=np.zeros((3, 30, 40), np.float32))
+    for c in range(3):
+        assert float((g["image"][c] - bg[c]).abs().max()) == 0.0
+    assert g["pair_count"] == 0
+    assert abs(float(g["loss"][0]) - np.mean(bg)) < 1e-7
+
+
+def test_all_culled_and_zero_opacity():
+    cam = scenes.identity_camera(48, 32, 48.0)
+    n = 50
+    rng = np.random.default_rng(0)
+    means = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-3, 0.19, n)])
+    sc = _scene(means, np.full((3, n), 0.1), np.tile([[1], [0], [0], [0]], n), np.full(n, 0.5),
+                np.full((3, n), 0.5))
+    g = run_gpu(sc, cam, target=np.ones((3, 32, 48), np.float32))
+    assert g["pair_count"] == 0 and float(g["image"].abs().max()) == 0.0
+    for k, v in g["grads"].items():
+        assert float(v.abs().max()) == 0.0, k
+    means[2] = rng.uniform(2, 4, n)
+    sc = _scene(means, np.full((3, n), 0.1), np.tile([[1], [0], [0], [0]], n), np.zeros(n),
+                np.full((3, n), 0.5))
+    g = run_gpu(sc, cam, target=np.ones((3, 32, 48), np.float32))
+    assert g["pair_count"] > 0 and float(g["image"].abs().max()) == 0.0
+    assert float(g["grads"]["means"].abs().max()) == 0.0
+    assert float(g["grads"]["sh"].abs().max()) == 0.0
+
+
+def test_non_finite_gaussians_are_culled():
+    sc, cam, tgt = _small(8, 60, 64, 48, 1)
+    sc.means[0, 3] = np.nan
+    sc.scales[1, 7] = np.inf
+    sc.sh[2, 1, 11] = np.nan
+    g = run_gpu(sc, cam, target=tgt)
+    rec = records_to_oracle(g["records"])
+    assert bool(rec["culled"][[3, 7, 11]].all())
+    assert bool(torch.isfinite(g["image"]).all())
+    for k, v in g["grads"].items():
+        assert bool(torch.isfinite(v).all()), k
+
+
+def test_capacity_growth_and_error():
+    """A workspace too small for the pairs reports TGS_ERR_CAPACITY with the count."""
+    from gpu_helpers import ctx
+    from paper_2412_13547_amd import api
+    sc, cam, tgt = _small(9, 200, 128, 96, 0)
+    dev = api.DeviceScene.from_scene(sc)
+    view = api.View(ctx(), sc.n, cam, pair_capacity=16)
+    view.preprocess_fwd(dev)
+    with pytest.raises(api.TgsError) as e:
+        view.bin_sort(dev, grow=False)
+    assert e.value.status == api.TGS_ERR_CAPACITY
+    need = int(view.state.pair_count)
+    assert need > 16
+    img = view.forward(dev)       # grows and re-runs
+    torch.cuda.synchronize()
+    assert int(view.state.pair_count) == need and view.state.pair_capacity >= need
+    assert bool(torch.isfinite(img).all())
