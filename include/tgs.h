@@ -94,7 +94,8 @@ typedef struct tgs_grads {
     float* sh;               /* device [sh_coeffs][3][n]; rows >= (deg+1)^2 are 0 */
 } tgs_grads;
 
-/* Sizes of one view, filled by tgs_query_sizes (host only). */
+/* Sizes of one view, filled by tgs_query_sizes (host only).  The tile grid
+ * may be at most 1024 tiles wide and 4096 tall (TGS_ERR_UNSUPPORTED). */
 typedef struct tgs_sizes {
     int32_t w_ds, h_ds;      /* downsampled image size                           */
     int32_t grid_x, grid_y;  /* tile grid of the downsampled image               */
@@ -135,8 +136,8 @@ typedef struct tgs_state {
     uint64_t off_records;        /* out: tgs_record[n]                                    */
     uint64_t off_tiles_touched;  /* out: uint32[n], ds tiles each Gaussian overlaps       */
     uint64_t off_depth_order;    /* out: uint32[n], Gaussian ids sorted by depth key      */
-    uint64_t off_pair_tiles;     /* out: uint32[pair_count], sorted tile ids              */
-    uint64_t off_pair_vals;      /* out: uint32[pair_count], Gaussian id of each pair     */
+    uint64_t off_pair_vals;      /* out: uint32[pair_count], Gaussian id of each pair in
+                                         (tile, depth, index) order                      */
     uint64_t off_ranges;         /* out: uint32[num_tiles][2], [start, end) per tile      */
     uint64_t off_grad2d;         /* out: float[n][9], dL/d(u,v,A,B,C,o,r,g,b) (backward)  */
 } tgs_state;

@@ -61,7 +61,7 @@ class tgs_state(C.Structure):
                 ("pair_capacity", C.c_uint64), ("pair_count", C.c_uint64),
                 ("key_bits", C.c_uint32), ("reserved", C.c_uint32),
                 ("off_records", C.c_uint64), ("off_tiles_touched", C.c_uint64),
-                ("off_depth_order", C.c_uint64), ("off_pair_tiles", C.c_uint64),
+                ("off_depth_order", C.c_uint64),
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
                 ("off_grad2d", C.c_uint64)]
 
@@ -365,9 +365,6 @@ class View:
 
     def depth_order(self):
         return self._view(self.state.off_depth_order, self.n, self._torch.int32)
-
-    def pair_tiles(self):
-        return self._view(self.state.off_pair_tiles, int(self.state.pair_count), self._torch.int32)
 
     def pair_vals(self):
         return self._view(self.state.off_pair_vals, int(self.state.pair_count), self._torch.int32)

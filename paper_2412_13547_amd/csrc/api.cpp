@@ -14,8 +14,12 @@
 
 struct tgs_context {
     int device;
-    uint64_t* pinned;   // host-pinned readback slot for the pair count
+    uint64_t* pinned;   // host-pinned readback of the tile-row starts
 };
+
+namespace {
+constexpr size_t kPinnedBytes = 4 * (tgs::kMaxCols * 4 + 8);   // row starts of the tallest grid
+}
 
 namespace {
 
@@ -92,10 +96,18 @@ tgs_status check_gaussians(const tgs_gaussians* g) {
     return TGS_OK;
 }
 
+tgs_status check_grid(const tgs::Grid& g) {
+    if (g.gx > tgs::kMaxCols || g.gy > 4 * tgs::kMaxCols)
+        return fail(TGS_ERR_UNSUPPORTED, "tile grid %dx%d exceeds %dx%d", g.gx, g.gy, tgs::kMaxCols,
+                    4 * tgs::kMaxCols);
+    return TGS_OK;
+}
+
 tgs_status check_common(const tgs_camera* cam, const tgs_dilation* dil, const tgs_options* opt) {
     tgs_status s = check_camera(cam);
     if (s == TGS_OK) s = check_dilation(dil, cam);
     if (s == TGS_OK && opt) s = check_options(opt);
+    if (s == TGS_OK && opt) s = check_grid(tgs::make_grid(*cam, *dil, opt->tile));
     return s;
 }
 
@@ -104,7 +116,7 @@ tgs_status check_state(const tgs_state* st, int64_t n, const tgs::Grid& grid, tg
     if (!st->workspace) return fail(TGS_ERR_INVALID_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(st->workspace) % 256 != 0)
         return fail(TGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    *L = tgs::make_layout(n, st->pair_capacity, grid.num_tiles());
+    *L = tgs::make_layout(n, st->pair_capacity, grid);
     if (st->workspace_bytes < L->total)
         return fail(TGS_ERR_INVALID_ARG, "workspace of %llu bytes < %llu required",
                     (unsigned long long)st->workspace_bytes, (unsigned long long)L->total);
@@ -126,17 +138,16 @@ tgs_status check_binned(const tgs_state* st, const tgs::Layout& L, const tgs::Gr
     if (st->pair_count > st->pair_capacity)
         return fail(TGS_ERR_CAPACITY, "state holds %llu pairs, capacity %llu",
                     (unsigned long long)st->pair_count, (unsigned long long)st->pair_capacity);
-    if (st->off_pair_vals != L.pair_val[0] && st->off_pair_vals != L.pair_val[1])
+    if (st->off_pair_vals != L.pair_vals)
         return fail(TGS_ERR_INVALID_ARG, "state offsets do not match its layout");
     return TGS_OK;
 }
 
-void publish_offsets(tgs_state* st, const tgs::Layout& L, int depth_buf, int pair_buf) {
+void publish_offsets(tgs_state* st, const tgs::Layout& L, int depth_buf) {
     st->off_records = L.records;
     st->off_tiles_touched = L.tiles_touched;
     st->off_depth_order = L.depth_val[depth_buf];
-    st->off_pair_tiles = L.pair_tile[pair_buf];
-    st->off_pair_vals = L.pair_val[pair_buf];
+    st->off_pair_vals = L.pair_vals;
     st->off_ranges = L.ranges;
     st->off_grad2d = L.grad2d;
 }
@@ -166,7 +177,7 @@ Grid make_grid(const tgs_camera& cam, const tgs_dilation& dil, int tile) {
     return g;
 }
 
-Layout make_layout(int64_t n, uint64_t cap, int64_t num_tiles) {
+Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     Layout L{};
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) {
@@ -175,21 +186,27 @@ Layout make_layout(int64_t n, uint64_t cap, int64_t num_tiles) {
         return at;
     };
     const uint64_t un = uint64_t(n);
+    const uint64_t gy = uint64_t(grid.gy), gx = uint64_t(grid.gx);
+    const uint64_t rowtot = gy * bin_chunks(n) + 1;
+    const uint64_t hist = gx * bin_max_slices(cap, grid.gy);
     L.records = take(un * kRecordBytes);
     L.tiles_touched = take(un * 4);
     for (int b = 0; b < 2; ++b) L.depth_key[b] = take(un * 4);
     for (int b = 0; b < 2; ++b) L.depth_val[b] = take(un * 4);
-    L.offsets = take((un + 1) * 8);
-    for (int b = 0; b < 2; ++b) L.pair_tile[b] = take(cap * 4);
-    for (int b = 0; b < 2; ++b) L.pair_val[b] = take(cap * 4);
-    L.ranges = take(uint64_t(num_tiles) * 8);
+    L.rowtot = take(rowtot * 4);
+    L.row_start = take((gy + 1) * 4);
+    L.first_slice = take((gy + 1) * 4);
+    L.row_cols = take(cap * 2);
+    L.row_vals = take(cap * 4);
+    L.pair_vals = take(cap * 4);
+    L.col_hist = take(hist * 4);
+    L.ranges = take(uint64_t(grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
-    const uint64_t most = cap > un ? cap : un;
-    const uint64_t counts = radix_counts_elems(most);
-    L.sort_counts = take(counts * 4);
-    const uint64_t parts = scan_partials_elems(counts > un ? counts : un);
-    L.scan_partials = take(parts * 8);
-    L.misc = take(256);
+    L.sort_counts = take(radix_counts_elems(un) * 4);
+    uint64_t most = radix_counts_elems(un);
+    if (rowtot > most) most = rowtot;
+    if (hist > most) most = hist;
+    L.scan_partials = take(scan_partials_elems(most) * 8);
     L.total = o;
     return L;
 }
@@ -244,7 +261,8 @@ tgs_status tgs_create(int device, tgs_context** out) {
     TGS_HIP(hipSetDevice(device));
     auto* ctx = new (std::nothrow) tgs_context{device, nullptr};
     if (!ctx) return fail(TGS_ERR_HIP, "out of host memory");
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), 64, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kPinnedBytes,
+                                 hipHostMallocDefault);
     if (e != hipSuccess) {
         delete ctx;
         return hip_fail(e, "hipHostMalloc");
@@ -269,7 +287,8 @@ tgs_status tgs_query_sizes(int64_t n, const tgs_camera* cam, const tgs_dilation*
     if (pair_capacity > uint64_t(UINT32_MAX))
         return fail(TGS_ERR_UNSUPPORTED, "pair capacity above 2^32 - 1");
     const tgs::Grid g = tgs::make_grid(*cam, *dil, opt->tile);
-    const tgs::Layout L = tgs::make_layout(n, pair_capacity, g.num_tiles());
+    if ((s = check_grid(g)) != TGS_OK) return s;
+    const tgs::Layout L = tgs::make_layout(n, pair_capacity, g);
     out->w_ds = g.w_ds;
     out->h_ds = g.h_ds;
     out->grid_x = g.gx;
@@ -297,7 +316,7 @@ tgs_status tgs_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, const tg
                                        static_cast<hipStream_t>(stream)));
     st->pair_count = 0;
     st->key_bits = 0;     // not binned yet
-    publish_offsets(st, L, 0, 0);
+    publish_offsets(st, L, 0);
     return TGS_OK;
 }
 
@@ -317,36 +336,41 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     const int64_t n = g->n;
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
     auto* partials = reinterpret_cast<uint64_t*>(ws + L.scan_partials);
-    auto* offsets = reinterpret_cast<uint64_t*>(ws + L.offsets);
 
     // 1. Gaussians by depth key (stable; culled and off-screen ones last)
     uint32_t* dkeys[2] = {u32(L.depth_key[0]), u32(L.depth_key[1])};
     uint32_t* dvals[2] = {u32(L.depth_val[0]), u32(L.depth_val[1])};
     int dres = 0;
     TGS_HIP(tgs::radix_sort(dkeys, dvals, uint64_t(n), 32, u32(L.sort_counts), partials, &dres, strm));
-    // 2. pair offsets in depth order, and the total read back
-    TGS_HIP(tgs::exclusive_scan_u64(u32(L.tiles_touched), dvals[dres], offsets, uint64_t(n),
-                                    partials, strm));
-    TGS_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, strm));
+    const uint32_t* order = dvals[dres];
+    // 2. pairs per (tile row, chunk of the depth order); scan -> row buckets
+    const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_chunks(n);
+    TGS_HIP(tgs::launch_row_counts(ws, L, order, n, grid, strm));
+    TGS_HIP(tgs::exclusive_scan_u32(u32(L.rowtot), u32(L.rowtot), nrow, partials, true, strm));
+    TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, strm));
+    // 3. row starts (and the pair count) back to the host
+    TGS_HIP(hipMemcpyAsync(ctx->pinned, u32(L.row_start), (uint64_t(grid.gy) + 1) * 4,
+                           hipMemcpyDeviceToHost, strm));
     TGS_HIP(hipStreamSynchronize(strm));
-    const uint64_t P = *ctx->pinned;
+    const uint32_t* rs = reinterpret_cast<const uint32_t*>(ctx->pinned);
+    const uint64_t P = rs[grid.gy];
+    uint64_t slices = 0;
+    for (int ty = 0; ty < grid.gy; ++ty) slices += (uint64_t(rs[ty + 1] - rs[ty]) + tgs::kSlice - 1) / tgs::kSlice;
     st->pair_count = P;
     st->key_bits = 0;
-    publish_offsets(st, L, dres, 0);
+    publish_offsets(st, L, dres);
     if (P > st->pair_capacity)
         return fail(TGS_ERR_CAPACITY, "%llu pairs needed, capacity %llu", (unsigned long long)P,
                     (unsigned long long)st->pair_capacity);
-    // 3. emit pairs in depth order, then sort them stably by tile id
-    uint32_t* ptiles[2] = {u32(L.pair_tile[0]), u32(L.pair_tile[1])};
-    uint32_t* pvals[2] = {u32(L.pair_val[0]), u32(L.pair_val[1])};
-    TGS_HIP(tgs::launch_emit_pairs(ws, L, dvals[dres], n, grid, ptiles[0], pvals[0], strm));
-    int pres = 0;
-    const int bits = key_bits_for(grid.num_tiles());
-    TGS_HIP(tgs::radix_sort(ptiles, pvals, P, bits, u32(L.sort_counts), partials, &pres, strm));
-    // 4. per-tile ranges
-    TGS_HIP(tgs::launch_ranges(ptiles[pres], P, u32(L.ranges), grid.num_tiles(), strm));
-    publish_offsets(st, L, dres, pres);
-    st->key_bits = uint32_t(bits);   // marks the state as binned for this grid
+    // 4. emit into row buckets, then a stable counting sort by column per row
+    TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, strm));
+    TGS_HIP(tgs::launch_col_hist(ws, L, grid, slices, strm));
+    TGS_HIP(tgs::exclusive_scan_u32(u32(L.col_hist), u32(L.col_hist), uint64_t(grid.gx) * slices,
+                                    partials, false, strm));
+    TGS_HIP(tgs::launch_col_scatter(ws, L, grid, slices, strm));
+    // 5. per-tile ranges from the column histogram scan
+    TGS_HIP(tgs::launch_tile_ranges(ws, L, grid, strm));
+    st->key_bits = uint32_t(key_bits_for(grid.num_tiles()));   // marks the state as binned
     return TGS_OK;
 }
 

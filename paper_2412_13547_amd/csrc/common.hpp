@@ -25,6 +25,9 @@ constexpr int kRadixBuckets = 1 << kRadixBits;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
+// binning: pairs per column-sort slice, and the widest tile grid supported
+constexpr int kSlice = 4096;
+constexpr int kMaxCols = 1024;
 
 enum RecordFlags : uint32_t {
     kClampR = 1u, kClampG = 2u, kClampB = 4u, kCulled = 8u, kFovX = 16u, kFovY = 32u
@@ -35,7 +38,7 @@ struct Grid {
     int stride, off_x, off_y;
     int tile;
     int w_ds, h_ds, gx, gy;
-    int64_t num_tiles() const { return int64_t(gx) * gy; }
+    __host__ __device__ int64_t num_tiles() const { return int64_t(gx) * gy; }
 };
 
 Grid make_grid(const tgs_camera& cam, const tgs_dilation& dil, int tile);
@@ -44,17 +47,21 @@ Grid make_grid(const tgs_camera& cam, const tgs_dilation& dil, int tile);
 struct Layout {
     uint64_t records, tiles_touched;
     uint64_t depth_key[2], depth_val[2];
-    uint64_t offsets;          // uint64[n + 1]
-    uint64_t pair_tile[2], pair_val[2];
+    uint64_t rowtot;           // uint32[gy * chunks + 1], pairs per (row, chunk), then scanned
+    uint64_t row_start;        // uint32[gy + 1]
+    uint64_t first_slice;      // uint32[gy + 1]
+    uint64_t row_cols;         // uint16[capacity], column of each pair, row-bucketed
+    uint64_t row_vals;         // uint32[capacity], Gaussian of each pair, row-bucketed
+    uint64_t pair_vals;        // uint32[capacity], Gaussian of each pair, final order
+    uint64_t col_hist;         // uint32[gx * max_slices], column histograms, then scanned
     uint64_t ranges;           // uint32[num_tiles][2]
     uint64_t grad2d;           // float[n][9]
     uint64_t sort_counts;      // uint32, radix digit counts
     uint64_t scan_partials;    // uint64, scan block sums
-    uint64_t misc;             // small counters
     uint64_t total;
 };
 
-Layout make_layout(int64_t n, uint64_t pair_capacity, int64_t num_tiles);
+Layout make_layout(int64_t n, uint64_t pair_capacity, const Grid& grid);
 
 // Device kernel launchers (stream-ordered, no synchronisation).
 struct CamDev {
@@ -79,18 +86,26 @@ hipError_t radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint64_t
                       uint32_t* counts, uint64_t* partials, int* result, hipStream_t s);
 uint64_t radix_counts_elems(uint64_t count);
 
-// Exclusive scan of uint32 values into uint64 (out has count + 1 entries;
-// out[count] is the total).  If gather != nullptr the i-th input is
-// in[gather[i]].
-hipError_t exclusive_scan_u64(const uint32_t* in, const uint32_t* gather, uint64_t* out,
-                              uint64_t count, uint64_t* partials, hipStream_t s);
+// Exclusive scan of uint32 (in may equal out); with write_total, out[count]
+// receives the total (out then has count + 1 entries).
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
+                              uint64_t* partials, bool write_total, hipStream_t s);
 uint64_t scan_partials_elems(uint64_t count);
 
-hipError_t launch_emit_pairs(const uint8_t* ws, const Layout& L, const uint32_t* order,
-                             int64_t n, const Grid& grid, uint32_t* tiles, uint32_t* vals,
-                             hipStream_t s);
-hipError_t launch_ranges(const uint32_t* tiles, uint64_t count, uint32_t* ranges,
-                         int64_t num_tiles, hipStream_t s);
+// binning (binning.hip)
+uint32_t bin_chunks(int64_t n);
+uint64_t bin_max_slices(uint64_t pairs, int gy);
+hipError_t launch_row_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
+                             const Grid& grid, hipStream_t s);
+hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid& grid,
+                            hipStream_t s);
+hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
+                            const Grid& grid, hipStream_t s);
+hipError_t launch_col_hist(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
+                           hipStream_t s);
+hipError_t launch_col_scatter(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
+                              hipStream_t s);
+hipError_t launch_tile_ranges(uint8_t* ws, const Layout& L, const Grid& grid, hipStream_t s);
 
 hipError_t launch_raster_fwd(const Grid& grid, const float bg[3], const uint8_t* ws,
                              const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,

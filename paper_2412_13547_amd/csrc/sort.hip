@@ -208,10 +208,11 @@ uint64_t radix_counts_elems(uint64_t count) {
 
 int radix_sort_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
 
-hipError_t exclusive_scan_u64(const uint32_t* in, const uint32_t* gather, uint64_t* out,
-                              uint64_t count, uint64_t* partials, hipStream_t s) {
-    if (count == 0) return fill_u32(reinterpret_cast<uint32_t*>(out), 0u, 2, s);
-    return exclusive_scan<uint32_t, uint64_t>(in, gather, out, count, partials, true, s);
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
+                              uint64_t* partials, bool write_total, hipStream_t s) {
+    if (count == 0) return write_total ? fill_u32(out, 0u, 1, s) : hipSuccess;
+    return exclusive_scan<uint32_t, uint32_t>(in, nullptr, out, count,
+                                              reinterpret_cast<uint32_t*>(partials), write_total, s);
 }
 
 hipError_t radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint64_t count, int bits,

@@ -62,7 +62,6 @@ def run_gpu(scene, cam, stride=1, off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0),
             host[k] = v.cpu()
     host["records"] = view.records().cpu()
     host["tiles_touched"] = view.tiles_touched().cpu()
-    host["pair_tiles"] = view.pair_tiles().cpu()
     host["pair_vals"] = view.pair_vals().cpu()
     host["ranges"] = view.ranges().cpu()
     host["pair_count"] = int(view.state.pair_count)

@@ -44,7 +44,7 @@ def test_query_sizes_host_only():
     assert (s.w_ds, s.h_ds, s.grid_x, s.grid_y) == (1920, 1080, 120, 68)
     assert s.num_tiles == 8160 and s.pixels == 1920 * 1080
     s2 = api.query_sizes(3_000_000, cam, api.dilation_struct(2, 1, 0), api.options_struct(16), 10_000_000)
-    assert s2.workspace_bytes > s.workspace_bytes + 4 * 4 * 9_000_000
+    assert s2.workspace_bytes >= s.workspace_bytes + 10 * 9_990_000   # >= 10 B per pair
     s3 = api.query_sizes(5, _cam(101, 37), api.dilation_struct(3, 2, 1), api.options_struct(8), 0)
     assert (s3.w_ds, s3.h_ds, s3.grid_x, s3.grid_y) == (33, 12, 5, 2)
 

@@ -96,7 +96,9 @@ def test_binning_sort_ranges_bit_exact(name):
     assert torch.equal(g["tiles_touched"].to(torch.int64), b["tiles_touched"])
     assert g["pair_count"] == b["keys"].numel()
     vals = g["pair_vals"].to(torch.int64)
-    tiles = g["pair_tiles"].to(torch.int64)
+    rg = g["ranges"].to(torch.int64)
+    tiles = torch.repeat_interleave(torch.arange(rg.shape[0]), rg[:, 1] - rg[:, 0])
+    assert tiles.numel() == vals.numel()
     keys = tiles * (1 << 32) + b["zbits"][vals]
     assert torch.equal(keys, b["keys"])
     assert torch.equal(vals, b["vals"])
