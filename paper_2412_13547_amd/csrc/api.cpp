@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -211,6 +212,22 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     return L;
 }
 
+RasterTuning raster_tuning() {
+    static const RasterTuning t = [] {
+        RasterTuning r;
+        if (const char* e = std::getenv("TGS_RASTER_PPT")) {
+            const int v = std::atoi(e);
+            if (v == 1 || v == 2 || v == 4) r.ppt = v;
+        }
+        if (const char* e = std::getenv("TGS_TILE_ORDER")) {
+            const int v = std::atoi(e);
+            if (v == 0 || v == 1) r.order = v;
+        }
+        return r;
+    }();
+    return t;
+}
+
 CamDev make_cam(const tgs_camera& c) {
     CamDev d{};
     for (int r = 0; r < 3; ++r) {
@@ -362,14 +379,10 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     if (P > st->pair_capacity)
         return fail(TGS_ERR_CAPACITY, "%llu pairs needed, capacity %llu", (unsigned long long)P,
                     (unsigned long long)st->pair_capacity);
-    // 4. emit into row buckets, then a stable counting sort by column per row
+    // 4. emit into row buckets, then a stable counting sort by column per row,
+    //    which also yields the per-tile ranges
     TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, strm));
-    TGS_HIP(tgs::launch_col_hist(ws, L, grid, slices, strm));
-    TGS_HIP(tgs::exclusive_scan_u32(u32(L.col_hist), u32(L.col_hist), uint64_t(grid.gx) * slices,
-                                    partials, false, strm));
-    TGS_HIP(tgs::launch_col_scatter(ws, L, grid, slices, strm));
-    // 5. per-tile ranges from the column histogram scan
-    TGS_HIP(tgs::launch_tile_ranges(ws, L, grid, strm));
+    TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, strm));
     st->key_bits = uint32_t(key_bits_for(grid.num_tiles()));   // marks the state as binned
     return TGS_OK;
 }
@@ -388,7 +401,7 @@ tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     if ((s = check_binned(st, L, grid)) != TGS_OK) return s;
     if ((s = use_device(ctx)) != TGS_OK) return s;
     auto* ws = static_cast<uint8_t*>(st->workspace);
-    TGS_HIP(tgs::launch_raster_fwd(grid, opt->bg, ws, L,
+    TGS_HIP(tgs::launch_raster_fwd(grid, tgs::raster_tuning(), opt->bg, ws, L,
                                    reinterpret_cast<const uint32_t*>(ws + st->off_pair_vals),
                                    uint32_t(st->pair_count), image, t_final, last_contrib, n_eval,
                                    static_cast<hipStream_t>(stream)));
@@ -436,7 +449,7 @@ tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     auto strm = static_cast<hipStream_t>(stream);
     auto* g2d = reinterpret_cast<float*>(ws + L.grad2d);
     TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
-    TGS_HIP(tgs::launch_raster_bwd(grid, opt->bg, ws, L,
+    TGS_HIP(tgs::launch_raster_bwd(grid, tgs::raster_tuning(), ws, L,
                                    reinterpret_cast<const uint32_t*>(ws + st->off_pair_vals),
                                    uint32_t(st->pair_count), image, dL_dimage, g2d, strm));
     return TGS_OK;

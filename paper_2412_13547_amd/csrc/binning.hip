@@ -12,29 +12,23 @@
 //   3. emit_rows: every chunk writes, row by row, its pairs (column, Gaussian)
 //      into the row buckets -- in depth order, each Gaussian's columns
 //      ascending, with fully coalesced stores;
-//   4. col_hist + scan + col_scatter: each row bucket is cut into slices of
-//      4096 pairs; a stable counting sort by column (LDS-staged, wavefront
-//      ballots for ranks) moves each slice's pairs to their final place.
-//      Within a column the depth order of step 3 is kept, which is the
-//      (tile, depth, index) order.
-//   5. tile_ranges: [start, end) of every tile straight from the column
-//      histogram scan.
-// Memory traffic: 6 B per pair written by the emission, 2 B read by the
+//   4. col_hist + col_scan + col_scatter: each row bucket is cut into slices
+//      of kSlice pairs; a stable counting sort by column (LDS-staged,
+//      wavefront ballots for ranks) moves each slice's pairs to their final
+//      place.  Within a column the depth order of step 3 is kept, which is the
+//      (tile, depth, index) order.  col_scan also writes every tile's
+//      [start, end).
+// Memory traffic per pair: 6 B written by the emission, 2 B read by the
 // histogram, 6 B read and 4 B written by the scatter.
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace tgs {
 namespace {
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    return (uint64_t(1) << __lane_id()) - 1;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
+constexpr int kScatterThreads = 512;
+constexpr int kScatterWaves = kScatterThreads / 64;
+constexpr int kScatterRounds = kSlice / kScatterThreads;   // pairs per thread
 
 __device__ __forceinline__ int wave_min(int x) {
     for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
@@ -44,17 +38,6 @@ __device__ __forceinline__ int wave_min(int x) {
 __device__ __forceinline__ int wave_max(int x) {
     for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
     return x;
-}
-
-__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t x, uint32_t& total) {
-    const int lane = __lane_id();
-    uint32_t incl = x;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    total = __shfl(incl, 63);
-    return incl - x;
 }
 
 // The tile rectangle of the Gaussian at depth position s (empty when culled,
@@ -86,7 +69,7 @@ row_counts_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ o
     const int yhi = wave_max(r.yhi);
     for (int ty = 0; ty < grid.gy; ++ty) {
         uint32_t tot = 0;
-        if (ty >= ylo && ty < yhi) tot = wave_sum((ty >= r.ylo && ty < r.yhi) ? w : 0u);
+        if (ty >= ylo && ty < yhi) tot = wave_total((ty >= r.ylo && ty < r.yhi) ? w : 0u);
         if (lane == 0) rowtot[uint64_t(ty) * nchunks + chunk] = tot;
     }
 }
@@ -97,6 +80,7 @@ __global__ void __launch_bounds__(256)
 row_setup_kernel(const uint32_t* __restrict__ rowscan, uint32_t nchunks, int gy,
                  uint32_t* __restrict__ row_start, uint32_t* __restrict__ first_slice) {
     __shared__ uint32_t carry;
+    __shared__ uint32_t wsum[4];
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int base = 0; base <= gy; base += 256) {
@@ -107,8 +91,6 @@ row_setup_kernel(const uint32_t* __restrict__ rowscan, uint32_t nchunks, int gy,
             row_start[ty] = s0;
             if (ty < gy) ns = (rowscan[uint64_t(ty + 1) * nchunks] - s0 + kSlice - 1) / kSlice;
         }
-        // block exclusive scan of ns
-        __shared__ uint32_t wsum[4];
         uint32_t tot;
         const uint32_t ex = wave_exclusive_sum(ns, tot);
         if (__lane_id() == 0) wsum[threadIdx.x >> 6] = tot;
@@ -142,26 +124,38 @@ emit_rows_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ or
     s_id[wv][lane] = id;
     const int ylo = wave_min(r.yhi > r.ylo ? r.ylo : grid.gy);
     const int yhi = wave_max(r.yhi);
-    for (int ty = ylo; ty < yhi; ++ty) {
-        uint32_t tot;
-        const uint32_t ex = wave_exclusive_sum((ty >= r.ylo && ty < r.yhi) ? w : 0u, tot);
-        if (tot == 0) continue;                        // wavefront-uniform
-        s_pref[wv][lane] = ex;
-        const uint64_t base = rowscan[uint64_t(ty) * nchunks + chunk];
-        for (uint32_t e = lane; e < tot; e += 64) {
-            int lo = 0, hi = 64;                       // largest lo with s_pref[lo] <= e
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_pref[wv][mid] <= e) lo = mid; else hi = mid;
+    for (int r0 = ylo; r0 < yhi; r0 += 64) {
+        // this chunk's segment [base, next) of rows r0 .. r0+63, one row per lane
+        uint32_t my_base = 0, my_next = 0;
+        if (r0 + lane < yhi) {
+            const uint64_t at = uint64_t(r0 + lane) * nchunks + chunk;
+            my_base = rowscan[at];
+            my_next = rowscan[at + 1];
+        }
+        const int r1 = min(r0 + 64, yhi);
+        for (int ty = r0; ty < r1; ++ty) {
+            uint32_t tot;
+            const uint32_t ex = wave_exclusive_sum((ty >= r.ylo && ty < r.yhi) ? w : 0u, tot);
+            if (tot == 0) continue;                    // wavefront-uniform
+            const uint32_t base = uint32_t(__builtin_amdgcn_readlane(int(my_base), ty - r0));
+            const uint32_t next = uint32_t(__builtin_amdgcn_readlane(int(my_next), ty - r0));
+            const uint32_t len = min(tot, next - base);    // never past this segment
+            s_pref[wv][lane] = ex;
+            for (uint32_t e = lane; e < len; e += 64) {
+                int lo = 0, hi = 64;                   // largest lo with s_pref[lo] <= e
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pref[wv][mid] <= e) lo = mid; else hi = mid;
+                }
+                cols[uint64_t(base) + e] = uint16_t(s_xlo[wv][lo] + int(e - s_pref[wv][lo]));
+                vals[uint64_t(base) + e] = s_id[wv][lo];
             }
-            cols[base + e] = uint16_t(s_xlo[wv][lo] + int(e - s_pref[wv][lo]));
-            vals[base + e] = s_id[wv][lo];
         }
     }
 }
 
 // Locate slice b: its row, index within the row and pair range.
-struct Slice { int ty; uint32_t k, ns, start, end; };
+struct Slice { int ty; uint32_t k, start, end; };
 
 __device__ __forceinline__ bool find_slice(uint32_t b, const uint32_t* first_slice,
                                            const uint32_t* row_start, int gy, Slice& s) {
@@ -173,138 +167,190 @@ __device__ __forceinline__ bool find_slice(uint32_t b, const uint32_t* first_sli
     }
     s.ty = lo;
     s.k = b - first_slice[lo];
-    s.ns = first_slice[lo + 1] - first_slice[lo];
     s.start = row_start[lo] + s.k * kSlice;
     s.end = min(s.start + uint32_t(kSlice), row_start[lo + 1]);
     return true;
 }
 
+// hist[b][tx]: pairs of slice b in column tx.
 __global__ void __launch_bounds__(256)
 col_hist_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict__ first_slice,
                 const uint32_t* __restrict__ row_start, Grid grid, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kMaxCols];
+    extern __shared__ uint32_t h[];
     Slice s;
     if (!find_slice(blockIdx.x, first_slice, row_start, grid.gy, s)) return;   // block-uniform
     for (int b = threadIdx.x; b < grid.gx; b += 256) h[b] = 0;
     __syncthreads();
     for (uint32_t i = s.start + threadIdx.x; i < s.end; i += 256) atomicAdd(&h[cols[i]], 1u);
     __syncthreads();
-    const uint64_t base = uint64_t(grid.gx) * first_slice[s.ty];
-    for (int b = threadIdx.x; b < grid.gx; b += 256) hist[base + uint64_t(b) * s.ns + s.k] = h[b];
+    const uint64_t base = uint64_t(blockIdx.x) * grid.gx;
+    for (int b = threadIdx.x; b < grid.gx; b += 256) hist[base + b] = h[b];
 }
 
-__global__ void __launch_bounds__(256)
+// Block-wide exclusive scan (blockDim.x = NT, one value per thread).
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t* s_w, uint32_t& total) {
+    const int wv = threadIdx.x >> 6;
+    uint32_t wt;
+    const uint32_t ex = wave_exclusive_sum(x, wt);
+    if (__lane_id() == 0) s_w[wv] = wt;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wv) before += s_w[w];
+        total += s_w[w];
+    }
+    __syncthreads();
+    return before + ex;
+}
+
+// One block per tile row: turns hist[b][tx] into the first output slot of
+// (slice b, column tx) -- order (row, column, slice) -- and writes the range
+// of every tile of the row.  The slices of a column are split into
+// segments of consecutive slices, one thread per (column, segment).
+__global__ void __launch_bounds__(1024)
+col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_slice,
+                const uint32_t* __restrict__ row_start, Grid grid, uint32_t* __restrict__ ranges) {
+    __shared__ uint32_t s_seg[1024];
+    __shared__ uint32_t s_start[kMaxCols];
+    __shared__ uint32_t s_w[16];
+    const int ty = blockIdx.x, t = threadIdx.x, gx = grid.gx;
+    const uint32_t s0 = first_slice[ty], ns = first_slice[ty + 1] - s0;
+    const int groups = max(1, 1024 / gx);
+    const int tx = t % gx, g = t / gx;
+    const bool act = g < groups;
+    const uint32_t seg = (ns + groups - 1) / groups;
+    const uint32_t k0 = act ? min(ns, uint32_t(g) * seg) : 0, k1 = act ? min(ns, k0 + seg) : 0;
+    uint32_t sum = 0;
+    for (uint32_t k = k0; k < k1; ++k) sum += hist[uint64_t(s0 + k) * gx + tx];
+    s_seg[t] = sum;
+    __syncthreads();
+    // column totals; segment sums -> exclusive prefixes over segments
+    uint32_t coltot = 0;
+    if (t < gx) {
+        for (int q = 0; q < groups; ++q) {
+            const uint32_t v = s_seg[q * gx + t];
+            s_seg[q * gx + t] = coltot;
+            coltot += v;
+        }
+    }
+    uint32_t all;
+    const uint32_t ex = block_exclusive_sum<1024>(t < gx ? coltot : 0u, s_w, all);
+    const uint32_t rs = row_start[ty];
+    if (t < gx) {
+        s_start[t] = rs + ex;
+        const uint64_t tile = uint64_t(ty) * gx + t;
+        ranges[2 * tile] = coltot > 0 ? rs + ex : 0u;
+        ranges[2 * tile + 1] = coltot > 0 ? rs + ex + coltot : 0u;
+    }
+    __syncthreads();
+    if (act) {
+        uint32_t run = s_start[tx] + s_seg[t];
+        for (uint32_t k = k0; k < k1; ++k) {
+            const uint64_t at = uint64_t(s0 + k) * gx + tx;
+            const uint32_t v = hist[at];
+            hist[at] = run;
+            run += v;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kScatterThreads)
 col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict__ vals,
                    const uint32_t* __restrict__ first_slice, const uint32_t* __restrict__ row_start,
                    const uint32_t* __restrict__ hist, Grid grid, int col_bits,
                    uint32_t* __restrict__ out) {
-    constexpr int W = 4, PER_WAVE = kSlice / W, ROUNDS = PER_WAVE / 64;
-    __shared__ uint32_t s_wcnt[W][kMaxCols];   // per wave, then wave prefix
-    __shared__ uint32_t s_start[kMaxCols];     // first local slot of each column
-    __shared__ uint32_t s_gbase[kMaxCols];     // first output slot of each column
-    __shared__ uint32_t s_val[kSlice];
-    __shared__ uint16_t s_col[kSlice];
-    __shared__ uint32_t s_part[256];
+    constexpr int W = kScatterWaves, R = kScatterRounds, PER_WAVE = 64 * R;
+    extern __shared__ uint32_t smem[];
+    const int gx = grid.gx;
+    uint32_t* s_val = smem;                              // [kSlice]
+    uint32_t* s_wcnt = s_val + kSlice;                   // [W][gx]: counts, then wave prefixes
+    uint32_t* s_start = s_wcnt + W * gx;                 // [gx]: first local slot of a column
+    uint32_t* s_gbase = s_start + gx;                    // [gx]: first output slot of a column
+    uint32_t* s_w = s_gbase + gx;                        // [W]
+    uint16_t* s_col = reinterpret_cast<uint16_t*>(s_w + W);   // [kSlice]
     Slice s;
     if (!find_slice(blockIdx.x, first_slice, row_start, grid.gy, s)) return;   // block-uniform
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
-    const int gx = grid.gx;
     const uint32_t count = s.end - s.start;
-    for (int b = tid; b < gx; b += 256)
-        for (int w = 0; w < W; ++w) s_wcnt[w][b] = 0;
-    __syncthreads();
-    uint32_t myv[ROUNDS], myrank[ROUNDS];
-    uint16_t mycol[ROUNDS];
-    // ranks within the wavefront's 1024 consecutive pairs, in input order
-    for (int r = 0; r < ROUNDS; ++r) {
+    for (int b = tid; b < W * gx; b += kScatterThreads) s_wcnt[b] = 0;
+    // all loads first: R independent pairs per lane in flight
+    uint32_t myv[R];
+    uint32_t mycol[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         const uint32_t idx = uint32_t(wv * PER_WAVE + r * 64 + lane);
         const bool valid = idx < count;
-        const uint32_t c = valid ? cols[s.start + idx] : 0u;
+        mycol[r] = valid ? uint32_t(cols[s.start + idx]) : 0u;
         myv[r] = valid ? vals[s.start + idx] : 0u;
-        mycol[r] = uint16_t(c);
+    }
+    __syncthreads();
+    // ranks within the wavefront's PER_WAVE consecutive pairs, in input order
+    uint32_t myrank[R];
+    uint32_t* wc = s_wcnt + wv * gx;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t idx = uint32_t(wv * PER_WAVE + r * 64 + lane);
+        const bool valid = idx < count;
+        const uint32_t c = mycol[r];
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < col_bits; ++b) {
             const bool bit = (c >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t before = valid ? s_wcnt[wv][c] : 0u;
-        myrank[r] = before + uint32_t(__popcll(peers & lanemask_lt()));
-        if (valid && (peers & lanemask_lt()) == 0) s_wcnt[wv][c] = before + uint32_t(__popcll(peers));
+        const uint32_t below = uint32_t(__popcll(peers & lanemask_lt()));
+        const uint32_t before = valid ? wc[c] : 0u;
+        myrank[r] = before + below;
+        if (valid && below == 0) wc[c] = before + uint32_t(__popcll(peers));
     }
     __syncthreads();
-    // per column: total, wave prefixes, and the local start (block scan over columns)
-    constexpr int CPT = kMaxCols / 256;        // columns per thread
-    uint32_t tot[CPT], run = 0;
-    for (int j = 0; j < CPT; ++j) {
-        const int b = tid * CPT + j;
-        uint32_t t = 0;
-        if (b < gx) {
+    // per column: total over waves (wave counts become wave prefixes), then
+    // the columns' local starts by a block scan (two columns per thread)
+    uint32_t tot2[2] = {0u, 0u};
+    for (int j = 0; j < 2; ++j) {
+        const int c = 2 * tid + j;
+        if (c < gx) {
+            uint32_t t = 0;
             for (int w = 0; w < W; ++w) {
-                const uint32_t c = s_wcnt[w][b];
-                s_wcnt[w][b] = t;
-                t += c;
+                const uint32_t v = s_wcnt[w * gx + c];
+                s_wcnt[w * gx + c] = t;
+                t += v;
             }
+            tot2[j] = t;
         }
-        tot[j] = t;
-        run += t;
     }
-    s_part[tid] = run;
-    __syncthreads();
-    if (wv == 0) {                              // scan the 256 partial sums with one wavefront
-        uint32_t v[4], sum = 0;
-        for (int j = 0; j < 4; ++j) { v[j] = s_part[lane * 4 + j]; sum += v[j]; }
-        uint32_t total;
-        uint32_t ex = wave_exclusive_sum(sum, total);
-        for (int j = 0; j < 4; ++j) { s_part[lane * 4 + j] = ex; ex += v[j]; }
-    }
-    __syncthreads();
-    {
-        uint32_t at = s_part[tid];
-        const uint64_t hb = uint64_t(gx) * first_slice[s.ty];
-        for (int j = 0; j < CPT; ++j) {
-            const int b = tid * CPT + j;
-            if (b < gx) {
-                s_start[b] = at;
-                s_gbase[b] = hist[hb + uint64_t(b) * s.ns + s.k];
-            }
-            at += tot[j];
+    uint32_t all;
+    const uint32_t ex = block_exclusive_sum<kScatterThreads>(tot2[0] + tot2[1], s_w, all);
+    for (int j = 0; j < 2; ++j) {
+        const int c = 2 * tid + j;
+        if (c < gx) {
+            s_start[c] = ex + (j ? tot2[0] : 0u);
+            s_gbase[c] = hist[uint64_t(blockIdx.x) * gx + c];
         }
     }
     __syncthreads();
-    for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         const uint32_t idx = uint32_t(wv * PER_WAVE + r * 64 + lane);
         if (idx < count) {
             const uint32_t c = mycol[r];
-            const uint32_t pos = s_start[c] + s_wcnt[wv][c] + myrank[r];
+            const uint32_t pos = s_start[c] + s_wcnt[wv * gx + c] + myrank[r];
             s_val[pos] = myv[r];
             s_col[pos] = uint16_t(c);
         }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < count; i += 256) {
+    for (uint32_t i = tid; i < count; i += kScatterThreads) {
         const uint32_t c = s_col[i];
         out[s_gbase[c] + (i - s_start[c])] = s_val[i];
     }
 }
 
-__global__ void tile_ranges_kernel(const uint32_t* __restrict__ hist,
-                                   const uint32_t* __restrict__ first_slice,
-                                   const uint32_t* __restrict__ row_start, Grid grid,
-                                   uint32_t* __restrict__ ranges) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= grid.num_tiles()) return;
-    const int ty = int(t / grid.gx), tx = int(t % grid.gx);
-    const uint32_t ns = first_slice[ty + 1] - first_slice[ty];
-    uint32_t a = 0, b = 0;
-    if (ns > 0) {
-        const uint64_t hb = uint64_t(grid.gx) * first_slice[ty];
-        a = hist[hb + uint64_t(tx) * ns];
-        b = tx + 1 < grid.gx ? hist[hb + uint64_t(tx + 1) * ns] : row_start[ty + 1];
-    }
-    if (a == b) a = b = 0;
-    ranges[2 * t] = a;
-    ranges[2 * t + 1] = b;
+size_t scatter_lds_bytes(int gx) {
+    return size_t(kSlice) * 4 + size_t(kScatterWaves * gx + 2 * gx + kScatterWaves) * 4 +
+           size_t(kSlice) * 2;
 }
 
 }  // namespace
@@ -346,40 +392,32 @@ hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order,
     return hipGetLastError();
 }
 
-hipError_t launch_col_hist(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
+hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
                            hipStream_t s) {
-    if (slices == 0) return hipSuccess;
-    col_hist_kernel<<<dim3(unsigned(slices)), dim3(256), 0, s>>>(
-        reinterpret_cast<const uint16_t*>(ws + L.row_cols),
-        reinterpret_cast<const uint32_t*>(ws + L.first_slice),
-        reinterpret_cast<const uint32_t*>(ws + L.row_start), grid,
-        reinterpret_cast<uint32_t*>(ws + L.col_hist));
-    return hipGetLastError();
-}
-
-hipError_t launch_col_scatter(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
-                              hipStream_t s) {
-    if (slices == 0) return hipSuccess;
-    int bits = 1;
-    while ((1 << bits) < grid.gx) ++bits;
-    col_scatter_kernel<<<dim3(unsigned(slices)), dim3(256), 0, s>>>(
-        reinterpret_cast<const uint16_t*>(ws + L.row_cols),
-        reinterpret_cast<const uint32_t*>(ws + L.row_vals),
-        reinterpret_cast<const uint32_t*>(ws + L.first_slice),
-        reinterpret_cast<const uint32_t*>(ws + L.row_start),
-        reinterpret_cast<const uint32_t*>(ws + L.col_hist), grid, bits,
-        reinterpret_cast<uint32_t*>(ws + L.pair_vals));
-    return hipGetLastError();
-}
-
-hipError_t launch_tile_ranges(uint8_t* ws, const Layout& L, const Grid& grid, hipStream_t s) {
-    const int64_t nt = grid.num_tiles();
-    if (nt == 0) return hipSuccess;
-    tile_ranges_kernel<<<dim3(unsigned((nt + 255) / 256)), dim3(256), 0, s>>>(
-        reinterpret_cast<const uint32_t*>(ws + L.col_hist),
-        reinterpret_cast<const uint32_t*>(ws + L.first_slice),
-        reinterpret_cast<const uint32_t*>(ws + L.row_start), grid,
-        reinterpret_cast<uint32_t*>(ws + L.ranges));
+    const auto* fs = reinterpret_cast<const uint32_t*>(ws + L.first_slice);
+    const auto* rs = reinterpret_cast<const uint32_t*>(ws + L.row_start);
+    auto* hist = reinterpret_cast<uint32_t*>(ws + L.col_hist);
+    auto* ranges = reinterpret_cast<uint32_t*>(ws + L.ranges);
+    if (slices > 0) {
+        col_hist_kernel<<<dim3(unsigned(slices)), dim3(256), size_t(grid.gx) * 4, s>>>(
+            reinterpret_cast<const uint16_t*>(ws + L.row_cols), fs, rs, grid, hist);
+    }
+    col_scan_kernel<<<dim3(unsigned(grid.gy)), dim3(1024), 0, s>>>(hist, fs, rs, grid, ranges);
+    if (slices > 0) {
+        int bits = 1;
+        while ((1 << bits) < grid.gx) ++bits;
+        const size_t lds = scatter_lds_bytes(grid.gx);
+        if (lds > 65536) {
+            // wide tile grids need more than the default 64 KiB of LDS per block
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&col_scatter_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+            if (e != hipSuccess) return e;
+        }
+        col_scatter_kernel<<<dim3(unsigned(slices)), dim3(kScatterThreads), lds, s>>>(
+            reinterpret_cast<const uint16_t*>(ws + L.row_cols),
+            reinterpret_cast<const uint32_t*>(ws + L.row_vals), fs, rs, hist, grid, bits,
+            reinterpret_cast<uint32_t*>(ws + L.pair_vals));
+    }
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 // binning: pairs per column-sort slice, and the widest tile grid supported
-constexpr int kSlice = 4096;
+constexpr int kSlice = 8192;
 constexpr int kMaxCols = 1024;
 
 enum RecordFlags : uint32_t {
@@ -101,18 +101,22 @@ hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid&
                             hipStream_t s);
 hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
                             const Grid& grid, hipStream_t s);
-hipError_t launch_col_hist(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
+// Stable counting sort of every row bucket by column, and the tile ranges.
+hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
                            hipStream_t s);
-hipError_t launch_col_scatter(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
-                              hipStream_t s);
-hipError_t launch_tile_ranges(uint8_t* ws, const Layout& L, const Grid& grid, hipStream_t s);
 
-hipError_t launch_raster_fwd(const Grid& grid, const float bg[3], const uint8_t* ws,
-                             const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
-                             float* image,
+// Launch knobs of the raster kernels (results do not depend on them):
+// ppt = pixels per thread (1, 2 or 4), order = workgroup-to-tile mapping
+// (0 natural, 1 XCD-interleaved 2x2 quads).
+struct RasterTuning { int ppt = 1, order = 0; };
+RasterTuning raster_tuning();     // defaults, overridable by TGS_RASTER_PPT / TGS_TILE_ORDER
+
+hipError_t launch_raster_fwd(const Grid& grid, const RasterTuning& tune, const float bg[3],
+                             const uint8_t* ws, const Layout& L, const uint32_t* pair_vals,
+                             uint32_t pair_count, float* image,
                              float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
                              hipStream_t s);
-hipError_t launch_raster_bwd(const Grid& grid, const float bg[3], const uint8_t* ws,
+hipError_t launch_raster_bwd(const Grid& grid, const RasterTuning& tune, const uint8_t* ws,
                              const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
                              const float* image,
                              const float* dL_dimage, float* grad2d, hipStream_t s);

@@ -1,12 +1,13 @@
 // Dilated compositing, forward and backward (stages (c) and (d1)), and the
 // L1 loss gradient.
 //
-// One workgroup per tile of the DOWNSAMPLED image, one thread per rendered
-// pixel (Sec. 4.1: pairs live in the downsampled grid, blending happens at
-// the full-resolution position d i + o of each downsampled pixel, so no
-// thread is masked off for an unrendered pixel).  The tile's list is staged
-// through LDS in batches of up to 256 splat records; every thread then walks
-// the batch front to back (Sec. 3 Eq. 2).
+// One workgroup per tile of the DOWNSAMPLED image (Sec. 4.1: pairs live in
+// the downsampled grid; each downsampled pixel is blended at its
+// full-resolution position d i + o, so no thread is spent on an unrendered
+// pixel).  Threads own 1, 2 or 4 pixels of the tile (launch knob): with more
+// pixels per thread the splat records staged in LDS, and the per-splat
+// gradient reduction of the backward, are shared by several pixels.  Every
+// pixel walks its tile's list front to back (Sec. 3 Eq. 2).
 //
 // The backward replays the forward walk in the same order with the same
 // arithmetic (one shared inline routine), so it takes bit-identical skip and
@@ -21,6 +22,7 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kXcds = 8;
 
 // alpha = min(0.99, o exp(p)), p = -1/2 (A dx^2 + C dy^2) - B dx dy; false if
 // the entry is skipped (p > 0 or alpha < 1/255).  ga = (u, v, A, B),
@@ -37,116 +39,212 @@ __device__ __forceinline__ bool splat_alpha(const float4 ga, const float4 gb, fl
     return alpha >= kAlphaMin;
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+// Tile of workgroup b.  order 0: tile = b.  order 1: the tile grid is cut
+// into 2x2 quads; quad q goes to XCD q mod 8 (workgroup b runs on XCD b mod 8)
+// and the 4 tiles of a quad are consecutive workgroups of that XCD, so they
+// run together and share splat records in its L2, while neighbouring quads
+// spread the expensive parts of the image over all XCDs.
+__device__ __forceinline__ int64_t tile_of_block(uint32_t b, const Grid& g, int order) {
+    if (order == 0) return b;
+    const int qx_n = (g.gx + 1) / 2;
+    const uint32_t xcd = b % kXcds, local = b / kXcds;
+    const int64_t q = int64_t(local / 4) * kXcds + xcd;
+    const int r = int(local % 4);
+    const int qy = int(q / qx_n), qx = int(q % qx_n);
+    const int tx = 2 * qx + (r & 1), ty = 2 * qy + (r >> 1);
+    if (tx >= g.gx || ty >= g.gy) return g.num_tiles();          // no tile: exit
+    return int64_t(ty) * g.gx + tx;
 }
 
-template <int T>
-__global__ void __launch_bounds__(T * T)
-raster_fwd_kernel(Grid grid, float bg0, float bg1, float bg2, const float4* __restrict__ rec,
-                  const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
-                  uint32_t pair_count, float* __restrict__ image, float* __restrict__ t_final,
+__host__ inline uint32_t blocks_for_tiles(const Grid& g, int order) {
+    if (order == 0) return uint32_t(g.num_tiles());
+    const int64_t quads = int64_t((g.gx + 1) / 2) * ((g.gy + 1) / 2);
+    return uint32_t(((quads + kXcds - 1) / kXcds) * kXcds * 4);
+}
+
+// Launch shape: a T x T tile is covered by (T/PX) x (T/PY) threads owning
+// PX x PY pixels each.
+template <int T, int PX_, int PY_>
+struct Shape {
+    static constexpr int PX = PX_, PY = PY_, NP = PX * PY;
+    static constexpr int TX = T / PX, TY = T / PY, NT = TX * TY;   // threads
+    static constexpr int BATCH = NT < 256 ? NT : 256;
+};
+
+// Sums of 9 per-lane values over the wavefront.  Eight of them are reduced
+// with a transposing butterfly (each exchange halves the values a lane keeps),
+// so lane 8c (c = 0..7) ends with the total of value c; value 8 is reduced
+// plainly and lane 1 keeps it.  Returns the value this lane owns and its
+// index (or -1).
+__device__ __forceinline__ float wave_sum9(const float* v, int& comp) {
+    const int lane = __lane_id();
+    const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+    float w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float send = h32 ? v[k] : v[k + 4];
+        const float keep = h32 ? v[k + 4] : v[k];
+        w[k] = keep + __shfl_xor(send, 32);
+    }
+    float x[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float send = h16 ? w[k] : w[k + 2];
+        const float keep = h16 ? w[k + 2] : w[k];
+        x[k] = keep + __shfl_xor(send, 16);
+    }
+    float y;
+    {
+        const float send = h8 ? x[0] : x[1];
+        const float keep = h8 ? x[1] : x[0];
+        y = keep + __shfl_xor(send, 8);
+    }
+    y += __shfl_xor(y, 4);
+    y += __shfl_xor(y, 2);
+    y += __shfl_xor(y, 1);
+    float z = v[8];
+    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
+    comp = -1;
+    if ((lane & 7) == 0) comp = (h32 ? 4 : 0) + (h16 ? 2 : 0) + (h8 ? 1 : 0);
+    if (lane == 1) {
+        comp = 8;
+        y = z;
+    }
+    return y;
+}
+
+template <int T, int PX, int PY>
+__global__ void __launch_bounds__((Shape<T, PX, PY>::NT))
+raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
+                  const float4* __restrict__ rec, const uint32_t* __restrict__ ranges,
+                  const uint32_t* __restrict__ vals, uint32_t pair_count,
+                  float* __restrict__ image, float* __restrict__ t_final,
                   uint32_t* __restrict__ last_contrib, uint32_t* __restrict__ n_eval) {
-    constexpr int NT = T * T;
-    constexpr int BATCH = NT < 256 ? NT : 256;
-    __shared__ float4 s_a[BATCH], s_b[BATCH];
-    __shared__ float s_c[BATCH];
+    using S = Shape<T, PX, PY>;
+    __shared__ float4 s_a[S::BATCH], s_b[S::BATCH];
+    __shared__ float s_c[S::BATCH];
+    const int64_t tile = tile_of_block(blockIdx.x, grid, order);
+    if (tile >= grid.num_tiles()) return;                      // block-uniform
     const int tid = threadIdx.x;
-    const uint32_t tile = blockIdx.x;
-    const int tx = int(tile % uint32_t(grid.gx)), ty = int(tile / uint32_t(grid.gx));
-    const int i = tx * T + (tid % T), j = ty * T + (tid / T);
-    const bool inside = i < grid.w_ds && j < grid.h_ds;
-    const float X = float(grid.stride * i + grid.off_x);
-    const float Y = float(grid.stride * j + grid.off_y);
+    const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
+    const int i0 = tx * T + (tid % S::TX) * S::PX, j0 = ty * T + (tid / S::TX) * S::PY;
     // ranges come from the sort of this state; clamping them to the pair
     // count keeps every list read inside the pair buffer
     const uint32_t end = min(ranges[2 * tile + 1], pair_count);
     const uint32_t start = min(ranges[2 * tile], end);
-    bool done = !inside;
-    float Tr = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-    uint32_t last = 0, neval = end - start;
-    for (uint32_t base = start; base < end; base += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
-        if (tid < BATCH && base + tid < end) {
+    float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
+    uint32_t last[S::NP], neval[S::NP];
+    bool done[S::NP];
+    bool alive = false;
+#pragma unroll
+    for (int k = 0; k < S::NP; ++k) {
+        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
+        done[k] = !(i < grid.w_ds && j < grid.h_ds);
+        alive |= !done[k];
+        X[k] = float(grid.stride * i + grid.off_x);
+        Y[k] = float(grid.stride * j + grid.off_y);
+        Tr[k] = 1.0f;
+        c0[k] = c1[k] = c2[k] = 0.0f;
+        last[k] = 0;
+        neval[k] = end - start;
+    }
+    for (uint32_t base = start; base < end; base += S::BATCH) {
+        if (__syncthreads_count(alive) == 0) break;
+        if (tid < S::BATCH && base + tid < end) {
             const uint64_t id = vals[base + tid];
             s_a[tid] = rec[3 * id];
             s_b[tid] = rec[3 * id + 1];
             s_c[tid] = rec[3 * id + 2].x;
         }
         __syncthreads();
-        const int cnt = min(BATCH, int(end - base));
-        for (int e = 0; e < cnt && !done; ++e) {
+        const int cnt = min(S::BATCH, int(end - base));
+        for (int e = 0; e < cnt && alive; ++e) {
             const float4 a = s_a[e], b = s_b[e];
-            float dx, dy, G, alpha;
-            if (!splat_alpha(a, b, X, Y, dx, dy, G, alpha)) continue;
-            const float Tn = Tr * (1.0f - alpha);
-            if (Tn < kTMin) {
-                done = true;
-                neval = base - start + uint32_t(e) + 1;
-                break;
+            const float bb = s_c[e];
+            alive = false;
+#pragma unroll
+            for (int k = 0; k < S::NP; ++k) {
+                if (done[k]) continue;
+                float dx, dy, G, alpha;
+                if (splat_alpha(a, b, X[k], Y[k], dx, dy, G, alpha)) {
+                    const float Tn = Tr[k] * (1.0f - alpha);
+                    if (Tn < kTMin) {
+                        done[k] = true;
+                        neval[k] = base - start + uint32_t(e) + 1;
+                        continue;
+                    }
+                    const float w = alpha * Tr[k];
+                    c0[k] += b.z * w;
+                    c1[k] += b.w * w;
+                    c2[k] += bb * w;
+                    Tr[k] = Tn;
+                    last[k] = base - start + uint32_t(e) + 1;
+                }
+                alive = true;
             }
-            const float w = alpha * Tr;
-            c0 += b.z * w;
-            c1 += b.w * w;
-            c2 += s_c[e] * w;
-            Tr = Tn;
-            last = base - start + uint32_t(e) + 1;
         }
     }
-    if (inside) {
-        const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
+    const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
+#pragma unroll
+    for (int k = 0; k < S::NP; ++k) {
+        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
+        if (!(i < grid.w_ds && j < grid.h_ds)) continue;
         const uint64_t p = uint64_t(j) * grid.w_ds + i;
-        image[p] = c0 + Tr * bg0;
-        image[pix + p] = c1 + Tr * bg1;
-        image[2 * pix + p] = c2 + Tr * bg2;
-        if (t_final) t_final[p] = Tr;
-        if (last_contrib) last_contrib[p] = last;
-        if (n_eval) n_eval[p] = neval;
+        image[p] = c0[k] + Tr[k] * bg0;
+        image[pix + p] = c1[k] + Tr[k] * bg1;
+        image[2 * pix + p] = c2[k] + Tr[k] * bg2;
+        if (t_final) t_final[p] = Tr[k];
+        if (last_contrib) last_contrib[p] = last[k];
+        if (n_eval) n_eval[p] = neval[k];
     }
 }
 
-template <int T>
-__global__ void __launch_bounds__(T * T)
-raster_bwd_kernel(Grid grid, const float4* __restrict__ rec, const uint32_t* __restrict__ ranges,
-                  const uint32_t* __restrict__ vals, uint32_t pair_count,
-                  const float* __restrict__ image, const float* __restrict__ dL_dimage,
-                  float* __restrict__ grad2d) {
-    constexpr int NT = T * T;
-    constexpr int BATCH = NT < 256 ? NT : 256;
-    __shared__ float4 s_a[BATCH], s_b[BATCH];
-    __shared__ float s_c[BATCH];
-    __shared__ uint32_t s_id[BATCH];
-    __shared__ float s_g[BATCH * kGrad2d];
+template <int T, int PX, int PY>
+__global__ void __launch_bounds__((Shape<T, PX, PY>::NT))
+raster_bwd_kernel(Grid grid, int order, const float4* __restrict__ rec,
+                  const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+                  uint32_t pair_count, const float* __restrict__ image,
+                  const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
+    using S = Shape<T, PX, PY>;
+    __shared__ float4 s_a[S::BATCH], s_b[S::BATCH];
+    __shared__ float s_c[S::BATCH];
+    __shared__ uint32_t s_id[S::BATCH];
+    const int64_t tile = tile_of_block(blockIdx.x, grid, order);
+    if (tile >= grid.num_tiles()) return;                      // block-uniform
     const int tid = threadIdx.x;
-    const uint32_t tile = blockIdx.x;
-    const int tx = int(tile % uint32_t(grid.gx)), ty = int(tile / uint32_t(grid.gx));
-    const int i = tx * T + (tid % T), j = ty * T + (tid / T);
-    const bool inside = i < grid.w_ds && j < grid.h_ds;
-    const float X = float(grid.stride * i + grid.off_x);
-    const float Y = float(grid.stride * j + grid.off_y);
-    // ranges come from the sort of this state; clamping them to the pair
-    // count keeps every list read inside the pair buffer
+    const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
+    const int i0 = tx * T + (tid % S::TX) * S::PX, j0 = ty * T + (tid / S::TX) * S::PY;
     const uint32_t end = min(ranges[2 * tile + 1], pair_count);
     const uint32_t start = min(ranges[2 * tile], end);
-    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, im0 = 0.0f, im1 = 0.0f, im2 = 0.0f;
-    if (inside) {
-        const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
-        const uint64_t p = uint64_t(j) * grid.w_ds + i;
-        g0 = dL_dimage[p];
-        g1 = dL_dimage[pix + p];
-        g2 = dL_dimage[2 * pix + p];
-        im0 = image[p];
-        im1 = image[pix + p];
-        im2 = image[2 * pix + p];
+    const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
+    float X[S::NP], Y[S::NP], Tr[S::NP], p0[S::NP], p1[S::NP], p2[S::NP];
+    float g0[S::NP], g1[S::NP], g2[S::NP], im0[S::NP], im1[S::NP], im2[S::NP];
+    bool done[S::NP];
+    bool alive = false;
+#pragma unroll
+    for (int k = 0; k < S::NP; ++k) {
+        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
+        const bool in = i < grid.w_ds && j < grid.h_ds;
+        done[k] = !in;
+        alive |= in;
+        X[k] = float(grid.stride * i + grid.off_x);
+        Y[k] = float(grid.stride * j + grid.off_y);
+        Tr[k] = 1.0f;
+        p0[k] = p1[k] = p2[k] = 0.0f;
+        g0[k] = g1[k] = g2[k] = im0[k] = im1[k] = im2[k] = 0.0f;
+        if (in) {
+            const uint64_t p = uint64_t(j) * grid.w_ds + i;
+            g0[k] = dL_dimage[p];
+            g1[k] = dL_dimage[pix + p];
+            g2[k] = dL_dimage[2 * pix + p];
+            im0[k] = image[p];
+            im1[k] = image[pix + p];
+            im2[k] = image[2 * pix + p];
+        }
     }
-    for (int k = tid; k < BATCH * kGrad2d; k += NT) s_g[k] = 0.0f;
-    bool done = !inside;
-    float Tr = 1.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f;
-    const int lane = tid & 63;
-    for (uint32_t base = start; base < end; base += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
-        if (tid < BATCH && base + tid < end) {
+    for (uint32_t base = start; base < end; base += S::BATCH) {
+        if (__syncthreads_count(alive) == 0) break;
+        if (tid < S::BATCH && base + tid < end) {
             const uint32_t id = vals[base + tid];
             s_id[tid] = id;
             s_a[tid] = rec[3 * uint64_t(id)];
@@ -154,58 +252,60 @@ raster_bwd_kernel(Grid grid, const float4* __restrict__ rec, const uint32_t* __r
             s_c[tid] = rec[3 * uint64_t(id) + 2].x;
         }
         __syncthreads();
-        const int cnt = min(BATCH, int(end - base));
+        const int cnt = min(S::BATCH, int(end - base));
         for (int e = 0; e < cnt; ++e) {
-            if (__ballot(!done) == 0) break;      // the whole wavefront has stopped
+            if (__ballot(alive) == 0) break;          // the whole wavefront has stopped
             float gv[kGrad2d];
+#pragma unroll
             for (int c = 0; c < kGrad2d; ++c) gv[c] = 0.0f;
             bool contrib = false;
-            if (!done) {
+            if (alive) {
                 const float4 a = s_a[e], b = s_b[e];
-                float dx, dy, G, alpha;
-                if (splat_alpha(a, b, X, Y, dx, dy, G, alpha)) {
-                    const float Tn = Tr * (1.0f - alpha);
-                    if (Tn < kTMin) {
-                        done = true;
-                    } else {
+                const float bb = s_c[e];
+                alive = false;
+#pragma unroll
+                for (int k = 0; k < S::NP; ++k) {
+                    if (done[k]) continue;
+                    float dx, dy, G, alpha;
+                    if (splat_alpha(a, b, X[k], Y[k], dx, dy, G, alpha)) {
+                        const float Tn = Tr[k] * (1.0f - alpha);
+                        if (Tn < kTMin) {
+                            done[k] = true;
+                            continue;
+                        }
                         contrib = true;
-                        const float bb = s_c[e];
-                        const float w = alpha * Tr;
-                        p0 += b.z * w;
-                        p1 += b.w * w;
-                        p2 += bb * w;
-                        gv[6] = w * g0;
-                        gv[7] = w * g1;
-                        gv[8] = w * g2;
+                        const float w = alpha * Tr[k];
+                        p0[k] += b.z * w;
+                        p1[k] += b.w * w;
+                        p2[k] += bb * w;
+                        gv[6] += w * g0[k];
+                        gv[7] += w * g1[k];
+                        gv[8] += w * g2[k];
                         const float inv = 1.0f / (1.0f - alpha);
-                        const float dal = g0 * (b.z * Tr - (im0 - p0) * inv) +
-                                          g1 * (b.w * Tr - (im1 - p1) * inv) +
-                                          g2 * (bb * Tr - (im2 - p2) * inv);
+                        const float dal = g0[k] * (b.z * Tr[k] - (im0[k] - p0[k]) * inv) +
+                                          g1[k] * (b.w * Tr[k] - (im1[k] - p1[k]) * inv) +
+                                          g2[k] * (bb * Tr[k] - (im2[k] - p2[k]) * inv);
                         // no gradient through the 0.99 clamp
-                        const bool clamped = b.y * G > kAlphaMax;
-                        const float dp = clamped ? 0.0f : alpha * dal;
-                        gv[5] = clamped ? 0.0f : G * dal;
-                        gv[0] = -dp * (a.z * dx + a.w * dy);
-                        gv[1] = -dp * (b.x * dy + a.w * dx);
-                        gv[2] = -0.5f * dp * dx * dx;
-                        gv[3] = -dp * dx * dy;
-                        gv[4] = -0.5f * dp * dy * dy;
-                        Tr = Tn;
+                        if (!(b.y * G > kAlphaMax)) {
+                            const float dp = alpha * dal;
+                            gv[5] += G * dal;
+                            gv[0] -= dp * (a.z * dx + a.w * dy);
+                            gv[1] -= dp * (b.x * dy + a.w * dx);
+                            gv[2] -= 0.5f * dp * dx * dx;
+                            gv[3] -= dp * dx * dy;
+                            gv[4] -= 0.5f * dp * dy * dy;
+                        }
+                        Tr[k] = Tn;
                     }
+                    alive = true;
                 }
             }
             if (__ballot(contrib) != 0) {
-                for (int c = 0; c < kGrad2d; ++c) {
-                    const float s = wave_sum(gv[c]);
-                    if (lane == 0) atomicAdd(&s_g[e * kGrad2d + c], s);
-                }
+                int comp;
+                const float s = wave_sum9(gv, comp);
+                if (comp >= 0 && s != 0.0f)
+                    atomicAdd(&grad2d[uint64_t(s_id[e]) * kGrad2d + comp], s);
             }
-        }
-        __syncthreads();
-        for (int k = tid; k < cnt * kGrad2d; k += NT) {
-            const float v = s_g[k];
-            if (v != 0.0f) atomicAdd(&grad2d[uint64_t(s_id[k / kGrad2d]) * kGrad2d + k % kGrad2d], v);
-            s_g[k] = 0.0f;
         }
     }
 }
@@ -238,54 +338,61 @@ l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restri
     }
 }
 
+template <int T, int PX, int PY>
+void fwd_launch(const Grid& grid, int order, const float bg[3], const float4* rec,
+                const uint32_t* ranges, const uint32_t* vals, uint32_t pc, float* image,
+                float* t_final, uint32_t* last, uint32_t* neval, hipStream_t s) {
+    raster_fwd_kernel<T, PX, PY><<<dim3(blocks_for_tiles(grid, order)),
+                                   dim3(Shape<T, PX, PY>::NT), 0, s>>>(
+        grid, order, bg[0], bg[1], bg[2], rec, ranges, vals, pc, image, t_final, last, neval);
+}
+
+template <int T, int PX, int PY>
+void bwd_launch(const Grid& grid, int order, const float4* rec, const uint32_t* ranges,
+                const uint32_t* vals, uint32_t pc, const float* image, const float* dL,
+                float* g2d, hipStream_t s) {
+    raster_bwd_kernel<T, PX, PY><<<dim3(blocks_for_tiles(grid, order)),
+                                   dim3(Shape<T, PX, PY>::NT), 0, s>>>(
+        grid, order, rec, ranges, vals, pc, image, dL, g2d);
+}
+
 }  // namespace
 
-hipError_t launch_raster_fwd(const Grid& grid, const float bg[3], const uint8_t* ws,
-                             const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
-                             float* image,
-                             float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
-                             hipStream_t s) {
+hipError_t launch_raster_fwd(const Grid& grid, const RasterTuning& tune, const float bg[3],
+                             const uint8_t* ws, const Layout& L, const uint32_t* pair_vals,
+                             uint32_t pair_count, float* image, float* t_final,
+                             uint32_t* last_contrib, uint32_t* n_eval, hipStream_t s) {
     const auto* rec = reinterpret_cast<const float4*>(ws + L.records);
     const auto* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-    const dim3 nb(unsigned(grid.num_tiles()));
     if (grid.num_tiles() == 0) return hipSuccess;
-    switch (grid.tile) {
-        case 8:
-            raster_fwd_kernel<8><<<nb, dim3(64), 0, s>>>(grid, bg[0], bg[1], bg[2], rec, ranges,
-                                                         pair_vals, pair_count, image, t_final, last_contrib, n_eval);
-            break;
-        case 32:
-            raster_fwd_kernel<32><<<nb, dim3(1024), 0, s>>>(grid, bg[0], bg[1], bg[2], rec, ranges,
-                                                            pair_vals, pair_count, image, t_final, last_contrib, n_eval);
-            break;
-        default:
-            raster_fwd_kernel<16><<<nb, dim3(256), 0, s>>>(grid, bg[0], bg[1], bg[2], rec, ranges,
-                                                           pair_vals, pair_count, image, t_final, last_contrib, n_eval);
-            break;
-    }
+    const int o = tune.order;
+#define TGS_FWD(T, PX, PY) fwd_launch<T, PX, PY>(grid, o, bg, rec, ranges, pair_vals, pair_count, \
+                                                image, t_final, last_contrib, n_eval, s)
+    if (grid.tile == 8) TGS_FWD(8, 1, 1);
+    else if (grid.tile == 32) { if (tune.ppt == 2) TGS_FWD(32, 2, 1); else TGS_FWD(32, 2, 2); }
+    else if (tune.ppt == 1) TGS_FWD(16, 1, 1);
+    else if (tune.ppt == 2) TGS_FWD(16, 2, 1);
+    else TGS_FWD(16, 2, 2);
+#undef TGS_FWD
     return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd(const Grid& grid, const float bg[3], const uint8_t* ws,
+hipError_t launch_raster_bwd(const Grid& grid, const RasterTuning& tune, const uint8_t* ws,
                              const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
-                             const float* image,
-                             const float* dL_dimage, float* grad2d, hipStream_t s) {
-    (void)bg;   // the background enters through image = C + T_final bg
+                             const float* image, const float* dL_dimage, float* grad2d,
+                             hipStream_t s) {
     const auto* rec = reinterpret_cast<const float4*>(ws + L.records);
     const auto* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-    const dim3 nb(unsigned(grid.num_tiles()));
     if (grid.num_tiles() == 0) return hipSuccess;
-    switch (grid.tile) {
-        case 8:
-            raster_bwd_kernel<8><<<nb, dim3(64), 0, s>>>(grid, rec, ranges, pair_vals, pair_count, image, dL_dimage, grad2d);
-            break;
-        case 32:
-            raster_bwd_kernel<32><<<nb, dim3(1024), 0, s>>>(grid, rec, ranges, pair_vals, pair_count, image, dL_dimage, grad2d);
-            break;
-        default:
-            raster_bwd_kernel<16><<<nb, dim3(256), 0, s>>>(grid, rec, ranges, pair_vals, pair_count, image, dL_dimage, grad2d);
-            break;
-    }
+    const int o = tune.order;
+#define TGS_BWD(T, PX, PY) bwd_launch<T, PX, PY>(grid, o, rec, ranges, pair_vals, pair_count, \
+                                                image, dL_dimage, grad2d, s)
+    if (grid.tile == 8) TGS_BWD(8, 1, 1);
+    else if (grid.tile == 32) { if (tune.ppt == 2) TGS_BWD(32, 2, 1); else TGS_BWD(32, 2, 2); }
+    else if (tune.ppt == 1) TGS_BWD(16, 1, 1);
+    else if (tune.ppt == 2) TGS_BWD(16, 2, 1);
+    else TGS_BWD(16, 2, 2);
+#undef TGS_BWD
     return hipGetLastError();
 }
 
