@@ -14,6 +14,7 @@
 // stop decisions and needs no per-pixel state from the forward: the colour
 // still to come behind entry k is image - (colour accumulated up to k).
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace tgs {
 namespace {
@@ -26,17 +27,17 @@ constexpr int kXcds = 8;
 
 // alpha = min(0.99, o exp(p)), p = -1/2 (A dx^2 + C dy^2) - B dx dy; false if
 // the entry is skipped (p > 0 or alpha < 1/255).  ga = (u, v, A, B),
-// gb = (C, o, r, g).  Compiled without FP contraction: forward and backward
-// evaluate exactly the same operations.
+// gb = (C, o, r, g).  G and alpha are computed either way (branch-free
+// callers select on the result).  Compiled without FP contraction: forward
+// and backward evaluate exactly the same operations.
 __device__ __forceinline__ bool splat_alpha(const float4 ga, const float4 gb, float X, float Y,
                                             float& dx, float& dy, float& G, float& alpha) {
     dx = ga.x - X;
     dy = ga.y - Y;
     const float power = -0.5f * (ga.z * dx * dx + gb.x * dy * dy) - ga.w * dx * dy;
-    if (power > 0.0f) return false;
     G = __builtin_amdgcn_exp2f(power * kLog2e);
     alpha = fminf(kAlphaMax, gb.y * G);
-    return alpha >= kAlphaMin;
+    return power <= 0.0f && alpha >= kAlphaMin;
 }
 
 // Tile of workgroup b.  order 0: tile = b.  order 1: the tile grid is cut
@@ -71,41 +72,51 @@ struct Shape {
     static constexpr int BATCH = NT < 256 ? NT : 256;
 };
 
-// Sums of 9 per-lane values over the wavefront.  Eight of them are reduced
-// with a transposing butterfly (each exchange halves the values a lane keeps),
-// so lane 8c (c = 0..7) ends with the total of value c; value 8 is reduced
-// plainly and lane 1 keeps it.  Returns the value this lane owns and its
-// index (or -1).
+// a + b after exchanging the upper 32 lanes of a with the lower 32 of b:
+// lanes 0-31 get a[i] + a[i+32], lanes 32-63 get b[i-32] + b[i].
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The same between rows of 16 lanes: rows 0 and 2 get a[row] + a[row + 1],
+// rows 1 and 3 get b[row - 1] + b[row].
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sums of 9 per-lane values over the wavefront.  Eight of them go through a
+// transposing butterfly -- each exchange halves the values a lane keeps: the
+// upper half-wave keeps values 4-7, the odd rows keep the upper two of the
+// remaining four, the upper 8 lanes of a row the second one -- and end with
+// a sum over the 8 lanes of each octet (row mirror, half mirror, quad swaps),
+// so lane 8c (c = 0..7) holds the total of value c.  Value 8 is summed over
+// all lanes the same way and lane 1 keeps it.  Returns the value this lane
+// owns and its index (or -1).
 __device__ __forceinline__ float wave_sum9(const float* v, int& comp) {
     const int lane = __lane_id();
-    const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+    const bool h16 = lane & 16, h8 = lane & 8;
     float w[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float send = h32 ? v[k] : v[k + 4];
-        const float keep = h32 ? v[k + 4] : v[k];
-        w[k] = keep + __shfl_xor(send, 32);
-    }
-    float x[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float send = h16 ? w[k] : w[k + 2];
-        const float keep = h16 ? w[k + 2] : w[k];
-        x[k] = keep + __shfl_xor(send, 16);
-    }
-    float y;
-    {
-        const float send = h8 ? x[0] : x[1];
-        const float keep = h8 ? x[1] : x[0];
-        y = keep + __shfl_xor(send, 8);
-    }
-    y += __shfl_xor(y, 4);
-    y += __shfl_xor(y, 2);
-    y += __shfl_xor(y, 1);
-    float z = v[8];
-    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
+    for (int k = 0; k < 4; ++k) w[k] = swap32_add(v[k], v[k + 4]);
+    const float x0 = swap16_add(w[0], w[2]);
+    const float x1 = swap16_add(w[1], w[3]);
+    const float send = h8 ? x0 : x1;
+    float y = (h8 ? x1 : x0) + dpp_f<kDppRowMirror>(send);
+    y += dpp_f<kDppRowHalfMirror>(y);
+    y += dpp_f<kDppQuadXor2>(y);
+    y += dpp_f<kDppQuadXor1>(y);
+    float z = swap32_add(v[8], v[8]);
+    z = swap16_add(z, z);
+    z += dpp_f<kDppRowMirror>(z);
+    z += dpp_f<kDppRowHalfMirror>(z);
+    z += dpp_f<kDppQuadXor2>(z);
+    z += dpp_f<kDppQuadXor1>(z);
     comp = -1;
-    if ((lane & 7) == 0) comp = (h32 ? 4 : 0) + (h16 ? 2 : 0) + (h8 ? 1 : 0);
+    if ((lane & 7) == 0) comp = ((lane & 32) ? 4 : 0) + (h16 ? 2 : 0) + (h8 ? 1 : 0);
     if (lane == 1) {
         comp = 8;
         y = z;
@@ -158,29 +169,29 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
         }
         __syncthreads();
         const int cnt = min(S::BATCH, int(end - base));
-        for (int e = 0; e < cnt && alive; ++e) {
+        // branch-free per entry: a skipped entry adds exactly 0 and leaves T
+        for (int e = 0; e < cnt; ++e) {
+            if (__ballot(alive) == 0) break;           // the whole wavefront has stopped
             const float4 a = s_a[e], b = s_b[e];
             const float bb = s_c[e];
+            const uint32_t pos = base - start + uint32_t(e) + 1;
             alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                if (done[k]) continue;
                 float dx, dy, G, alpha;
-                if (splat_alpha(a, b, X[k], Y[k], dx, dy, G, alpha)) {
-                    const float Tn = Tr[k] * (1.0f - alpha);
-                    if (Tn < kTMin) {
-                        done[k] = true;
-                        neval[k] = base - start + uint32_t(e) + 1;
-                        continue;
-                    }
-                    const float w = alpha * Tr[k];
-                    c0[k] += b.z * w;
-                    c1[k] += b.w * w;
-                    c2[k] += bb * w;
-                    Tr[k] = Tn;
-                    last[k] = base - start + uint32_t(e) + 1;
-                }
-                alive = true;
+                const bool hit = splat_alpha(a, b, X[k], Y[k], dx, dy, G, alpha) && !done[k];
+                const float Tn = Tr[k] * (1.0f - alpha);
+                const bool stop = hit && Tn < kTMin;
+                const bool blend = hit && !stop;
+                const float w = blend ? alpha * Tr[k] : 0.0f;
+                c0[k] += b.z * w;
+                c1[k] += b.w * w;
+                c2[k] += bb * w;
+                Tr[k] = blend ? Tn : Tr[k];
+                last[k] = blend ? pos : last[k];
+                neval[k] = stop ? pos : neval[k];
+                done[k] = done[k] || stop;
+                alive = alive || !done[k];
             }
         }
     }
@@ -255,57 +266,55 @@ raster_bwd_kernel(Grid grid, int order, const float4* __restrict__ rec,
         const int cnt = min(S::BATCH, int(end - base));
         for (int e = 0; e < cnt; ++e) {
             if (__ballot(alive) == 0) break;          // the whole wavefront has stopped
+            const float4 a = s_a[e], b = s_b[e];
+            const float bb = s_c[e];
+            // decisions, exactly as in the forward
+            float dx[S::NP], dy[S::NP], G[S::NP], alpha[S::NP];
+            bool blend[S::NP];
+            bool any = false;
+            alive = false;
+#pragma unroll
+            for (int k = 0; k < S::NP; ++k) {
+                const bool hit = splat_alpha(a, b, X[k], Y[k], dx[k], dy[k], G[k], alpha[k]) && !done[k];
+                const bool stop = hit && Tr[k] * (1.0f - alpha[k]) < kTMin;
+                blend[k] = hit && !stop;
+                any = any || blend[k];
+                done[k] = done[k] || stop;
+                alive = alive || !done[k];
+            }
+            if (__ballot(any) == 0) continue;          // no pixel of the wavefront blends it
             float gv[kGrad2d];
 #pragma unroll
             for (int c = 0; c < kGrad2d; ++c) gv[c] = 0.0f;
-            bool contrib = false;
-            if (alive) {
-                const float4 a = s_a[e], b = s_b[e];
-                const float bb = s_c[e];
-                alive = false;
 #pragma unroll
-                for (int k = 0; k < S::NP; ++k) {
-                    if (done[k]) continue;
-                    float dx, dy, G, alpha;
-                    if (splat_alpha(a, b, X[k], Y[k], dx, dy, G, alpha)) {
-                        const float Tn = Tr[k] * (1.0f - alpha);
-                        if (Tn < kTMin) {
-                            done[k] = true;
-                            continue;
-                        }
-                        contrib = true;
-                        const float w = alpha * Tr[k];
-                        p0[k] += b.z * w;
-                        p1[k] += b.w * w;
-                        p2[k] += bb * w;
-                        gv[6] += w * g0[k];
-                        gv[7] += w * g1[k];
-                        gv[8] += w * g2[k];
-                        const float inv = 1.0f / (1.0f - alpha);
-                        const float dal = g0[k] * (b.z * Tr[k] - (im0[k] - p0[k]) * inv) +
-                                          g1[k] * (b.w * Tr[k] - (im1[k] - p1[k]) * inv) +
-                                          g2[k] * (bb * Tr[k] - (im2[k] - p2[k]) * inv);
-                        // no gradient through the 0.99 clamp
-                        if (!(b.y * G > kAlphaMax)) {
-                            const float dp = alpha * dal;
-                            gv[5] += G * dal;
-                            gv[0] -= dp * (a.z * dx + a.w * dy);
-                            gv[1] -= dp * (b.x * dy + a.w * dx);
-                            gv[2] -= 0.5f * dp * dx * dx;
-                            gv[3] -= dp * dx * dy;
-                            gv[4] -= 0.5f * dp * dy * dy;
-                        }
-                        Tr[k] = Tn;
-                    }
-                    alive = true;
-                }
+            for (int k = 0; k < S::NP; ++k) {
+                const float T0 = Tr[k];
+                const float w = blend[k] ? alpha[k] * T0 : 0.0f;
+                p0[k] += b.z * w;
+                p1[k] += b.w * w;
+                p2[k] += bb * w;
+                gv[6] += w * g0[k];
+                gv[7] += w * g1[k];
+                gv[8] += w * g2[k];
+                // d image / d alpha = rgb T - (colour behind) / (1 - alpha)
+                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[k]);
+                const float dal = g0[k] * (b.z * T0 - (im0[k] - p0[k]) * inv) +
+                                  g1[k] * (b.w * T0 - (im1[k] - p1[k]) * inv) +
+                                  g2[k] * (bb * T0 - (im2[k] - p2[k]) * inv);
+                // no gradient through the 0.99 clamp
+                const bool live = blend[k] && !(b.y * G[k] > kAlphaMax);
+                const float dp = live ? alpha[k] * dal : 0.0f;
+                gv[5] += live ? G[k] * dal : 0.0f;
+                gv[0] -= dp * (a.z * dx[k] + a.w * dy[k]);
+                gv[1] -= dp * (b.x * dy[k] + a.w * dx[k]);
+                gv[2] -= 0.5f * dp * dx[k] * dx[k];
+                gv[3] -= dp * dx[k] * dy[k];
+                gv[4] -= 0.5f * dp * dy[k] * dy[k];
+                Tr[k] = blend[k] ? T0 * (1.0f - alpha[k]) : T0;
             }
-            if (__ballot(contrib) != 0) {
-                int comp;
-                const float s = wave_sum9(gv, comp);
-                if (comp >= 0 && s != 0.0f)
-                    atomicAdd(&grad2d[uint64_t(s_id[e]) * kGrad2d + comp], s);
-            }
+            int comp;
+            const float s = wave_sum9(gv, comp);
+            if (comp >= 0 && s != 0.0f) atomicAdd(&grad2d[uint64_t(s_id[e]) * kGrad2d + comp], s);
         }
     }
 }
