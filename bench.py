@@ -8,7 +8,12 @@ same view.
 One step = preprocess -> pairs + sort + ranges -> dilated blend -> L1 loss
 gradient against the full-resolution target -> blend backward -> preprocess
 backward with densification statistics, on inputs already resident in HBM.
-Prints ONE JSON line.
+Prints ONE JSON line (diagnostics go to stderr).
+
+Gaussian-pixel evaluations: forward = list entries examined per rendered
+pixel until its walk ends (stop entry included); backward = entries up to the
+pixel's last blended one.  Both are counted by the kernels themselves
+(per-pixel outputs checked against the CPU checker in the tests).
 """
 from __future__ import annotations
 
@@ -22,11 +27,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
-PEAK_VALU = 256 * 4 * 16 * 2.4e9   # FP32 lane-ops/s (256 CU x 4 SIMD x 16 lanes x 2.4 GHz)
-# op model (FP32 VALU lane-operations per Gaussian-pixel evaluation)
-OPS_FWD = 21
-OPS_BWD = 55
+PEAK_HBM = 8.0e12                    # B/s, MI355X HBM3E
+PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# Arithmetic of the method per list entry (FP32 VALU lane-operations):
+#   every examined entry: offset, quadratic form, exp, opacity, clamp, the two
+#   threshold tests and the transmittance product            -> 21
+#   blended entry, forward: weight and colour accumulation       -> 7
+#   blended entry, backward: weight, prefix colour, d/drgb, d/dalpha through
+#   the colour behind, d/d(o, u, v, A, B, C), and the 9-value sum over pixels -> 67
+OPS_EXAMINE, OPS_BLEND_FWD, OPS_BLEND_BWD = 21, 7, 67
 STAGES = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd", "preprocess_bwd")
 
 
@@ -40,7 +49,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 class Runner:
@@ -68,12 +83,16 @@ class Runner:
                                   t.empty(shape, dtype=t.float32, device="cuda"))
         return self.images[shape]
 
-    def step(self, k, events=None):
+    def _phase(self, k):
         from paper_2412_13547_amd import scenes
         ox, oy = scenes.phase_offsets(k, self.stride)
         v = self.view
         if (int(v.dil.off_x), int(v.dil.off_y)) != (ox, oy):
             v.set_offsets(ox, oy)
+
+    def step(self, k, events=None):
+        self._phase(k)
+        v = self.view
         img, dL = self._bufs()
         rec = (lambda i: events[i].record()) if events else (lambda i: None)
         rec(0)
@@ -90,20 +109,18 @@ class Runner:
         v.preprocess_bwd(self.dev, self.grads, self.pos, self.col, self.vis)
         rec(6)
 
-    def evals(self, k):
-        """Gaussian-pixel evaluations of step k: entries examined per pixel in
-        the forward plus entries blended (walked back) in the backward."""
+    def counts(self, k):
+        """Per-step sums of n_eval, last_contrib and n_blend for phase k."""
         t = self.torch
-        from paper_2412_13547_amd import scenes
-        ox, oy = scenes.phase_offsets(k, self.stride)
-        self.view.set_offsets(ox, oy)
+        self._phase(k)
         img, _ = self._bufs()
         shape = self.view.image_shape
-        last = t.empty(shape[1:], dtype=t.int32, device="cuda")
-        neval = t.empty(shape[1:], dtype=t.int32, device="cuda")
-        self.view.forward(self.dev, img, last_contrib=last, n_eval=neval)
+        z = lambda: t.empty(shape[1:], dtype=t.int32, device="cuda")
+        last, neval, nblend = z(), z(), z()
+        self.view.forward(self.dev, img, last_contrib=last, n_eval=neval, n_blend=nblend)
         t.cuda.synchronize()
-        return int(neval.sum(dtype=t.int64)), int(last.sum(dtype=t.int64))
+        s = lambda x: int(x.sum(dtype=t.int64))
+        return s(neval), s(last), s(nblend), int(self.view.state.pair_count)
 
     def timed(self, steps, warmup):
         t = self.torch
@@ -118,7 +135,7 @@ class Runner:
         t.cuda.synchronize()
         wall = time.perf_counter() - t0
         per_step = [e[0].elapsed_time(e[6]) for e in ev]
-        stage = {s: statistics.median([e[i].elapsed_time(e[i + 1]) for e in ev])
+        stage = {s: statistics.mean([e[i].elapsed_time(e[i + 1]) for e in ev])
                  for i, s in enumerate(STAGES)}
         return wall, per_step, stage
 
@@ -135,8 +152,7 @@ def cpu_baseline(runner, seconds):
     v.set_offsets(0, 0)
     v.forward(runner.dev, runner._bufs()[0])
     torch.cuda.synchronize()
-    r32 = v.records().cpu()
-    r = r32.to(torch.float64)
+    r = v.records().cpu().to(torch.float64)
     rec = dict(u=r[:, 0], v=r[:, 1], A=r[:, 2], B=r[:, 3], C=r[:, 4], opacity=r[:, 5],
                rgb=r[:, 6:9].clone())
     vals = v.pair_vals().cpu().to(torch.int64)
@@ -160,8 +176,8 @@ def cpu_baseline(runner, seconds):
     el = time.perf_counter() - t0
     return {"value": evals / el, "unit": "Gaussian-pixel evals/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"{tiles} random non-empty tiles of phase (0,0), blend forward + backward "
-                      f"in float64 ({el:.1f} s)"}
+            "sample": f"{tiles} random non-empty tiles of phase (0,0): float64 blend forward + "
+                      f"backward of the checker, {el:.1f} s; evals counted as in the metric"}
 
 
 def main():
@@ -173,50 +189,61 @@ def main():
     import torch
     from paper_2412_13547_amd import api, scenes
 
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")      # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("# calibration copy: 1 GiB read + 1 GiB written")
+
     sc, cam, tgt = scenes.workload(args.workload, n=args.n)
     w = scenes.WORKLOADS[args.workload]
     stride = w.get("stride", 1)
     dev = api.DeviceScene.from_scene(sc)
     target = torch.as_tensor(tgt).cuda()
     del tgt
-    print(f"# scene ready: n={sc.n} {cam.width}x{cam.height} stride={stride}", file=sys.stderr,
-          flush=True)
+    log(f"# scene ready: n={sc.n} {cam.width}x{cam.height} stride={stride}")
 
     dil = Runner(api, torch, dev, cam, target, stride)
     wall, per_step, stage = dil.timed(args.steps, args.warmup)
     ms = 1000.0 * wall / args.steps
-    ev = [dil.evals(k) for k in range(stride * stride)]
-    fwd_evals = float(np.mean([e[0] for e in ev]))
-    bwd_evals = float(np.mean([e[1] for e in ev]))
-    pairs = int(dil.view.state.pair_count)
-    print(f"# dilated: {ms:.3f} ms/step, pairs {pairs}, stages {stage}", file=sys.stderr, flush=True)
+    cnt = [dil.counts(k) for k in range(stride * stride)]
+    fwd_evals = float(np.mean([c[0] for c in cnt]))
+    bwd_evals = float(np.mean([c[1] for c in cnt]))
+    blended = float(np.mean([c[2] for c in cnt]))
+    pairs = float(np.mean([c[3] for c in cnt]))
+    log(f"# dilated: {ms:.3f} ms/step, pairs {pairs:.0f}, stages {stage}")
 
     plain = None
     if not args.no_plain and stride > 1:
         pr = Runner(api, torch, dev, cam, target, 1)
-        pwall, pper, pstage = pr.timed(max(3, args.steps // 2), 2)
-        pe = pr.evals(0)
-        pms = 1000.0 * pwall / max(3, args.steps // 2)
-        plain = {"ms_per_step": pms, "evals_per_s": (pe[0] + pe[1]) / (pms / 1000.0),
-                 "pairs": int(pr.view.state.pair_count), "stages_ms": pstage,
-                 "fwd_evals": pe[0], "bwd_evals": pe[1]}
-        print(f"# plain: {pms:.3f} ms/step, stages {pstage}", file=sys.stderr, flush=True)
+        psteps = max(3, args.steps // 2)
+        pwall, pper, pstage = pr.timed(psteps, 2)
+        pc = pr.counts(0)
+        pms = 1000.0 * pwall / psteps
+        plain = {"ms_per_step": pms, "evals_per_s": (pc[0] + pc[1]) / (pms / 1000.0),
+                 "pairs": pc[3], "stages_ms": pstage, "fwd_evals": pc[0], "bwd_evals": pc[1]}
+        log(f"# plain: {pms:.3f} ms/step, stages {pstage}")
         del pr
 
-    # roofline of the dominant kernel (the stage taking the most time)
-    dom = max(("raster_fwd", "raster_bwd", "bin_sort", "preprocess_fwd", "preprocess_bwd"),
-              key=lambda s: stage[s])
+    # rooflines: the two raster kernels against FP32 VALU issue, the binning
+    # stage against HBM (bytes the implementation has to move)
+    def alu(ops, t_ms):
+        a = ops / (t_ms / 1000.0) / 1e12
+        return {"bound": "alu", "achieved": a, "peak": PEAK_VALU / 1e12, "unit": "T lane-ops/s",
+                "frac": a / (PEAK_VALU / 1e12)}
     n = sc.n
-    if dom in ("raster_fwd", "raster_bwd"):
-        ops = fwd_evals * OPS_FWD if dom == "raster_fwd" else bwd_evals * OPS_BWD
-        achieved = ops / (stage[dom] / 1000.0) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_VALU / 1e12,
-                "unit": "T lane-ops/s", "frac": achieved / (PEAK_VALU / 1e12), "traffic": None}
-    else:
-        per = {"bin_sort": pairs * 44.0, "preprocess_fwd": n * 296.0, "preprocess_bwd": n * 520.0}[dom]
-        achieved = per / (stage[dom] / 1000.0) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9), "traffic": None}
+    roof_bwd = dict(kernel="raster_bwd_kernel<16,1,1>",
+                    **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_BWD * blended, stage["raster_bwd"]),
+                    traffic=None)
+    roof_fwd = dict(kernel="raster_fwd_kernel<16,1,1>",
+                    **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_FWD * blended, stage["raster_fwd"]))
+    sort_bytes = 18.0 * pairs + 200.0 * n
+    roof_sort = {"stage": "bin_sort", "bound": "hbm",
+                 "achieved": sort_bytes / (stage["bin_sort"] / 1000.0) / 1e9,
+                 "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof_sort["frac"] = roof_sort["achieved"] / roof_sort["peak"]
 
     out = {
         "metric": "fwd+bwd ms/iter & Gaussian-pixel evals/s, 4K dilated batched vs plain",
@@ -231,11 +258,12 @@ def main():
         "config": {"workload": w["name"], "gaussians": n, "sh_degree": sc.sh_degree,
                    "width": cam.width, "height": cam.height, "stride": stride, "tile": 16,
                    "phases": "cycle (0,0),(1,0),(0,1),(1,1)" if stride == 2 else "single"},
-        "pairs": pairs, "fwd_evals": fwd_evals, "bwd_evals": bwd_evals,
+        "pairs": pairs, "fwd_evals": fwd_evals, "bwd_evals": bwd_evals, "blended": blended,
         "stages_ms": stage,
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms) if plain else None,
-        "roofline": roof,
+        "roofline": roof_bwd,
+        "rooflines_other": [roof_fwd, roof_sort],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dil, args.cpu_seconds)

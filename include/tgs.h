@@ -189,10 +189,12 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
  * before the entry that would take T below 1e-4, and outputs C + T bg.
  * image: device [3][H_ds][W_ds].  Optional (may be NULL) device outputs per
  * downsampled pixel: t_final float, last_contrib uint32 (1-based index of the
- * last blended list entry), n_eval uint32 (entries examined, stop included). */
+ * last blended list entry), n_eval uint32 (entries examined, stop included),
+ * n_blend uint32 (entries blended). */
 tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
                           const tgs_options* opt, const tgs_state* st, int64_t n, float* image,
-                          float* t_final, uint32_t* last_contrib, uint32_t* n_eval, void* stream);
+                          float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
+                          uint32_t* n_blend, void* stream);
 
 /* Stages (a)-(c) in order.  Same arguments and outputs as the three calls. */
 tgs_status tgs_forward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,

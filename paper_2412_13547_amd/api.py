@@ -85,7 +85,7 @@ def _declare(lib):
         "tgs_bin_sort": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
                                    _P(tgs_options), _P(tgs_state), vp]),
         "tgs_raster_fwd": (C.c_int, [vp, _P(tgs_camera), _P(tgs_dilation), _P(tgs_options),
-                                     _P(tgs_state), C.c_int64, vp, vp, vp, vp, vp]),
+                                     _P(tgs_state), C.c_int64, vp, vp, vp, vp, vp, vp]),
         "tgs_forward": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
                                   _P(tgs_options), _P(tgs_state), vp, vp]),
         "tgs_l1_grad": (C.c_int, [vp, _P(tgs_camera), _P(tgs_dilation), vp, vp, vp, vp, vp]),
@@ -294,19 +294,21 @@ class View:
                                     _stream(stream))
         check(st)
 
-    def raster_fwd(self, image, t_final=None, last_contrib=None, n_eval=None, stream=None):
+    def raster_fwd(self, image, t_final=None, last_contrib=None, n_eval=None, n_blend=None,
+                   stream=None):
         check(lib().tgs_raster_fwd(self.ctx.handle, C.byref(self.cam_s), C.byref(self.dil),
                                    C.byref(self.opt), C.byref(self.state), self.n, _ptr(image),
-                                   _ptr(t_final), _ptr(last_contrib), _ptr(n_eval), _stream(stream)))
+                                   _ptr(t_final), _ptr(last_contrib), _ptr(n_eval), _ptr(n_blend),
+                                   _stream(stream)))
 
     def forward(self, scene: DeviceScene, image=None, stream=None, t_final=None, last_contrib=None,
-                n_eval=None):
+                n_eval=None, n_blend=None):
         torch = self._torch
         if image is None:
             image = torch.empty(self.image_shape, dtype=torch.float32, device="cuda")
         self.preprocess_fwd(scene, stream)
         self.bin_sort(scene, stream)
-        self.raster_fwd(image, t_final, last_contrib, n_eval, stream)
+        self.raster_fwd(image, t_final, last_contrib, n_eval, n_blend, stream)
         return image
 
     def l1_grad(self, image, target, dL_dimage=None, loss=None, stream=None):

@@ -389,7 +389,8 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
 
 tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
                           const tgs_options* opt, const tgs_state* st, int64_t n, float* image,
-                          float* t_final, uint32_t* last_contrib, uint32_t* n_eval, void* stream) {
+                          float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
+                          uint32_t* n_blend, void* stream) {
     tgs_status s = check_common(cam, dil, opt);
     if (s == TGS_OK && !opt) s = fail(TGS_ERR_INVALID_ARG, "options is NULL");
     if (s != TGS_OK) return s;
@@ -404,7 +405,7 @@ tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     TGS_HIP(tgs::launch_raster_fwd(grid, tgs::raster_tuning(), opt->bg, ws, L,
                                    reinterpret_cast<const uint32_t*>(ws + st->off_pair_vals),
                                    uint32_t(st->pair_count), image, t_final, last_contrib, n_eval,
-                                   static_cast<hipStream_t>(stream)));
+                                   n_blend, static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
 
@@ -415,7 +416,8 @@ tgs_status tgs_forward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camer
     tgs_status s = tgs_preprocess_fwd(ctx, g, cam, dil, opt, st, stream);
     if (s == TGS_OK) s = tgs_bin_sort(ctx, g, cam, dil, opt, st, stream);
     if (s == TGS_OK)
-        s = tgs_raster_fwd(ctx, cam, dil, opt, st, g->n, image, nullptr, nullptr, nullptr, stream);
+        s = tgs_raster_fwd(ctx, cam, dil, opt, st, g->n, image, nullptr, nullptr, nullptr, nullptr,
+                           stream);
     return s;
 }
 

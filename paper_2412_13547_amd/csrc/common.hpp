@@ -115,6 +115,7 @@ hipError_t launch_raster_fwd(const Grid& grid, const RasterTuning& tune, const f
                              const uint8_t* ws, const Layout& L, const uint32_t* pair_vals,
                              uint32_t pair_count, float* image,
                              float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
+                             uint32_t* n_blend,
                              hipStream_t s);
 hipError_t launch_raster_bwd(const Grid& grid, const RasterTuning& tune, const uint8_t* ws,
                              const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,

@@ -130,7 +130,8 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
                   const float4* __restrict__ rec, const uint32_t* __restrict__ ranges,
                   const uint32_t* __restrict__ vals, uint32_t pair_count,
                   float* __restrict__ image, float* __restrict__ t_final,
-                  uint32_t* __restrict__ last_contrib, uint32_t* __restrict__ n_eval) {
+                  uint32_t* __restrict__ last_contrib, uint32_t* __restrict__ n_eval,
+                  uint32_t* __restrict__ n_blend) {
     using S = Shape<T, PX, PY>;
     __shared__ float4 s_a[S::BATCH], s_b[S::BATCH];
     __shared__ float s_c[S::BATCH];
@@ -144,7 +145,7 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
     const uint32_t end = min(ranges[2 * tile + 1], pair_count);
     const uint32_t start = min(ranges[2 * tile], end);
     float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
-    uint32_t last[S::NP], neval[S::NP];
+    uint32_t last[S::NP], neval[S::NP], nblend[S::NP];
     bool done[S::NP];
     bool alive = false;
 #pragma unroll
@@ -157,6 +158,7 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
         Tr[k] = 1.0f;
         c0[k] = c1[k] = c2[k] = 0.0f;
         last[k] = 0;
+        nblend[k] = 0;
         neval[k] = end - start;
     }
     for (uint32_t base = start; base < end; base += S::BATCH) {
@@ -189,6 +191,7 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
                 c2[k] += bb * w;
                 Tr[k] = blend ? Tn : Tr[k];
                 last[k] = blend ? pos : last[k];
+                nblend[k] += blend ? 1u : 0u;
                 neval[k] = stop ? pos : neval[k];
                 done[k] = done[k] || stop;
                 alive = alive || !done[k];
@@ -207,6 +210,7 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
         if (t_final) t_final[p] = Tr[k];
         if (last_contrib) last_contrib[p] = last[k];
         if (n_eval) n_eval[p] = neval[k];
+        if (n_blend) n_blend[p] = nblend[k];
     }
 }
 
@@ -350,10 +354,11 @@ l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restri
 template <int T, int PX, int PY>
 void fwd_launch(const Grid& grid, int order, const float bg[3], const float4* rec,
                 const uint32_t* ranges, const uint32_t* vals, uint32_t pc, float* image,
-                float* t_final, uint32_t* last, uint32_t* neval, hipStream_t s) {
+                float* t_final, uint32_t* last, uint32_t* neval, uint32_t* nblend, hipStream_t s) {
     raster_fwd_kernel<T, PX, PY><<<dim3(blocks_for_tiles(grid, order)),
                                    dim3(Shape<T, PX, PY>::NT), 0, s>>>(
-        grid, order, bg[0], bg[1], bg[2], rec, ranges, vals, pc, image, t_final, last, neval);
+        grid, order, bg[0], bg[1], bg[2], rec, ranges, vals, pc, image, t_final, last, neval,
+        nblend);
 }
 
 template <int T, int PX, int PY>
@@ -370,13 +375,14 @@ void bwd_launch(const Grid& grid, int order, const float4* rec, const uint32_t* 
 hipError_t launch_raster_fwd(const Grid& grid, const RasterTuning& tune, const float bg[3],
                              const uint8_t* ws, const Layout& L, const uint32_t* pair_vals,
                              uint32_t pair_count, float* image, float* t_final,
-                             uint32_t* last_contrib, uint32_t* n_eval, hipStream_t s) {
+                             uint32_t* last_contrib, uint32_t* n_eval, uint32_t* n_blend,
+                             hipStream_t s) {
     const auto* rec = reinterpret_cast<const float4*>(ws + L.records);
     const auto* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
     if (grid.num_tiles() == 0) return hipSuccess;
     const int o = tune.order;
 #define TGS_FWD(T, PX, PY) fwd_launch<T, PX, PY>(grid, o, bg, rec, ranges, pair_vals, pair_count, \
-                                                image, t_final, last_contrib, n_eval, s)
+                                                image, t_final, last_contrib, n_eval, n_blend, s)
     if (grid.tile == 8) TGS_FWD(8, 1, 1);
     else if (grid.tile == 32) { if (tune.ppt == 2) TGS_FWD(32, 2, 1); else TGS_FWD(32, 2, 2); }
     else if (tune.ppt == 1) TGS_FWD(16, 1, 1);

@@ -40,8 +40,10 @@ def run_gpu(scene, cam, stride=1, off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0),
     tfin = torch.empty(shape[1:], dtype=torch.float32, device="cuda")
     last = torch.empty(shape[1:], dtype=torch.int32, device="cuda")
     neval = torch.empty(shape[1:], dtype=torch.int32, device="cuda")
-    view.forward(dev, image, t_final=tfin, last_contrib=last, n_eval=neval)
-    out = dict(view=view, image=image, t_final=tfin, last_contrib=last, n_eval=neval)
+    nblend = torch.empty(shape[1:], dtype=torch.int32, device="cuda")
+    view.forward(dev, image, t_final=tfin, last_contrib=last, n_eval=neval, n_blend=nblend)
+    out = dict(view=view, image=image, t_final=tfin, last_contrib=last, n_eval=neval,
+               n_blend=nblend)
     if backward:
         if dL_dimage is None:
             tgt = torch.as_tensor(np.asarray(target, np.float32)).cuda()

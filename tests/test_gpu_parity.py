@@ -118,6 +118,7 @@ def test_raster_forward_matches_checker(name):
     keep = ~flag
     assert torch.equal(g["last_contrib"].to(torch.int64)[keep], o["last_contrib"][keep])
     assert torch.equal(g["n_eval"].to(torch.int64)[keep], o["n_eval"][keep])
+    assert torch.equal(g["n_blend"].to(torch.int64)[keep], o["n_blend"][keep])
     assert float((g["t_final"].to(F64) - o["t_final"]).abs()[keep].max()) <= 1e-5
 
 
