@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the 12-view batch (2M Gaussians, mixed resolutions and strides)")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--lds-batch", type=int, default=0)
     return ap.parse_args()
 
 
@@ -180,6 +184,154 @@ def cpu_baseline(runner, seconds):
                       f"backward of the checker, {el:.1f} s; evals counted as in the metric"}
 
 
+def _time_events(torch, fn, steps):
+    """Per-step milliseconds of fn() between events on the current stream."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def run_batched(args, api, torch, np):
+    """The multi-view batch: views of mixed resolution and stride rendered by
+    the batched calls, replayed from one captured graph; compared with the
+    same step enqueued eagerly, with the views processed one by one through
+    the single-view calls, and with the plain full-resolution batch."""
+    from paper_2412_13547_amd import scenes
+    w = scenes.WORKLOADS[3]
+    n = args.n or w["n"]
+    sc = scenes.cluster_scene(3, n, w["sh_degree"])
+    vspec = scenes.batched_views(2003, w["views"])
+    dev = api.DeviceScene.from_scene(sc)
+    del sc
+    targets = [torch.as_tensor(scenes.target_image(c.width, c.height, 1003 + k)).cuda()
+               for k, (c, _d) in enumerate(vspec)]
+    ctx = api.Context(0)
+    grads = dev.zeros_like()
+    pos = torch.empty(n, dtype=torch.float32, device="cuda")
+    col = torch.empty(n, dtype=torch.float32, device="cuda")
+    vis = torch.empty(n, dtype=torch.uint8, device="cuda")
+    views = [(c, d) + scenes.phase_offsets(k, d) for k, (c, d) in enumerate(vspec)]
+    log("# batch views: " + ", ".join(f"{c.width}x{c.height}/d{d}" for c, d, _x, _y in views))
+
+    def make(vs, counts=False):
+        b = api.Batch(ctx, n, vs, tile=16, lds_batch=args.lds_batch, counts=counts)
+        b.set_targets(targets)
+        b.fit_capacity(dev)
+        return b
+
+    def graph_of(b):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            b.step(dev, grads, pos, col, vis)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            b.step(dev, grads, pos, col, vis)
+        return g
+
+    K = args.batched_steps
+    res = {"workload": w["name"], "gaussians": n, "sh_degree": w["sh_degree"],
+           "views": [f"{c.width}x{c.height}/d{d}/o{ox}{oy}" for c, d, ox, oy in views]}
+    # evaluation counts (one forward with the per-pixel counters)
+    b = make(views, counts=True)
+    b.forward(dev)
+    pc = b.pair_counts()
+    s64 = lambda ts: int(sum(int(t.sum(dtype=torch.int64)) for t in ts))
+    fwd_e, bwd_e, blended = s64(b.n_eval), s64(b.last_contrib), s64(b.n_blend)
+    res.update(pairs=int(sum(pc)), fwd_evals=fwd_e, bwd_evals=bwd_e, blended=blended)
+    del b
+    torch.cuda.empty_cache()
+    b = make(views)
+    # eager, staged: per-stage means
+    stage_names = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd",
+                   "preprocess_bwd")
+    fns = (lambda: b.preprocess_fwd(dev), lambda: b.bin_sort(dev), lambda: b.raster_fwd(),
+           lambda: b.l1_grad(), lambda: b.raster_bwd(),
+           lambda: b.preprocess_bwd(dev, grads, pos, col, vis))
+    for _ in range(2):
+        for f in fns:
+            f()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(K)]
+    torch.cuda.synchronize()
+    for k in range(K):
+        ev[k][0].record()
+        for i, f in enumerate(fns):
+            f()
+            ev[k][i + 1].record()
+    torch.cuda.synchronize()
+    res["stages_ms"] = {s: statistics.mean([e[i].elapsed_time(e[i + 1]) for e in ev])
+                        for i, s in enumerate(stage_names)}
+    eager = _time_events(torch, lambda: b.step(dev, grads, pos, col, vis), K)
+    g = graph_of(b)
+    g.replay()
+    graphed = _time_events(torch, g.replay, K)
+    res["ms_per_step"] = float(np.median(graphed))
+    res["ms_eager"] = float(np.median(eager))
+    res["ms_p10"], res["ms_p90"] = float(np.percentile(graphed, 10)), float(np.percentile(graphed, 90))
+    res["evals_per_s"] = (fwd_e + bwd_e) / (res["ms_per_step"] / 1000.0)
+    log(f"# batched: graph {res['ms_per_step']:.3f} ms, eager {res['ms_eager']:.3f} ms, "
+        f"stages {res['stages_ms']}")
+    del g, b
+    torch.cuda.empty_cache()
+    # one view at a time through the single-view calls (each binning reads its
+    # pair count back)
+    singles = [api.View(ctx, n, c, d, ox, oy, 16, lds_batch=args.lds_batch) for c, d, ox, oy in views]
+    imgs = [torch.empty(v.image_shape, dtype=torch.float32, device="cuda") for v in singles]
+    dls = [torch.empty_like(t) for t in imgs]
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def per_view():
+        for v, img, dl, tg in zip(singles, imgs, dls, targets):
+            v.forward(dev, img)
+            v.l1_grad(img, tg, dl, loss)
+            v.backward(dev, img, dl, grads, pos, col, vis)
+    per_view()
+    res["ms_per_view_calls"] = float(np.median(_time_events(torch, per_view, max(3, K // 2))))
+    del singles, imgs, dls
+    torch.cuda.empty_cache()
+    # plain: every view at full resolution, batched and graphed
+    if not args.no_plain:
+        plain_views = [(c, 1, 0, 0) for c, _d, _x, _y in views]
+        b = make(plain_views, counts=True)
+        b.forward(dev)
+        ppc = b.pair_counts()
+        pe = s64(b.n_eval) + s64(b.last_contrib)
+        del b
+        torch.cuda.empty_cache()
+        b = make(plain_views)
+        g = graph_of(b)
+        g.replay()
+        pt = _time_events(torch, g.replay, max(3, K // 2))
+        res["plain"] = {"ms_per_step": float(np.median(pt)), "pairs": int(sum(ppc)), "evals": pe,
+                        "evals_per_s": pe / (float(np.median(pt)) / 1000.0)}
+        res["speedup_vs_plain"] = res["plain"]["ms_per_step"] / res["ms_per_step"]
+        log(f"# plain batch: {res['plain']['ms_per_step']:.3f} ms")
+        del g, b
+        torch.cuda.empty_cache()
+    res["speedup_vs_per_view_calls"] = res["ms_per_view_calls"] / res["ms_per_step"]
+    res["speedup_graph_vs_eager"] = res["ms_eager"] / res["ms_per_step"]
+    st = res["stages_ms"]
+    res["roofline_raster_bwd"] = dict(**_alu(OPS_EXAMINE * fwd_e + OPS_BLEND_BWD * blended,
+                                             st["raster_bwd"]))
+    res["roofline_raster_fwd"] = dict(**_alu(OPS_EXAMINE * fwd_e + OPS_BLEND_FWD * blended,
+                                             st["raster_fwd"]))
+    return res
+
+
+def _alu(ops, t_ms):
+    a = ops / (t_ms / 1000.0) / 1e12
+    return {"bound": "alu", "achieved": a, "peak": PEAK_VALU / 1e12, "unit": "T lane-ops/s",
+            "frac": a / (PEAK_VALU / 1e12)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -229,10 +381,7 @@ def main():
 
     # rooflines: the two raster kernels against FP32 VALU issue, the binning
     # stage against HBM (bytes the implementation has to move)
-    def alu(ops, t_ms):
-        a = ops / (t_ms / 1000.0) / 1e12
-        return {"bound": "alu", "achieved": a, "peak": PEAK_VALU / 1e12, "unit": "T lane-ops/s",
-                "frac": a / (PEAK_VALU / 1e12)}
+    alu = _alu
     n = sc.n
     roof_bwd = dict(kernel="raster_bwd_kernel<16,1,1>",
                     **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_BWD * blended, stage["raster_bwd"]),
@@ -267,6 +416,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dil, args.cpu_seconds)
+    if args.batched:
+        del dil
+        torch.cuda.empty_cache()
+        out["batched"] = run_batched(args, api, torch, np)
     print(json.dumps(out), flush=True)
 
 

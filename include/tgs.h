@@ -25,7 +25,9 @@
  *    integer coordinates.
  *  - Device work is enqueued on the given stream; calls return before it
  *    finishes, except tgs_forward / tgs_bin_sort, which read the pair count
- *    back to the host once (see tgs_bin_sort).
+ *    back to the host once (see tgs_bin_sort), and tgs_pair_counts.  The
+ *    batched calls (tgs_batch_*) never synchronise, so a whole fitting step
+ *    of several views can be captured in one HIP graph.
  *  - Arguments are validated on the host before any HIP call; a failing call
  *    has enqueued nothing.  No C++ exception crosses this interface.
  *    tgs_last_error() returns a thread-local description of the last failure.
@@ -80,7 +82,10 @@ typedef struct tgs_options {
     int32_t tile;            /* tile edge T in downsampled pixels: 8, 16 or 32.
                                 The paper fixes 16 (Sec. 4.1); T changes which
                                 Gaussians a pixel considers, hence the result.  */
-    int32_t reserved;        /* must be 0                                        */
+    int32_t lds_batch;       /* splat records staged in LDS per round by the
+                                rasterizer: 64, 128 or 256, or 0 for the default
+                                of the tile size.  Speed only; results do not
+                                depend on it.                                    */
     float bg[3];             /* background colour added with the final T         */
     uint32_t flags;          /* must be 0                                        */
 } tgs_options;
@@ -140,7 +145,28 @@ typedef struct tgs_state {
                                          (tile, depth, index) order                      */
     uint64_t off_ranges;         /* out: uint32[num_tiles][2], [start, end) per tile      */
     uint64_t off_grad2d;         /* out: float[n][9], dL/d(u,v,A,B,C,o,r,g,b) (backward)  */
+    uint64_t off_pair_count;     /* out: uint32, the pair count on the device; above
+                                         pair_capacity when a batched bin/sort overflowed */
 } tgs_state;
+
+/* st->pair_count after a batched bin/sort, until tgs_pair_counts reads the
+ * device count back. */
+#define TGS_PAIR_COUNT_PENDING UINT64_MAX
+
+/* Most views of one batched call. */
+#define TGS_MAX_VIEWS 16
+
+/* Per-view device buffers of the batched calls. */
+typedef struct tgs_view_io {
+    float* image;            /* [3][H_ds][W_ds]; written by the forward, read by the backward */
+    float* t_final;          /* optional [H_ds][W_ds] float, as tgs_raster_fwd               */
+    uint32_t* last_contrib;  /* optional [H_ds][W_ds]                                        */
+    uint32_t* n_eval;        /* optional [H_ds][W_ds]                                        */
+    uint32_t* n_blend;       /* optional [H_ds][W_ds]                                        */
+    const float* target;     /* [3][H][W] full-resolution target (tgs_batch_l1_grad)         */
+    float* dL_dimage;        /* [3][H_ds][W_ds]; written by tgs_batch_l1_grad, read by the
+                                backward                                                    */
+} tgs_view_io;
 
 typedef struct tgs_context tgs_context;
 
@@ -236,6 +262,91 @@ tgs_status tgs_backward(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
                         const tgs_dilation* dil, const tgs_options* opt, const tgs_state* st,
                         const float* image, const float* dL_dimage, const tgs_grads* out,
                         float* pos_stat, float* col_stat, uint8_t* visible, void* stream);
+
+/* ---- Batched views (several cameras and dilation patterns, one Gaussian set).
+ *
+ * The views of one call share the Gaussians, the tile size, the LDS batch
+ * and the background; each has its own camera, dilation pattern and state
+ * (workspace), and the workspaces must not overlap.  1 <= views <=
+ * TGS_MAX_VIEWS.  Each call enqueues a fixed sequence of kernels and never
+ * reads back from the device, so the sequence can be captured in a graph and
+ * replayed.  The preprocess forward and backward and the rasterizer forward
+ * and backward are single launches covering every view; tile/Gaussian
+ * binning runs per view.  A failing call has enqueued nothing, except the
+ * composite tgs_batch_forward / tgs_batch_backward, whose arguments are all
+ * checked first as well.  Results of each view are those of the single-view
+ * calls on the same camera and pattern, up to the order of float additions
+ * in the summed gradients.
+ *
+ * Pair capacity: every view's binning writes its pair count to the device
+ * and, when the count exceeds the view's pair_capacity, emits no pair and
+ * renders the background with zero gradients.  tgs_pair_counts reads the
+ * counts back and reports TGS_ERR_CAPACITY; the caller then grows the
+ * workspaces and repeats the step. */
+
+/* Stage (a) for every view: one launch that reads the parameters once and
+ * writes every view's records and tiles_touched (as tgs_preprocess_fwd). */
+tgs_status tgs_batch_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                                    const tgs_camera* cams, const tgs_dilation* dils,
+                                    const tgs_options* opt, tgs_state* states, void* stream);
+
+/* Stage (b) for every view (as tgs_bin_sort, without the readback): the
+ * pair count stays on the device and a view whose pairs exceed its capacity
+ * gets empty ranges.  Sets states[v].pair_count to TGS_PAIR_COUNT_PENDING. */
+tgs_status tgs_batch_bin_sort(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                              const tgs_camera* cams, const tgs_dilation* dils,
+                              const tgs_options* opt, tgs_state* states, void* stream);
+
+/* Stage (c) for every view: one launch over the tiles of all views (as
+ * tgs_raster_fwd; outputs in io[v], image required). */
+tgs_status tgs_batch_raster_fwd(tgs_context* ctx, int64_t n, int32_t views,
+                                const tgs_camera* cams, const tgs_dilation* dils,
+                                const tgs_options* opt, const tgs_state* states,
+                                const tgs_view_io* io, void* stream);
+
+/* Stages (a)-(c) for every view, the three calls above in order. */
+tgs_status tgs_batch_forward(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                             const tgs_camera* cams, const tgs_dilation* dils,
+                             const tgs_options* opt, tgs_state* states, const tgs_view_io* io,
+                             void* stream);
+
+/* The L1 loss and its gradient (as tgs_l1_grad) for every view: reads
+ * io[v].image and io[v].target, writes io[v].dL_dimage.  loss: device
+ * double[views], overwritten (may be NULL). */
+tgs_status tgs_batch_l1_grad(tgs_context* ctx, int32_t views, const tgs_camera* cams,
+                             const tgs_dilation* dils, const tgs_view_io* io, double* loss,
+                             void* stream);
+
+/* Stage (d1) for every view: one launch over the tiles of all views, from
+ * io[v].image and io[v].dL_dimage into each view's grad2d (as
+ * tgs_raster_bwd). */
+tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views,
+                                const tgs_camera* cams, const tgs_dilation* dils,
+                                const tgs_options* opt, const tgs_state* states,
+                                const tgs_view_io* io, void* stream);
+
+/* Stage (d2) for every view: one launch that sums the parameter gradients
+ * over the views (the Gaussians are shared, so the gradient of the summed
+ * loss is the sum).  The statistics of Sec. 4.3 are summed over the views
+ * where the Gaussian is visible and visible[i] counts those views.  Each of
+ * pos_stat, col_stat, visible may be NULL. */
+tgs_status tgs_batch_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                                    const tgs_camera* cams, const tgs_dilation* dils,
+                                    const tgs_options* opt, const tgs_state* states,
+                                    const tgs_grads* out, float* pos_stat, float* col_stat,
+                                    uint8_t* visible, void* stream);
+
+/* Stages (d1)-(d2) for every view, the two calls above in order. */
+tgs_status tgs_batch_backward(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                              const tgs_camera* cams, const tgs_dilation* dils,
+                              const tgs_options* opt, const tgs_state* states,
+                              const tgs_view_io* io, const tgs_grads* out, float* pos_stat,
+                              float* col_stat, uint8_t* visible, void* stream);
+
+/* Reads the device pair count of every state back (one stream
+ * synchronisation) into states[v].pair_count.  Returns TGS_ERR_CAPACITY if
+ * any count exceeds its pair_capacity (that view rendered nothing). */
+tgs_status tgs_pair_counts(tgs_context* ctx, int32_t views, tgs_state* states, void* stream);
 
 #ifdef __cplusplus
 }

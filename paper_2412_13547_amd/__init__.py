@@ -5,4 +5,4 @@ The compute path is the C-ABI library ``libtgs.so`` built from ``csrc/`` (HIP).
 Importing the package loads nothing; the library is loaded on first use of
 ``api`` and a missing build raises instead of falling back to anything else.
 """
-__all__ = ["api", "scenes"]
+__all__ = ["api", "autotune", "scenes"]

@@ -21,7 +21,13 @@ EXPORTED = (
     "tgs_status_str", "tgs_last_error", "tgs_version", "tgs_create", "tgs_destroy",
     "tgs_query_sizes", "tgs_preprocess_fwd", "tgs_bin_sort", "tgs_raster_fwd", "tgs_forward",
     "tgs_l1_grad", "tgs_raster_bwd", "tgs_preprocess_bwd", "tgs_backward",
+    "tgs_batch_preprocess_fwd", "tgs_batch_bin_sort", "tgs_batch_raster_fwd",
+    "tgs_batch_forward", "tgs_batch_l1_grad", "tgs_batch_raster_bwd", "tgs_batch_preprocess_bwd",
+    "tgs_batch_backward", "tgs_pair_counts",
 )
+
+MAX_VIEWS = 16
+PAIR_COUNT_PENDING = (1 << 64) - 1
 
 
 class tgs_camera(C.Structure):
@@ -41,7 +47,7 @@ class tgs_gaussians(C.Structure):
 
 
 class tgs_options(C.Structure):
-    _fields_ = [("tile", C.c_int32), ("reserved", C.c_int32), ("bg", C.c_float * 3),
+    _fields_ = [("tile", C.c_int32), ("lds_batch", C.c_int32), ("bg", C.c_float * 3),
                 ("flags", C.c_uint32)]
 
 
@@ -63,7 +69,13 @@ class tgs_state(C.Structure):
                 ("off_records", C.c_uint64), ("off_tiles_touched", C.c_uint64),
                 ("off_depth_order", C.c_uint64),
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
-                ("off_grad2d", C.c_uint64)]
+                ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64)]
+
+
+class tgs_view_io(C.Structure):
+    _fields_ = [("image", C.c_void_p), ("t_final", C.c_void_p), ("last_contrib", C.c_void_p),
+                ("n_eval", C.c_void_p), ("n_blend", C.c_void_p), ("target", C.c_void_p),
+                ("dL_dimage", C.c_void_p)]
 
 
 _P = C.POINTER
@@ -97,6 +109,29 @@ def _declare(lib):
         "tgs_backward": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
                                    _P(tgs_options), _P(tgs_state), vp, vp, _P(tgs_grads), vp, vp,
                                    vp, vp]),
+        "tgs_batch_forward": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
+                                        _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
+                                        _P(tgs_view_io), vp]),
+        "tgs_batch_l1_grad": (C.c_int, [vp, C.c_int32, _P(tgs_camera), _P(tgs_dilation),
+                                        _P(tgs_view_io), vp, vp]),
+        "tgs_batch_backward": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
+                                         _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
+                                         _P(tgs_view_io), _P(tgs_grads), vp, vp, vp, vp]),
+        "tgs_pair_counts": (C.c_int, [vp, C.c_int32, _P(tgs_state), vp]),
+        "tgs_batch_preprocess_fwd": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
+                                               _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
+                                               vp]),
+        "tgs_batch_bin_sort": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
+                                         _P(tgs_dilation), _P(tgs_options), _P(tgs_state), vp]),
+        "tgs_batch_raster_fwd": (C.c_int, [vp, C.c_int64, C.c_int32, _P(tgs_camera),
+                                           _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
+                                           _P(tgs_view_io), vp]),
+        "tgs_batch_raster_bwd": (C.c_int, [vp, C.c_int64, C.c_int32, _P(tgs_camera),
+                                           _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
+                                           _P(tgs_view_io), vp]),
+        "tgs_batch_preprocess_bwd": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
+                                               _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
+                                               _P(tgs_grads), vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -147,10 +182,10 @@ def dilation_struct(stride=1, off_x=0, off_y=0) -> tgs_dilation:
     return tgs_dilation(int(stride), int(off_x), int(off_y))
 
 
-def options_struct(tile=16, bg=(0.0, 0.0, 0.0)) -> tgs_options:
+def options_struct(tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0) -> tgs_options:
     o = tgs_options()
     o.tile = int(tile)
-    o.reserved = 0
+    o.lds_batch = int(lds_batch)
     for k in range(3):
         o.bg[k] = float(bg[k])
     o.flags = 0
@@ -239,15 +274,16 @@ class View:
     """
 
     def __init__(self, ctx: Context, n: int, cam, stride=1, off_x=0, off_y=0, tile=16,
-                 bg=(0.0, 0.0, 0.0), pair_capacity: int | None = None):
+                 bg=(0.0, 0.0, 0.0), pair_capacity: int | None = None, lds_batch: int = 0,
+                 state: tgs_state | None = None):
         import torch
         self.ctx = ctx
         self.n = int(n)
         self.cam = cam
         self.cam_s = camera_struct(cam)
         self.dil = dilation_struct(stride, off_x, off_y)
-        self.opt = options_struct(tile, bg)
-        self.state = tgs_state()
+        self.opt = options_struct(tile, bg, lds_batch)
+        self.state = state if state is not None else tgs_state()
         self.workspace = None
         self.sizes = query_sizes(self.n, self.cam_s, self.dil, self.opt, 0)
         self._torch = torch
@@ -377,3 +413,146 @@ class View:
 
     def grad2d(self):
         return self._view(self.state.off_grad2d, self.n * 9, self._torch.float32).view(self.n, 9)
+
+
+def _grads_struct(grads: DeviceScene) -> tgs_grads:
+    return tgs_grads(_ptr(grads.means), _ptr(grads.scales), _ptr(grads.quats),
+                     _ptr(grads.opacities), _ptr(grads.sh))
+
+
+class Batch:
+    """Up to MAX_VIEWS views (camera + dilation pattern) of one Gaussian set,
+    processed by the batched calls: one preprocess launch, per-view binning,
+    one rasterizer launch per direction, one summed preprocess backward.
+    None of its step methods synchronises, so ``step`` can be captured in a
+    HIP graph (``torch.cuda.CUDAGraph``) once the capacities fit.
+
+    views: sequence of (camera, stride, off_x, off_y).  Images and upstream
+    gradients are allocated here; targets are full-resolution [3][H][W]
+    float32 device tensors set with ``set_targets``."""
+
+    def __init__(self, ctx: Context, n: int, views, tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0,
+                 pair_capacity=None, counts: bool = False):
+        import torch
+        self._torch = torch
+        nv = len(views)
+        if not 1 <= nv <= MAX_VIEWS:
+            raise ValueError(f"a batch holds 1..{MAX_VIEWS} views, got {nv}")
+        self.ctx, self.n, self.nv = ctx, int(n), nv
+        self.states = (tgs_state * nv)()
+        caps = pair_capacity if isinstance(pair_capacity, (list, tuple)) else [pair_capacity] * nv
+        self.views = [View(ctx, n, cam, stride, ox, oy, tile, bg, pair_capacity=caps[k],
+                           lds_batch=lds_batch, state=self.states[k])
+                      for k, (cam, stride, ox, oy) in enumerate(views)]
+        self.cams = (tgs_camera * nv)(*[v.cam_s for v in self.views])
+        self.dils = (tgs_dilation * nv)(*[v.dil for v in self.views])
+        self.opt = options_struct(tile, bg, lds_batch)
+        self.io = (tgs_view_io * nv)()
+        f32, i32 = torch.float32, torch.int32
+        self.images = [torch.zeros(v.image_shape, dtype=f32, device="cuda") for v in self.views]
+        self.dL = [torch.zeros(v.image_shape, dtype=f32, device="cuda") for v in self.views]
+        self.targets = [None] * nv
+        self.loss = torch.zeros(nv, dtype=torch.float64, device="cuda")
+        self.t_final = self.last_contrib = self.n_eval = self.n_blend = None
+        if counts:
+            px = lambda v, dt: torch.zeros(v.image_shape[1:], dtype=dt, device="cuda")
+            self.t_final = [px(v, f32) for v in self.views]
+            self.last_contrib = [px(v, i32) for v in self.views]
+            self.n_eval = [px(v, i32) for v in self.views]
+            self.n_blend = [px(v, i32) for v in self.views]
+        for k in range(nv):
+            io = self.io[k]
+            io.image = _ptr(self.images[k])
+            io.dL_dimage = _ptr(self.dL[k])
+            if counts:
+                io.t_final = _ptr(self.t_final[k])
+                io.last_contrib = _ptr(self.last_contrib[k])
+                io.n_eval = _ptr(self.n_eval[k])
+                io.n_blend = _ptr(self.n_blend[k])
+
+    def set_targets(self, targets):
+        for k, t in enumerate(targets):
+            v = self.views[k]
+            assert tuple(t.shape) == (3, v.cam_s.height, v.cam_s.width) and t.is_contiguous()
+            self.targets[k] = t
+            self.io[k].target = _ptr(t)
+
+    def forward(self, scene: DeviceScene, stream=None):
+        g = scene.struct()
+        check(lib().tgs_batch_forward(self.ctx.handle, C.byref(g), self.nv, self.cams, self.dils,
+                                      C.byref(self.opt), self.states, self.io, _stream(stream)))
+        return self.images
+
+    # -- stages (each one batched call) --------------------------------------
+    def preprocess_fwd(self, scene: DeviceScene, stream=None):
+        g = scene.struct()
+        check(lib().tgs_batch_preprocess_fwd(self.ctx.handle, C.byref(g), self.nv, self.cams,
+                                             self.dils, C.byref(self.opt), self.states,
+                                             _stream(stream)))
+
+    def bin_sort(self, scene: DeviceScene, stream=None):
+        g = scene.struct()
+        check(lib().tgs_batch_bin_sort(self.ctx.handle, C.byref(g), self.nv, self.cams, self.dils,
+                                       C.byref(self.opt), self.states, _stream(stream)))
+
+    def raster_fwd(self, stream=None):
+        check(lib().tgs_batch_raster_fwd(self.ctx.handle, self.n, self.nv, self.cams, self.dils,
+                                         C.byref(self.opt), self.states, self.io, _stream(stream)))
+
+    def raster_bwd(self, stream=None):
+        check(lib().tgs_batch_raster_bwd(self.ctx.handle, self.n, self.nv, self.cams, self.dils,
+                                         C.byref(self.opt), self.states, self.io, _stream(stream)))
+
+    def preprocess_bwd(self, scene: DeviceScene, grads: DeviceScene, pos_stat=None, col_stat=None,
+                       visible=None, stream=None):
+        g = scene.struct()
+        out = _grads_struct(grads)
+        check(lib().tgs_batch_preprocess_bwd(self.ctx.handle, C.byref(g), self.nv, self.cams,
+                                             self.dils, C.byref(self.opt), self.states,
+                                             C.byref(out), _ptr(pos_stat), _ptr(col_stat),
+                                             _ptr(visible), _stream(stream)))
+
+    def l1_grad(self, stream=None):
+        if any(t is None for t in self.targets):
+            raise ValueError("set_targets first")
+        check(lib().tgs_batch_l1_grad(self.ctx.handle, self.nv, self.cams, self.dils, self.io,
+                                      _ptr(self.loss), _stream(stream)))
+        return self.loss
+
+    def backward(self, scene: DeviceScene, grads: DeviceScene, pos_stat=None, col_stat=None,
+                 visible=None, stream=None):
+        g = scene.struct()
+        out = _grads_struct(grads)
+        check(lib().tgs_batch_backward(self.ctx.handle, C.byref(g), self.nv, self.cams, self.dils,
+                                       C.byref(self.opt), self.states, self.io, C.byref(out),
+                                       _ptr(pos_stat), _ptr(col_stat), _ptr(visible),
+                                       _stream(stream)))
+        return grads
+
+    def step(self, scene: DeviceScene, grads: DeviceScene, pos_stat=None, col_stat=None,
+             visible=None, stream=None):
+        """Forward, L1 loss gradient and backward of every view (no synchronisation)."""
+        self.forward(scene, stream)
+        self.l1_grad(stream)
+        self.backward(scene, grads, pos_stat, col_stat, visible, stream)
+
+    def pair_counts(self, stream=None) -> list:
+        """Device pair counts read back (synchronises); raises TgsError on overflow."""
+        st = lib().tgs_pair_counts(self.ctx.handle, self.nv, self.states, _stream(stream))
+        counts = [int(s.pair_count) for s in self.states]
+        if st != TGS_OK:
+            raise TgsError(st, lib().tgs_last_error().decode())
+        return counts
+
+    def fit_capacity(self, scene: DeviceScene, slack: float = 1.1, tries: int = 4) -> list:
+        """Run forwards until every view's pairs fit its workspace; returns the counts.
+        Workspaces are re-allocated, so capture graphs only after this."""
+        for _ in range(tries):
+            self.forward(scene)
+            lib().tgs_pair_counts(self.ctx.handle, self.nv, self.states, _stream(None))
+            over = [k for k, s in enumerate(self.states) if s.pair_count > s.pair_capacity]
+            if not over:
+                return [int(s.pair_count) for s in self.states]
+            for k in over:
+                self.views[k].reserve(int(self.states[k].pair_count * slack) + 4096)
+        raise TgsError(TGS_ERR_CAPACITY, "pair capacity did not converge")

@@ -76,8 +76,10 @@ tgs_status check_options(const tgs_options* opt) {
     if (!opt) return fail(TGS_ERR_INVALID_ARG, "options is NULL");
     if (opt->tile != 8 && opt->tile != 16 && opt->tile != 32)
         return fail(TGS_ERR_INVALID_ARG, "tile %d must be 8, 16 or 32", opt->tile);
-    if (opt->reserved != 0 || opt->flags != 0)
-        return fail(TGS_ERR_INVALID_ARG, "reserved option fields must be 0");
+    if (opt->lds_batch != 0 && opt->lds_batch != 64 && opt->lds_batch != 128 &&
+        opt->lds_batch != 256)
+        return fail(TGS_ERR_INVALID_ARG, "lds_batch %d must be 0, 64, 128 or 256", opt->lds_batch);
+    if (opt->flags != 0) return fail(TGS_ERR_INVALID_ARG, "option flags must be 0");
     for (int c = 0; c < 3; ++c)
         if (!finitef(opt->bg[c])) return fail(TGS_ERR_INVALID_ARG, "background is not finite");
     return TGS_OK;
@@ -132,11 +134,16 @@ int key_bits_for(int64_t num_tiles) {
 
 // The raster stages read ranges and pair values written by tgs_bin_sort for
 // the same tile grid; refuse a state that was not binned (or was binned for
-// another grid) instead of reading stale indices.
-tgs_status check_binned(const tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid) {
+// another grid) instead of reading stale indices.  A batched bin leaves the
+// count on the device (pending), where the kernels check it themselves.
+tgs_status check_binned(const tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid,
+                        bool allow_pending) {
     if (st->key_bits == 0 || st->key_bits != uint32_t(key_bits_for(grid.num_tiles())))
         return fail(TGS_ERR_INVALID_ARG, "state has not been binned for this tile grid");
-    if (st->pair_count > st->pair_capacity)
+    if (st->pair_count == TGS_PAIR_COUNT_PENDING) {
+        if (!allow_pending)
+            return fail(TGS_ERR_INVALID_ARG, "pair count pending: call tgs_pair_counts first");
+    } else if (st->pair_count > st->pair_capacity)
         return fail(TGS_ERR_CAPACITY, "state holds %llu pairs, capacity %llu",
                     (unsigned long long)st->pair_count, (unsigned long long)st->pair_capacity);
     if (st->off_pair_vals != L.pair_vals)
@@ -144,7 +151,8 @@ tgs_status check_binned(const tgs_state* st, const tgs::Layout& L, const tgs::Gr
     return TGS_OK;
 }
 
-void publish_offsets(tgs_state* st, const tgs::Layout& L, int depth_buf) {
+void publish_offsets(tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid, int depth_buf) {
+    st->off_pair_count = L.row_start + 4 * uint64_t(grid.gy);
     st->off_records = L.records;
     st->off_tiles_touched = L.tiles_touched;
     st->off_depth_order = L.depth_val[depth_buf];
@@ -156,6 +164,78 @@ void publish_offsets(tgs_state* st, const tgs::Layout& L, int depth_buf) {
 tgs_status use_device(tgs_context* ctx) {
     if (!ctx) return fail(TGS_ERR_INVALID_ARG, "context is NULL");
     TGS_HIP(hipSetDevice(ctx->device));
+    return TGS_OK;
+}
+
+// The table entry of one view for the preprocess kernels.
+tgs::PrepView prep_view(const tgs_camera& cam, const tgs::Grid& grid, uint8_t* ws,
+                        const tgs::Layout& L) {
+    tgs::PrepView v{};
+    v.cam = tgs::make_cam(cam);
+    v.grid = grid;
+    v.rec = reinterpret_cast<tgs_record*>(ws + L.records);
+    v.touched = reinterpret_cast<uint32_t*>(ws + L.tiles_touched);
+    v.depth_key = reinterpret_cast<uint32_t*>(ws + L.depth_key[0]);
+    v.depth_val = reinterpret_cast<uint32_t*>(ws + L.depth_val[0]);
+    v.g2d = reinterpret_cast<const float*>(ws + L.grad2d);
+    return v;
+}
+
+// The table entry of one binned view for the raster kernels.
+tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const tgs_state& st,
+                            const tgs::Layout& L) {
+    auto* ws = static_cast<uint8_t*>(st.workspace);
+    tgs::RasterView v{};
+    v.grid = grid;
+    v.capacity = uint32_t(st.pair_capacity);
+    for (int c = 0; c < 3; ++c) v.bg[c] = opt.bg[c];
+    v.rec = reinterpret_cast<const float4*>(ws + L.records);
+    v.ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
+    v.vals = reinterpret_cast<const uint32_t*>(ws + L.pair_vals);
+    v.pair_count = reinterpret_cast<const uint32_t*>(ws + L.row_start) + grid.gy;
+    v.g2d = reinterpret_cast<float*>(ws + L.grad2d);
+    return v;
+}
+
+void add_raster_view(tgs::RasterViews& t, const tgs::RasterView& v) {
+    if (t.count == 0) t.first_block[0] = 0;
+    t.v[t.count] = v;
+    t.first_block[t.count + 1] = t.first_block[t.count] + uint32_t(v.grid.num_tiles());
+    ++t.count;
+}
+
+int lds_batch_of(const tgs_options& opt) {
+    return opt.lds_batch ? opt.lds_batch : tgs::default_lds_batch(opt.tile);
+}
+
+// Depth sort and the pair counts per (tile row, chunk), up to the row starts
+// and the device pair count.  Returns the depth-sort result buffer.
+tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
+                          hipStream_t strm, int* dres, const uint32_t** order) {
+    auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+    auto* partials = reinterpret_cast<uint64_t*>(ws + L.scan_partials);
+    // Gaussians by depth key (stable; culled and off-screen ones last)
+    uint32_t* dkeys[2] = {u32(L.depth_key[0]), u32(L.depth_key[1])};
+    uint32_t* dvals[2] = {u32(L.depth_val[0]), u32(L.depth_val[1])};
+    TGS_HIP(tgs::radix_sort(dkeys, dvals, uint64_t(n), 32, u32(L.sort_counts), partials, dres, strm));
+    *order = dvals[*dres];
+    // pairs per (tile row, chunk of the depth order); scan -> row buckets
+    const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_chunks(n);
+    TGS_HIP(tgs::launch_row_counts(ws, L, *order, n, grid, strm));
+    TGS_HIP(tgs::exclusive_scan_u32(u32(L.rowtot), u32(L.rowtot), nrow, partials, true, strm));
+    TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, strm));
+    return TGS_OK;
+}
+
+// Emission into row buckets, then a stable counting sort by column per row,
+// which also yields the per-tile ranges.  `slices` bounds the column-sort
+// slices from above; the kernels skip all work when the device pair count
+// exceeds the capacity.
+tgs_status enqueue_emit(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
+                        const uint32_t* order, uint64_t slices, uint32_t capacity,
+                        hipStream_t strm) {
+    TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, capacity, strm));
+    TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, capacity, strm));
     return TGS_OK;
 }
 
@@ -212,21 +292,7 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     return L;
 }
 
-RasterTuning raster_tuning() {
-    static const RasterTuning t = [] {
-        RasterTuning r;
-        if (const char* e = std::getenv("TGS_RASTER_PPT")) {
-            const int v = std::atoi(e);
-            if (v == 1 || v == 2 || v == 4) r.ppt = v;
-        }
-        if (const char* e = std::getenv("TGS_TILE_ORDER")) {
-            const int v = std::atoi(e);
-            if (v == 0 || v == 1) r.order = v;
-        }
-        return r;
-    }();
-    return t;
-}
+int default_lds_batch(int tile) { return tile == 8 ? 64 : 256; }
 
 CamDev make_cam(const tgs_camera& c) {
     CamDev d{};
@@ -276,6 +342,7 @@ tgs_status tgs_create(int device, tgs_context** out) {
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return fail(TGS_ERR_NO_DEVICE, "device %d not available (%d devices)", device, count);
     TGS_HIP(hipSetDevice(device));
+    TGS_HIP(tgs::prepare_binning_kernels());
     auto* ctx = new (std::nothrow) tgs_context{device, nullptr};
     if (!ctx) return fail(TGS_ERR_HIP, "out of host memory");
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kPinnedBytes,
@@ -328,12 +395,13 @@ tgs_status tgs_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, const tg
     tgs::Layout L;
     if ((s = check_state(st, g->n, grid, &L)) != TGS_OK) return s;
     if ((s = use_device(ctx)) != TGS_OK) return s;
-    auto* ws = static_cast<uint8_t*>(st->workspace);
-    TGS_HIP(tgs::launch_preprocess_fwd(*g, tgs::make_cam(*cam), grid, ws, L,
-                                       static_cast<hipStream_t>(stream)));
+    tgs::PrepViews t{};
+    t.count = 1;
+    t.v[0] = prep_view(*cam, grid, static_cast<uint8_t*>(st->workspace), L);
+    TGS_HIP(tgs::launch_preprocess_fwd(*g, t, static_cast<hipStream_t>(stream)));
     st->pair_count = 0;
     st->key_bits = 0;     // not binned yet
-    publish_offsets(st, L, 0);
+    publish_offsets(st, L, grid, 0);
     return TGS_OK;
 }
 
@@ -350,23 +418,12 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     if ((s = use_device(ctx)) != TGS_OK) return s;
     auto* ws = static_cast<uint8_t*>(st->workspace);
     auto strm = static_cast<hipStream_t>(stream);
-    const int64_t n = g->n;
-    auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
-    auto* partials = reinterpret_cast<uint64_t*>(ws + L.scan_partials);
-
-    // 1. Gaussians by depth key (stable; culled and off-screen ones last)
-    uint32_t* dkeys[2] = {u32(L.depth_key[0]), u32(L.depth_key[1])};
-    uint32_t* dvals[2] = {u32(L.depth_val[0]), u32(L.depth_val[1])};
     int dres = 0;
-    TGS_HIP(tgs::radix_sort(dkeys, dvals, uint64_t(n), 32, u32(L.sort_counts), partials, &dres, strm));
-    const uint32_t* order = dvals[dres];
-    // 2. pairs per (tile row, chunk of the depth order); scan -> row buckets
-    const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_chunks(n);
-    TGS_HIP(tgs::launch_row_counts(ws, L, order, n, grid, strm));
-    TGS_HIP(tgs::exclusive_scan_u32(u32(L.rowtot), u32(L.rowtot), nrow, partials, true, strm));
-    TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, strm));
-    // 3. row starts (and the pair count) back to the host
-    TGS_HIP(hipMemcpyAsync(ctx->pinned, u32(L.row_start), (uint64_t(grid.gy) + 1) * 4,
+    const uint32_t* order = nullptr;
+    if ((s = enqueue_counts(ws, L, grid, g->n, strm, &dres, &order)) != TGS_OK) return s;
+    // row starts (and the pair count) back to the host: the column sort is
+    // then launched with exactly as many slices as there are
+    TGS_HIP(hipMemcpyAsync(ctx->pinned, ws + L.row_start, (uint64_t(grid.gy) + 1) * 4,
                            hipMemcpyDeviceToHost, strm));
     TGS_HIP(hipStreamSynchronize(strm));
     const uint32_t* rs = reinterpret_cast<const uint32_t*>(ctx->pinned);
@@ -375,14 +432,12 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     for (int ty = 0; ty < grid.gy; ++ty) slices += (uint64_t(rs[ty + 1] - rs[ty]) + tgs::kSlice - 1) / tgs::kSlice;
     st->pair_count = P;
     st->key_bits = 0;
-    publish_offsets(st, L, dres);
+    publish_offsets(st, L, grid, dres);
     if (P > st->pair_capacity)
         return fail(TGS_ERR_CAPACITY, "%llu pairs needed, capacity %llu", (unsigned long long)P,
                     (unsigned long long)st->pair_capacity);
-    // 4. emit into row buckets, then a stable counting sort by column per row,
-    //    which also yields the per-tile ranges
-    TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, strm));
-    TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, strm));
+    if ((s = enqueue_emit(ws, L, grid, g->n, order, slices, uint32_t(st->pair_capacity), strm)) != TGS_OK)
+        return s;
     st->key_bits = uint32_t(key_bits_for(grid.num_tiles()));   // marks the state as binned
     return TGS_OK;
 }
@@ -399,13 +454,18 @@ tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     if (!image) return fail(TGS_ERR_INVALID_ARG, "image is NULL");
     tgs::Layout L;
     if ((s = check_state(st, n, grid, &L)) != TGS_OK) return s;
-    if ((s = check_binned(st, L, grid)) != TGS_OK) return s;
+    if ((s = check_binned(st, L, grid, true)) != TGS_OK) return s;
     if ((s = use_device(ctx)) != TGS_OK) return s;
-    auto* ws = static_cast<uint8_t*>(st->workspace);
-    TGS_HIP(tgs::launch_raster_fwd(grid, tgs::raster_tuning(), opt->bg, ws, L,
-                                   reinterpret_cast<const uint32_t*>(ws + st->off_pair_vals),
-                                   uint32_t(st->pair_count), image, t_final, last_contrib, n_eval,
-                                   n_blend, static_cast<hipStream_t>(stream)));
+    tgs::RasterView v = raster_view(grid, *opt, *st, L);
+    v.image = image;
+    v.t_final = t_final;
+    v.last_contrib = last_contrib;
+    v.n_eval = n_eval;
+    v.n_blend = n_blend;
+    tgs::RasterViews t{};
+    add_raster_view(t, v);
+    TGS_HIP(tgs::launch_raster_fwd(opt->tile, lds_batch_of(*opt), t,
+                                   static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
 
@@ -445,15 +505,16 @@ tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     const tgs::Grid grid = tgs::make_grid(*cam, *dil, opt->tile);
     tgs::Layout L;
     if ((s = check_state(st, n, grid, &L)) != TGS_OK) return s;
-    if ((s = check_binned(st, L, grid)) != TGS_OK) return s;
+    if ((s = check_binned(st, L, grid, true)) != TGS_OK) return s;
     if ((s = use_device(ctx)) != TGS_OK) return s;
-    auto* ws = static_cast<uint8_t*>(st->workspace);
     auto strm = static_cast<hipStream_t>(stream);
-    auto* g2d = reinterpret_cast<float*>(ws + L.grad2d);
-    TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
-    TGS_HIP(tgs::launch_raster_bwd(grid, tgs::raster_tuning(), ws, L,
-                                   reinterpret_cast<const uint32_t*>(ws + st->off_pair_vals),
-                                   uint32_t(st->pair_count), image, dL_dimage, g2d, strm));
+    tgs::RasterView v = raster_view(grid, *opt, *st, L);
+    v.image = const_cast<float*>(image);
+    v.dL = dL_dimage;
+    TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(v.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
+    tgs::RasterViews t{};
+    add_raster_view(t, v);
+    TGS_HIP(tgs::launch_raster_bwd(opt->tile, lds_batch_of(*opt), t, strm));
     return TGS_OK;
 }
 
@@ -471,9 +532,11 @@ tgs_status tgs_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, const tg
     tgs::Layout L;
     if ((s = check_state(st, g->n, grid, &L)) != TGS_OK) return s;
     if ((s = use_device(ctx)) != TGS_OK) return s;
-    TGS_HIP(tgs::launch_preprocess_bwd(*g, tgs::make_cam(*cam),
-                                       static_cast<const uint8_t*>(st->workspace), L, *out, pos_stat,
-                                       col_stat, visible, static_cast<hipStream_t>(stream)));
+    tgs::PrepViews t{};
+    t.count = 1;
+    t.v[0] = prep_view(*cam, grid, static_cast<uint8_t*>(st->workspace), L);
+    TGS_HIP(tgs::launch_preprocess_bwd(*g, t, *out, pos_stat, col_stat, visible,
+                                       static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
 
@@ -487,6 +550,269 @@ tgs_status tgs_backward(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     if (s == TGS_OK)
         s = tgs_preprocess_bwd(ctx, g, cam, dil, opt, st, out, pos_stat, col_stat, visible, stream);
     return s;
+}
+
+// ---- batched views
+
+namespace {
+
+// Validation shared by the batched calls; fills the grids and layouts.
+tgs_status check_views(int64_t n, int32_t views, const tgs_camera* cams, const tgs_dilation* dils,
+                       const tgs_options* opt, const tgs_state* states, tgs::Grid* grids,
+                       tgs::Layout* Ls) {
+    if (n < 0) return fail(TGS_ERR_INVALID_ARG, "n < 0");
+    if (views < 1 || views > TGS_MAX_VIEWS)
+        return fail(TGS_ERR_INVALID_ARG, "views = %d must be in [1, %d]", views, TGS_MAX_VIEWS);
+    if (!cams || !dils || !states) return fail(TGS_ERR_INVALID_ARG, "a per-view array is NULL");
+    tgs_status s = check_options(opt);
+    if (s != TGS_OK) return s;
+    for (int v = 0; v < views; ++v) {
+        if ((s = check_common(&cams[v], &dils[v], opt)) != TGS_OK)
+            return fail(s, "view %d: %s", v, g_error.c_str());
+        grids[v] = tgs::make_grid(cams[v], dils[v], opt->tile);
+        if ((s = check_state(&states[v], n, grids[v], &Ls[v])) != TGS_OK)
+            return fail(s, "view %d: %s", v, g_error.c_str());
+        if (states[v].pair_capacity > uint64_t(UINT32_MAX))
+            return fail(TGS_ERR_UNSUPPORTED, "view %d: pair capacity above 2^32 - 1", v);
+    }
+    // workspaces must be disjoint: the views are processed concurrently
+    for (int a = 0; a < views; ++a) {
+        const auto a0 = reinterpret_cast<uintptr_t>(states[a].workspace);
+        for (int b = a + 1; b < views; ++b) {
+            const auto b0 = reinterpret_cast<uintptr_t>(states[b].workspace);
+            if (a0 < b0 + Ls[b].total && b0 < a0 + Ls[a].total)
+                return fail(TGS_ERR_INVALID_ARG, "workspaces of views %d and %d overlap", a, b);
+        }
+    }
+    return TGS_OK;
+}
+
+tgs_status check_binned_views(int32_t views, const tgs_state* states, const tgs::Grid* grids,
+                              const tgs::Layout* Ls) {
+    for (int v = 0; v < views; ++v) {
+        tgs_status s = check_binned(&states[v], Ls[v], grids[v], true);
+        if (s != TGS_OK) return fail(s, "view %d: %s", v, g_error.c_str());
+    }
+    return TGS_OK;
+}
+
+tgs_status check_io(int32_t views, const tgs_view_io* io, bool need_dL) {
+    if (!io) return fail(TGS_ERR_INVALID_ARG, "io is NULL");
+    for (int v = 0; v < views; ++v) {
+        if (!io[v].image) return fail(TGS_ERR_INVALID_ARG, "view %d: image is NULL", v);
+        if (need_dL && !io[v].dL_dimage)
+            return fail(TGS_ERR_INVALID_ARG, "view %d: dL_dimage is NULL", v);
+    }
+    return TGS_OK;
+}
+
+tgs_status check_grads(const tgs_gaussians* g, const tgs_grads* out) {
+    if (!out || (g->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacities || !out->sh)))
+        return fail(TGS_ERR_INVALID_ARG, "a gradient pointer is NULL");
+    return TGS_OK;
+}
+
+#define TGS_CHECK(expr)                      \
+    do {                                     \
+        tgs_status s_ = (expr);              \
+        if (s_ != TGS_OK) return s_;         \
+    } while (0)
+
+}  // namespace
+
+tgs_status tgs_batch_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                                    const tgs_camera* cams, const tgs_dilation* dils,
+                                    const tgs_options* opt, tgs_state* states, void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_gaussians(g));
+    TGS_CHECK(check_views(g->n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(use_device(ctx));
+    tgs::PrepViews pt{};
+    pt.count = views;
+    for (int v = 0; v < views; ++v)
+        pt.v[v] = prep_view(cams[v], grids[v], static_cast<uint8_t*>(states[v].workspace), Ls[v]);
+    TGS_HIP(tgs::launch_preprocess_fwd(*g, pt, static_cast<hipStream_t>(stream)));
+    for (int v = 0; v < views; ++v) {
+        states[v].pair_count = 0;
+        states[v].key_bits = 0;
+        publish_offsets(&states[v], Ls[v], grids[v], 0);
+    }
+    return TGS_OK;
+}
+
+tgs_status tgs_batch_bin_sort(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                              const tgs_camera* cams, const tgs_dilation* dils,
+                              const tgs_options* opt, tgs_state* states, void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_gaussians(g));
+    TGS_CHECK(check_views(g->n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(use_device(ctx));
+    auto strm = static_cast<hipStream_t>(stream);
+    for (int v = 0; v < views; ++v) {
+        tgs_state& st = states[v];
+        auto* ws = static_cast<uint8_t*>(st.workspace);
+        const uint32_t cap = uint32_t(st.pair_capacity);
+        int dres = 0;
+        const uint32_t* order = nullptr;
+        TGS_CHECK(enqueue_counts(ws, Ls[v], grids[v], g->n, strm, &dres, &order));
+        TGS_CHECK(enqueue_emit(ws, Ls[v], grids[v], g->n, order, tgs::bin_max_slices(cap, grids[v].gy),
+                               cap, strm));
+        publish_offsets(&st, Ls[v], grids[v], dres);
+        st.pair_count = TGS_PAIR_COUNT_PENDING;
+        st.key_bits = uint32_t(key_bits_for(grids[v].num_tiles()));
+    }
+    return TGS_OK;
+}
+
+tgs_status tgs_batch_raster_fwd(tgs_context* ctx, int64_t n, int32_t views, const tgs_camera* cams,
+                                const tgs_dilation* dils, const tgs_options* opt,
+                                const tgs_state* states, const tgs_view_io* io, void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_views(n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(check_io(views, io, false));
+    TGS_CHECK(check_binned_views(views, states, grids, Ls));
+    TGS_CHECK(use_device(ctx));
+    tgs::RasterViews rt{};
+    for (int v = 0; v < views; ++v) {
+        tgs::RasterView rv = raster_view(grids[v], *opt, states[v], Ls[v]);
+        rv.image = io[v].image;
+        rv.t_final = io[v].t_final;
+        rv.last_contrib = io[v].last_contrib;
+        rv.n_eval = io[v].n_eval;
+        rv.n_blend = io[v].n_blend;
+        add_raster_view(rt, rv);
+    }
+    TGS_HIP(tgs::launch_raster_fwd(opt->tile, lds_batch_of(*opt), rt,
+                                   static_cast<hipStream_t>(stream)));
+    return TGS_OK;
+}
+
+tgs_status tgs_batch_forward(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                             const tgs_camera* cams, const tgs_dilation* dils,
+                             const tgs_options* opt, tgs_state* states, const tgs_view_io* io,
+                             void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_gaussians(g));
+    TGS_CHECK(check_views(g->n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(check_io(views, io, false));
+    TGS_CHECK(tgs_batch_preprocess_fwd(ctx, g, views, cams, dils, opt, states, stream));
+    TGS_CHECK(tgs_batch_bin_sort(ctx, g, views, cams, dils, opt, states, stream));
+    return tgs_batch_raster_fwd(ctx, g->n, views, cams, dils, opt, states, io, stream);
+}
+
+tgs_status tgs_batch_l1_grad(tgs_context* ctx, int32_t views, const tgs_camera* cams,
+                             const tgs_dilation* dils, const tgs_view_io* io, double* loss,
+                             void* stream) {
+    if (views < 1 || views > TGS_MAX_VIEWS)
+        return fail(TGS_ERR_INVALID_ARG, "views = %d must be in [1, %d]", views, TGS_MAX_VIEWS);
+    if (!cams || !dils || !io) return fail(TGS_ERR_INVALID_ARG, "a per-view array is NULL");
+    tgs_status s;
+    for (int v = 0; v < views; ++v) {
+        if ((s = check_common(&cams[v], &dils[v], nullptr)) != TGS_OK)
+            return fail(s, "view %d: %s", v, g_error.c_str());
+        if (!io[v].image || !io[v].target || !io[v].dL_dimage)
+            return fail(TGS_ERR_INVALID_ARG, "view %d: a buffer is NULL", v);
+    }
+    TGS_CHECK(use_device(ctx));
+    auto strm = static_cast<hipStream_t>(stream);
+    for (int v = 0; v < views; ++v) {
+        const tgs::Grid grid = tgs::make_grid(cams[v], dils[v], 16);
+        TGS_HIP(tgs::launch_l1_grad(grid, io[v].image, io[v].target, io[v].dL_dimage,
+                                    loss ? loss + v : nullptr, strm));
+    }
+    return TGS_OK;
+}
+
+tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views, const tgs_camera* cams,
+                                const tgs_dilation* dils, const tgs_options* opt,
+                                const tgs_state* states, const tgs_view_io* io, void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_views(n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(check_io(views, io, true));
+    TGS_CHECK(check_binned_views(views, states, grids, Ls));
+    TGS_CHECK(use_device(ctx));
+    auto strm = static_cast<hipStream_t>(stream);
+    tgs::RasterViews rt{};
+    for (int v = 0; v < views; ++v) {
+        tgs::RasterView rv = raster_view(grids[v], *opt, states[v], Ls[v]);
+        rv.image = io[v].image;
+        rv.dL = io[v].dL_dimage;
+        TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(rv.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
+        add_raster_view(rt, rv);
+    }
+    TGS_HIP(tgs::launch_raster_bwd(opt->tile, lds_batch_of(*opt), rt, strm));
+    return TGS_OK;
+}
+
+tgs_status tgs_batch_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                                    const tgs_camera* cams, const tgs_dilation* dils,
+                                    const tgs_options* opt, const tgs_state* states,
+                                    const tgs_grads* out, float* pos_stat, float* col_stat,
+                                    uint8_t* visible, void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_gaussians(g));
+    TGS_CHECK(check_views(g->n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(check_grads(g, out));
+    TGS_CHECK(use_device(ctx));
+    tgs::PrepViews pt{};
+    pt.count = views;
+    for (int v = 0; v < views; ++v)
+        pt.v[v] = prep_view(cams[v], grids[v], static_cast<uint8_t*>(states[v].workspace), Ls[v]);
+    TGS_HIP(tgs::launch_preprocess_bwd(*g, pt, *out, pos_stat, col_stat, visible,
+                                       static_cast<hipStream_t>(stream)));
+    return TGS_OK;
+}
+
+tgs_status tgs_batch_backward(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
+                              const tgs_camera* cams, const tgs_dilation* dils,
+                              const tgs_options* opt, const tgs_state* states,
+                              const tgs_view_io* io, const tgs_grads* out, float* pos_stat,
+                              float* col_stat, uint8_t* visible, void* stream) {
+    tgs::Grid grids[TGS_MAX_VIEWS];
+    tgs::Layout Ls[TGS_MAX_VIEWS];
+    TGS_CHECK(check_gaussians(g));
+    TGS_CHECK(check_views(g->n, views, cams, dils, opt, states, grids, Ls));
+    TGS_CHECK(check_grads(g, out));
+    TGS_CHECK(check_io(views, io, true));
+    TGS_CHECK(check_binned_views(views, states, grids, Ls));
+    TGS_CHECK(tgs_batch_raster_bwd(ctx, g->n, views, cams, dils, opt, states, io, stream));
+    return tgs_batch_preprocess_bwd(ctx, g, views, cams, dils, opt, states, out, pos_stat,
+                                    col_stat, visible, stream);
+}
+
+tgs_status tgs_pair_counts(tgs_context* ctx, int32_t views, tgs_state* states, void* stream) {
+    if (views < 1 || views > TGS_MAX_VIEWS)
+        return fail(TGS_ERR_INVALID_ARG, "views = %d must be in [1, %d]", views, TGS_MAX_VIEWS);
+    if (!states) return fail(TGS_ERR_INVALID_ARG, "states is NULL");
+    for (int v = 0; v < views; ++v) {
+        const tgs_state& st = states[v];
+        if (!st.workspace || st.key_bits == 0 || st.off_pair_count + 4 > st.workspace_bytes)
+            return fail(TGS_ERR_INVALID_ARG, "view %d has not been binned", v);
+    }
+    tgs_status s = use_device(ctx);
+    if (s != TGS_OK) return s;
+    auto strm = static_cast<hipStream_t>(stream);
+    auto* pin = reinterpret_cast<uint32_t*>(ctx->pinned);
+    for (int v = 0; v < views; ++v)
+        TGS_HIP(hipMemcpyAsync(pin + v, static_cast<uint8_t*>(states[v].workspace) + states[v].off_pair_count,
+                               4, hipMemcpyDeviceToHost, strm));
+    TGS_HIP(hipStreamSynchronize(strm));
+    int over = -1;
+    for (int v = 0; v < views; ++v) {
+        states[v].pair_count = pin[v];
+        if (pin[v] > states[v].pair_capacity && over < 0) over = v;
+    }
+    if (over >= 0)
+        return fail(TGS_ERR_CAPACITY, "view %d: %llu pairs needed, capacity %llu", over,
+                    (unsigned long long)states[over].pair_count,
+                    (unsigned long long)states[over].pair_capacity);
+    return TGS_OK;
 }
 
 }  // extern "C"

@@ -20,6 +20,12 @@
 //      [start, end).
 // Memory traffic per pair: 6 B written by the emission, 2 B read by the
 // histogram, 6 B read and 4 B written by the scatter.
+//
+// The pair count is known only on the device (the scanned total).  Steps 3
+// and 4 read it and write nothing when it exceeds the buffers' capacity, so
+// the whole stage can be enqueued (or captured in a graph) without reading
+// it back; col_scan then writes empty ranges and the rasterizer renders the
+// background.
 #include "common.hpp"
 #include "wave.hpp"
 
@@ -110,12 +116,13 @@ row_setup_kernel(const uint32_t* __restrict__ rowscan, uint32_t nchunks, int gy,
 __global__ void __launch_bounds__(256)
 emit_rows_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order, int64_t n,
                  Grid grid, const uint32_t* __restrict__ rowscan, uint32_t nchunks,
-                 uint16_t* __restrict__ cols, uint32_t* __restrict__ vals) {
+                 uint32_t capacity, uint16_t* __restrict__ cols, uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_pref[4][64];
     __shared__ int s_xlo[4][64];
     __shared__ uint32_t s_id[4][64];
     const uint32_t chunk = (uint32_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     if (chunk >= nchunks) return;                      // wavefront-uniform
+    if (rowscan[uint64_t(grid.gy) * nchunks] > capacity) return;   // overflow: uniform
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     uint32_t id;
     const Rect r = rect_of(rec, order, int64_t(chunk) * 64 + lane, n, grid, id);
@@ -158,8 +165,9 @@ emit_rows_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ or
 struct Slice { int ty; uint32_t k, start, end; };
 
 __device__ __forceinline__ bool find_slice(uint32_t b, const uint32_t* first_slice,
-                                           const uint32_t* row_start, int gy, Slice& s) {
-    if (b >= first_slice[gy]) return false;
+                                           const uint32_t* row_start, int gy, uint32_t capacity,
+                                           Slice& s) {
+    if (row_start[gy] > capacity || b >= first_slice[gy]) return false;
     int lo = 0, hi = gy;                                // largest lo with first_slice[lo] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -175,10 +183,11 @@ __device__ __forceinline__ bool find_slice(uint32_t b, const uint32_t* first_sli
 // hist[b][tx]: pairs of slice b in column tx.
 __global__ void __launch_bounds__(256)
 col_hist_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict__ first_slice,
-                const uint32_t* __restrict__ row_start, Grid grid, uint32_t* __restrict__ hist) {
+                const uint32_t* __restrict__ row_start, Grid grid, uint32_t capacity,
+                uint32_t* __restrict__ hist) {
     extern __shared__ uint32_t h[];
     Slice s;
-    if (!find_slice(blockIdx.x, first_slice, row_start, grid.gy, s)) return;   // block-uniform
+    if (!find_slice(blockIdx.x, first_slice, row_start, grid.gy, capacity, s)) return;   // block-uniform
     for (int b = threadIdx.x; b < grid.gx; b += 256) h[b] = 0;
     __syncthreads();
     for (uint32_t i = s.start + threadIdx.x; i < s.end; i += 256) atomicAdd(&h[cols[i]], 1u);
@@ -211,11 +220,20 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t* s_
 // segments of consecutive slices, one thread per (column, segment).
 __global__ void __launch_bounds__(1024)
 col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_slice,
-                const uint32_t* __restrict__ row_start, Grid grid, uint32_t* __restrict__ ranges) {
+                const uint32_t* __restrict__ row_start, Grid grid, uint32_t capacity,
+                uint32_t* __restrict__ ranges) {
     __shared__ uint32_t s_seg[1024];
     __shared__ uint32_t s_start[kMaxCols];
     __shared__ uint32_t s_w[16];
     const int ty = blockIdx.x, t = threadIdx.x, gx = grid.gx;
+    if (row_start[grid.gy] > capacity) {               // overflow: empty ranges, block-uniform
+        if (t < gx) {
+            const uint64_t tile = uint64_t(ty) * gx + t;
+            ranges[2 * tile] = 0u;
+            ranges[2 * tile + 1] = 0u;
+        }
+        return;
+    }
     const uint32_t s0 = first_slice[ty], ns = first_slice[ty + 1] - s0;
     const int groups = max(1, 1024 / gx);
     const int tx = t % gx, g = t / gx;
@@ -260,7 +278,7 @@ __global__ void __launch_bounds__(kScatterThreads)
 col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict__ vals,
                    const uint32_t* __restrict__ first_slice, const uint32_t* __restrict__ row_start,
                    const uint32_t* __restrict__ hist, Grid grid, int col_bits,
-                   uint32_t* __restrict__ out) {
+                   uint32_t capacity, uint32_t* __restrict__ out) {
     constexpr int W = kScatterWaves, R = kScatterRounds, PER_WAVE = 64 * R;
     extern __shared__ uint32_t smem[];
     const int gx = grid.gx;
@@ -271,7 +289,7 @@ col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict
     uint32_t* s_w = s_gbase + gx;                        // [W]
     uint16_t* s_col = reinterpret_cast<uint16_t*>(s_w + W);   // [kSlice]
     Slice s;
-    if (!find_slice(blockIdx.x, first_slice, row_start, grid.gy, s)) return;   // block-uniform
+    if (!find_slice(blockIdx.x, first_slice, row_start, grid.gy, capacity, s)) return;   // block-uniform
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
     const uint32_t count = s.end - s.start;
     for (int b = tid; b < W * gx; b += kScatterThreads) s_wcnt[b] = 0;
@@ -382,40 +400,42 @@ hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid&
 }
 
 hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                            const Grid& grid, hipStream_t s) {
+                            const Grid& grid, uint32_t capacity, hipStream_t s) {
     const uint32_t nchunks = bin_chunks(n);
     if (nchunks == 0) return hipSuccess;
     emit_rows_kernel<<<dim3((nchunks + 3) / 4), dim3(256), 0, s>>>(
         reinterpret_cast<const float4*>(ws + L.records), order, n, grid,
-        reinterpret_cast<const uint32_t*>(ws + L.rowtot), nchunks,
+        reinterpret_cast<const uint32_t*>(ws + L.rowtot), nchunks, capacity,
         reinterpret_cast<uint16_t*>(ws + L.row_cols), reinterpret_cast<uint32_t*>(ws + L.row_vals));
     return hipGetLastError();
 }
 
+hipError_t prepare_binning_kernels() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&col_scatter_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(scatter_lds_bytes(kMaxCols)));
+}
+
 hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
-                           hipStream_t s) {
+                           uint32_t capacity, hipStream_t s) {
     const auto* fs = reinterpret_cast<const uint32_t*>(ws + L.first_slice);
     const auto* rs = reinterpret_cast<const uint32_t*>(ws + L.row_start);
     auto* hist = reinterpret_cast<uint32_t*>(ws + L.col_hist);
     auto* ranges = reinterpret_cast<uint32_t*>(ws + L.ranges);
     if (slices > 0) {
         col_hist_kernel<<<dim3(unsigned(slices)), dim3(256), size_t(grid.gx) * 4, s>>>(
-            reinterpret_cast<const uint16_t*>(ws + L.row_cols), fs, rs, grid, hist);
+            reinterpret_cast<const uint16_t*>(ws + L.row_cols), fs, rs, grid, capacity, hist);
     }
-    col_scan_kernel<<<dim3(unsigned(grid.gy)), dim3(1024), 0, s>>>(hist, fs, rs, grid, ranges);
+    col_scan_kernel<<<dim3(unsigned(grid.gy)), dim3(1024), 0, s>>>(hist, fs, rs, grid, capacity,
+                                                                  ranges);
     if (slices > 0) {
         int bits = 1;
         while ((1 << bits) < grid.gx) ++bits;
-        const size_t lds = scatter_lds_bytes(grid.gx);
-        if (lds > 65536) {
-            // wide tile grids need more than the default 64 KiB of LDS per block
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&col_scatter_kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-            if (e != hipSuccess) return e;
-        }
-        col_scatter_kernel<<<dim3(unsigned(slices)), dim3(kScatterThreads), lds, s>>>(
+        // LDS above the default 64 KiB is enabled once by prepare_binning_kernels
+        col_scatter_kernel<<<dim3(unsigned(slices)), dim3(kScatterThreads),
+                             scatter_lds_bytes(grid.gx), s>>>(
             reinterpret_cast<const uint16_t*>(ws + L.row_cols),
-            reinterpret_cast<const uint32_t*>(ws + L.row_vals), fs, rs, hist, grid, bits,
+            reinterpret_cast<const uint32_t*>(ws + L.row_vals), fs, rs, hist, grid, bits, capacity,
             reinterpret_cast<uint32_t*>(ws + L.pair_vals));
     }
     return hipGetLastError();

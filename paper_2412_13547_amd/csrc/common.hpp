@@ -73,11 +73,33 @@ struct CamDev {
 };
 CamDev make_cam(const tgs_camera& c);
 
-hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const CamDev& cam, const Grid& grid,
-                                 uint8_t* ws, const Layout& L, hipStream_t s);
-hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const CamDev& cam, const uint8_t* ws,
-                                 const Layout& L, const tgs_grads& out, float* pos_stat,
-                                 float* col_stat, uint8_t* visible, hipStream_t s);
+// Views of one launch.  Kernels that serve several views at once take a
+// table of up to kMaxViews views by value (kernel arguments stay well below
+// the 4 KiB argument segment).
+constexpr int kMaxViews = 16;
+
+// One view of the per-Gaussian preprocess.
+struct PrepView {
+    CamDev cam;
+    Grid grid;
+    tgs_record* rec;          // forward out / backward in
+    uint32_t* touched;        // forward out / backward in
+    uint32_t* depth_key;      // forward out
+    uint32_t* depth_val;      // forward out
+    const float* g2d;         // backward in
+};
+struct PrepViews {
+    int count;
+    PrepView v[kMaxViews];
+};
+static_assert(sizeof(PrepViews) <= 3584, "preprocess view table too large for kernel arguments");
+
+hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s);
+// Gradients summed over the views; statistics summed over the views where the
+// Gaussian is visible, visible = number of such views.
+hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const PrepViews& views,
+                                 const tgs_grads& out, float* pos_stat, float* col_stat,
+                                 uint8_t* visible, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs on bits [0, bits).
 // Returns the index (0 or 1) of the buffer pair holding the result.
@@ -92,7 +114,10 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
                               uint64_t* partials, bool write_total, hipStream_t s);
 uint64_t scan_partials_elems(uint64_t count);
 
-// binning (binning.hip)
+// binning (binning.hip).  The pair count lives on the device (row_start[gy]);
+// the emission and the column sort do nothing when it exceeds `capacity`
+// (and the column sort then writes empty ranges), so the stage can be
+// enqueued without reading the count back.
 uint32_t bin_chunks(int64_t n);
 uint64_t bin_max_slices(uint64_t pairs, int gy);
 hipError_t launch_row_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
@@ -100,27 +125,43 @@ hipError_t launch_row_counts(const uint8_t* ws, const Layout& L, const uint32_t*
 hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid& grid,
                             hipStream_t s);
 hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                            const Grid& grid, hipStream_t s);
-// Stable counting sort of every row bucket by column, and the tile ranges.
+                            const Grid& grid, uint32_t capacity, hipStream_t s);
+// Stable counting sort of every row bucket by column, and the tile ranges;
+// `slices` bounds the number of column-sort slices from above.
 hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
-                           hipStream_t s);
+                           uint32_t capacity, hipStream_t s);
+// One-time kernel attributes (the column scatter of the widest grid needs
+// more than 64 KiB of LDS).
+hipError_t prepare_binning_kernels();
 
-// Launch knobs of the raster kernels (results do not depend on them):
-// ppt = pixels per thread (1, 2 or 4), order = workgroup-to-tile mapping
-// (0 natural, 1 XCD-interleaved 2x2 quads).
-struct RasterTuning { int ppt = 1, order = 0; };
-RasterTuning raster_tuning();     // defaults, overridable by TGS_RASTER_PPT / TGS_TILE_ORDER
+// One view of a raster launch.
+struct RasterView {
+    Grid grid;
+    uint32_t capacity;        // pairs the view's buffers hold
+    float bg[3];
+    const float4* rec;        // tgs_record[n] as 3 float4
+    const uint32_t* ranges;   // [num_tiles][2]
+    const uint32_t* vals;     // pair values in (tile, depth, index) order
+    const uint32_t* pair_count;   // device: pairs binned; above capacity = overflow
+    float* image;             // forward out / backward in
+    float* t_final;           // forward, optional
+    uint32_t* last_contrib;   // forward, optional
+    uint32_t* n_eval;         // forward, optional
+    uint32_t* n_blend;        // forward, optional
+    const float* dL;          // backward in
+    float* g2d;               // backward out (accumulated; zero it first)
+};
+struct RasterViews {
+    int count;
+    uint32_t first_block[kMaxViews + 1];   // workgroups of views [0, v): prefix of tile counts
+    RasterView v[kMaxViews];
+};
+static_assert(sizeof(RasterViews) <= 3584, "raster view table too large for kernel arguments");
 
-hipError_t launch_raster_fwd(const Grid& grid, const RasterTuning& tune, const float bg[3],
-                             const uint8_t* ws, const Layout& L, const uint32_t* pair_vals,
-                             uint32_t pair_count, float* image,
-                             float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
-                             uint32_t* n_blend,
-                             hipStream_t s);
-hipError_t launch_raster_bwd(const Grid& grid, const RasterTuning& tune, const uint8_t* ws,
-                             const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
-                             const float* image,
-                             const float* dL_dimage, float* grad2d, hipStream_t s);
+// Default Gaussians per LDS round of a tile size; valid choices 64, 128, 256.
+int default_lds_batch(int tile);
+hipError_t launch_raster_fwd(int tile, int lds_batch, const RasterViews& views, hipStream_t s);
+hipError_t launch_raster_bwd(int tile, int lds_batch, const RasterViews& views, hipStream_t s);
 hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,
                           float* dL_dimage, double* loss, hipStream_t s);
 

@@ -8,7 +8,10 @@
 // parameters, and the densification statistics of Sec. 4.3.
 //
 // One thread per Gaussian; parameters are read structure-of-arrays so that
-// every load instruction of a wavefront touches 64 consecutive floats.
+// every load instruction of a wavefront touches 64 consecutive floats.  Both
+// kernels serve a table of views (cameras and dilation patterns): the
+// forward reads the parameters once and writes every view's records, the
+// backward sums the parameter gradients of every view before writing them.
 #include "common.hpp"
 
 namespace tgs {
@@ -177,26 +180,14 @@ __device__ __forceinline__ bool finite_all(const float* x, int k) {
     return ok;
 }
 
+// The record of one Gaussian in one view; returns the tiles it overlaps.
 template <int DEG>
-__global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, CamDev cam, Grid grid,
-                                                             tgs_record* __restrict__ rec,
-                                                             uint32_t* __restrict__ touched,
-                                                             uint32_t* __restrict__ depth_key,
-                                                             uint32_t* __restrict__ depth_val) {
+__device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid& grid, bool ok,
+                                                   const float m[3], const float s[3],
+                                                   const float q[4], float op, const float* sh,
+                                                   float4 out[3]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int64_t n = g.n;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float m[3], s[3], q[4], sh[K * 3];
-    for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
-    for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
-    for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
-    const float op = g.opacities[i];
-    for (int k = 0; k < K * 3; ++k) sh[k] = g.sh[k * n + i];
-
     Proj p;
-    bool ok = finite_all(m, 3) && finite_all(s, 3) && finite_all(q, 4) && isfinite(op) &&
-              finite_all(sh, K * 3);
     ok = ok && project(cam, m, s, q, p);
     float det = 0.0f;
     if (ok) {
@@ -210,72 +201,80 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Ca
         radius = int(ceilf(3.0f * sqrtf(lam)));
         ok = radius > 0;
     }
-    tgs_record r;
-    uint32_t nt = 0;
     if (!ok) {
-        r = tgs_record{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, kCulled};
-    } else {
-        const float A = p.c / det, B = -p.b / det, C = p.a / det;
-        // colour
-        float dx = m[0] - cam.campos[0], dy = m[1] - cam.campos[1], dz = m[2] - cam.campos[2];
-        const float len = sqrtf(dx * dx + dy * dy + dz * dz);
-        dx /= len; dy /= len; dz /= len;
-        float Y[16];
-        sh_basis<DEG>(dx, dy, dz, Y);
-        float rgb[3];
-        uint32_t flags = (p.fovx ? kFovX : 0u) | (p.fovy ? kFovY : 0u);
-        for (int c = 0; c < 3; ++c) {
-            float acc = 0.0f;
-            for (int k = 0; k < K; ++k) acc += sh[k * 3 + c] * Y[k];
-            acc += 0.5f;
-            if (acc < 0.0f) flags |= (1u << c);
-            rgb[c] = fmaxf(acc, 0.0f);
-        }
-        r = tgs_record{p.u, p.v, A, B, C, op, rgb[0], rgb[1], rgb[2], p.tz, radius, flags};
-        const Rect rc = tile_rect(p.u, p.v, radius, grid);
-        nt = uint32_t(rc.xhi - rc.xlo) * uint32_t(rc.yhi - rc.ylo);
+        out[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out[2] = make_float4(0.0f, 0.0f, __int_as_float(0), __uint_as_float(kCulled));
+        return 0;
     }
-    float4* dst = reinterpret_cast<float4*>(rec + i);
-    dst[0] = make_float4(r.u, r.v, r.A, r.B);
-    dst[1] = make_float4(r.C, r.opacity, r.r, r.g);
-    dst[2] = make_float4(r.b, r.z, __int_as_float(r.radius), __uint_as_float(r.flags));
-    touched[i] = nt;
-    depth_key[i] = nt > 0 ? __float_as_uint(r.z) : 0xFFFFFFFFu;
-    depth_val[i] = uint32_t(i);
+    const float A = p.c / det, B = -p.b / det, C = p.a / det;
+    // colour
+    float dx = m[0] - cam.campos[0], dy = m[1] - cam.campos[1], dz = m[2] - cam.campos[2];
+    const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+    dx /= len; dy /= len; dz /= len;
+    float Y[16];
+    sh_basis<DEG>(dx, dy, dz, Y);
+    float rgb[3];
+    uint32_t flags = (p.fovx ? kFovX : 0u) | (p.fovy ? kFovY : 0u);
+    for (int c = 0; c < 3; ++c) {
+        float acc = 0.0f;
+        for (int k = 0; k < K; ++k) acc += sh[k * 3 + c] * Y[k];
+        acc += 0.5f;
+        if (acc < 0.0f) flags |= (1u << c);
+        rgb[c] = fmaxf(acc, 0.0f);
+    }
+    out[0] = make_float4(p.u, p.v, A, B);
+    out[1] = make_float4(C, op, rgb[0], rgb[1]);
+    out[2] = make_float4(rgb[2], p.tz, __int_as_float(radius), __uint_as_float(flags));
+    const Rect rc = tile_rect(p.u, p.v, radius, grid);
+    return uint32_t(rc.xhi - rc.xlo) * uint32_t(rc.yhi - rc.ylo);
 }
 
-template <int DEG>
-__global__ void __launch_bounds__(256) preprocess_bwd_kernel(
-    tgs_gaussians g, CamDev cam, const tgs_record* __restrict__ rec,
-    const uint32_t* __restrict__ touched, const float* __restrict__ g2d, tgs_grads out,
-    float* __restrict__ pos_stat, float* __restrict__ col_stat, uint8_t* __restrict__ visible) {
+// One thread per Gaussian: the parameters are read once and the record of
+// every view of the table is written.
+template <int DEG, bool MULTI>
+__global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, PrepViews views) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t n = g.n;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int kc = g.sh_coeffs;
-    const float4 r2 = reinterpret_cast<const float4*>(rec + i)[2];
-    const uint32_t flags = __float_as_uint(r2.w);
-    const bool vis = touched[i] > 0 && !(flags & kCulled);
-    if (!vis) {
-        for (int k = 0; k < 3; ++k) out.means[k * n + i] = 0.0f;
-        for (int k = 0; k < 3; ++k) out.scales[k * n + i] = 0.0f;
-        for (int k = 0; k < 4; ++k) out.quats[k * n + i] = 0.0f;
-        out.opacities[i] = 0.0f;
-        for (int k = 0; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
-        if (pos_stat) pos_stat[i] = 0.0f;
-        if (col_stat) col_stat[i] = 0.0f;
-        if (visible) visible[i] = 0;
-        return;
-    }
-    float gr[kGrad2d];
-    for (int k = 0; k < kGrad2d; ++k) gr[k] = g2d[i * kGrad2d + k];
-    const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
-
-    float m[3], s[3], q[4];
+    float m[3], s[3], q[4], sh[K * 3];
     for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
     for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
     for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
+    const float op = g.opacities[i];
+    for (int k = 0; k < K * 3; ++k) sh[k] = g.sh[k * n + i];
+    const bool ok = finite_all(m, 3) && finite_all(s, 3) && finite_all(q, 4) && isfinite(op) &&
+                    finite_all(sh, K * 3);
+    const int nv = MULTI ? views.count : 1;
+    for (int v = 0; v < nv; ++v) {
+        const PrepView& pv = views.v[v];
+        float4 r[3];
+        const uint32_t nt = preprocess_one<DEG>(pv.cam, pv.grid, ok, m, s, q, op, sh, r);
+        float4* dst = reinterpret_cast<float4*>(pv.rec + i);
+        dst[0] = r[0];
+        dst[1] = r[1];
+        dst[2] = r[2];
+        pv.touched[i] = nt;
+        pv.depth_key[i] = nt > 0 ? __float_as_uint(r[2].y) : 0xFFFFFFFFu;
+        pv.depth_val[i] = uint32_t(i);
+    }
+}
+
+// Parameter gradients of Gaussian i in one view, written to (dm, ds, dq);
+// gr = dL/d(u, v, A, B, C, o, r, g, b).  The SH coefficients are read from
+// sh_g ([K*3][n]); their gradients are added to dsh_acc (ACC) or written to
+// dsh_g (single view).
+template <int DEG, bool ACC>
+__device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const float m[3],
+                                                    const float s[3], const float q[4],
+                                                    const float* sh_g, float* dsh_g, int64_t n,
+                                                    int64_t i, uint32_t flags,
+                                                    const float gr[kGrad2d], float dm_out[3],
+                                                    float ds_out[3], float dq_out[4],
+                                                    float* dsh_acc) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
     Proj p;
     project(cam, m, s, q, p);
     float dm[3] = {0.0f, 0.0f, 0.0f};
@@ -293,13 +292,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
         for (int k = 0; k < K; ++k) {
             float acc = 0.0f;
             for (int c = 0; c < 3; ++c) {
-                const float coef = g.sh[(k * 3 + c) * n + i];
-                out.sh[(k * 3 + c) * n + i] = Y[k] * graw[c];
-                acc += coef * graw[c];
+                const float d = Y[k] * graw[c];
+                if constexpr (ACC) dsh_acc[k * 3 + c] += d;
+                else dsh_g[(k * 3 + c) * n + i] = d;
+                acc += sh_g[(k * 3 + c) * n + i] * graw[c];
             }
             w[k] = acc;
         }
-        for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
         float gdx, gdy, gdz;
         sh_basis_grad<DEG>(dx, dy, dz, w, gdx, gdy, gdz);
         // through the normalisation of dir
@@ -386,51 +385,152 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
                     y * dR[5] + x * dR[6] + y * dR[7]);
     // through q / |q|
     const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    for (int k = 0; k < 4; ++k) out.quats[k * n + i] = (dq[k] - p.qn[k] * qd) / p.qlen;
+    for (int k = 0; k < 4; ++k) dq_out[k] = (dq[k] - p.qn[k] * qd) / p.qlen;
+    for (int k = 0; k < 3; ++k) ds_out[k] = ds[k];
+    for (int k = 0; k < 3; ++k) dm_out[k] = dm[k];
+}
+
+// One thread per Gaussian, one view.
+template <int DEG>
+__global__ void __launch_bounds__(256) preprocess_bwd_kernel(
+    tgs_gaussians g, PrepViews views, tgs_grads out, float* __restrict__ pos_stat,
+    float* __restrict__ col_stat, uint8_t* __restrict__ visible) {
+    const int64_t n = g.n;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int kc = g.sh_coeffs;
+    const PrepView& pv = views.v[0];
+    const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
+    const uint32_t flags = __float_as_uint(r2.w);
+    if (!(pv.touched[i] > 0 && !(flags & kCulled))) {
+        for (int k = 0; k < 3; ++k) out.means[k * n + i] = 0.0f;
+        for (int k = 0; k < 3; ++k) out.scales[k * n + i] = 0.0f;
+        for (int k = 0; k < 4; ++k) out.quats[k * n + i] = 0.0f;
+        out.opacities[i] = 0.0f;
+        for (int k = 0; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
+        if (pos_stat) pos_stat[i] = 0.0f;
+        if (col_stat) col_stat[i] = 0.0f;
+        if (visible) visible[i] = 0;
+        return;
+    }
+    float gr[kGrad2d];
+    for (int k = 0; k < kGrad2d; ++k) gr[k] = pv.g2d[i * kGrad2d + k];
+    float m[3], s[3], q[4];
+    for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
+    for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
+    for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
+    float dm[3], ds[3], dq[4];
+    preprocess_grad_one<DEG, false>(pv.cam, m, s, q, g.sh, out.sh, n, i, flags, gr, dm, ds, dq,
+                                    nullptr);
+    for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
+    for (int k = 0; k < 4; ++k) out.quats[k * n + i] = dq[k];
     for (int k = 0; k < 3; ++k) out.scales[k * n + i] = ds[k];
     for (int k = 0; k < 3; ++k) out.means[k * n + i] = dm[k];
     out.opacities[i] = gr[5];
     if (pos_stat) {
-        const float px = gu * (0.5f * float(cam.width)), py = gv * (0.5f * float(cam.height));
+        const float px = gr[0] * (0.5f * float(pv.cam.width));
+        const float py = gr[1] * (0.5f * float(pv.cam.height));
         pos_stat[i] = sqrtf(px * px + py * py);
     }
     if (col_stat) col_stat[i] = sqrtf(gr[6] * gr[6] + gr[7] * gr[7] + gr[8] * gr[8]);
     if (visible) visible[i] = 1;
 }
 
+// One thread per Gaussian, several views: the gradients of every view are
+// summed in registers (in view order) and written once.
+template <int DEG>
+__global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
+    tgs_gaussians g, PrepViews views, tgs_grads out, float* __restrict__ pos_stat,
+    float* __restrict__ col_stat, uint8_t* __restrict__ visible) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t n = g.n;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int kc = g.sh_coeffs;
+    float dm[3] = {0.0f, 0.0f, 0.0f}, ds[3] = {0.0f, 0.0f, 0.0f};
+    float dq[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dop = 0.0f;
+    float dsh[K * 3];
+    for (int k = 0; k < K * 3; ++k) dsh[k] = 0.0f;
+    float pos = 0.0f, col = 0.0f;
+    uint32_t nvis = 0;
+    float m[3], s[3], q[4];
+    for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
+    for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
+    for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
+    for (int v = 0; v < views.count; ++v) {
+        const PrepView& pv = views.v[v];
+        const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
+        const uint32_t flags = __float_as_uint(r2.w);
+        if (!(pv.touched[i] > 0 && !(flags & kCulled))) continue;
+        float gr[kGrad2d];
+        for (int k = 0; k < kGrad2d; ++k) gr[k] = pv.g2d[i * kGrad2d + k];
+        float vm[3], vs[3], vq[4];
+        preprocess_grad_one<DEG, true>(pv.cam, m, s, q, g.sh, nullptr, n, i, flags, gr, vm, vs,
+                                       vq, dsh);
+        for (int k = 0; k < 3; ++k) dm[k] += vm[k];
+        for (int k = 0; k < 3; ++k) ds[k] += vs[k];
+        for (int k = 0; k < 4; ++k) dq[k] += vq[k];
+        dop += gr[5];
+        const float px = gr[0] * (0.5f * float(pv.cam.width));
+        const float py = gr[1] * (0.5f * float(pv.cam.height));
+        pos += sqrtf(px * px + py * py);
+        col += sqrtf(gr[6] * gr[6] + gr[7] * gr[7] + gr[8] * gr[8]);
+        ++nvis;
+    }
+    for (int k = 0; k < 3; ++k) out.means[k * n + i] = dm[k];
+    for (int k = 0; k < 3; ++k) out.scales[k * n + i] = ds[k];
+    for (int k = 0; k < 4; ++k) out.quats[k * n + i] = dq[k];
+    out.opacities[i] = dop;
+    for (int k = 0; k < K * 3; ++k) out.sh[k * n + i] = dsh[k];
+    for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
+    if (pos_stat) pos_stat[i] = pos;
+    if (col_stat) col_stat[i] = col;
+    if (visible) visible[i] = uint8_t(nvis);
+}
+
+template <bool MULTI>
+void launch_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s) {
+    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
+    switch (g.sh_degree) {
+        case 0: preprocess_fwd_kernel<0, MULTI><<<nb, block, 0, s>>>(g, views); break;
+        case 1: preprocess_fwd_kernel<1, MULTI><<<nb, block, 0, s>>>(g, views); break;
+        case 2: preprocess_fwd_kernel<2, MULTI><<<nb, block, 0, s>>>(g, views); break;
+        default: preprocess_fwd_kernel<3, MULTI><<<nb, block, 0, s>>>(g, views); break;
+    }
+}
+
+template <bool MULTI>
+void launch_bwd(const tgs_gaussians& g, const PrepViews& views, const tgs_grads& out,
+                float* pos_stat, float* col_stat, uint8_t* visible, hipStream_t s) {
+    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
+#define TGS_BWD(D)                                                                                 \
+    if (MULTI) preprocess_bwd_multi_kernel<D><<<nb, block, 0, s>>>(g, views, out, pos_stat, col_stat, visible); \
+    else preprocess_bwd_kernel<D><<<nb, block, 0, s>>>(g, views, out, pos_stat, col_stat, visible)
+    switch (g.sh_degree) {
+        case 0: TGS_BWD(0); break;
+        case 1: TGS_BWD(1); break;
+        case 2: TGS_BWD(2); break;
+        default: TGS_BWD(3); break;
+    }
+#undef TGS_BWD
+}
+
 }  // namespace
 
-hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const CamDev& cam, const Grid& grid,
-                                 uint8_t* ws, const Layout& L, hipStream_t s) {
-    if (g.n == 0) return hipSuccess;
-    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
-    auto* rec = reinterpret_cast<tgs_record*>(ws + L.records);
-    auto* touched = reinterpret_cast<uint32_t*>(ws + L.tiles_touched);
-    auto* dk = reinterpret_cast<uint32_t*>(ws + L.depth_key[0]);
-    auto* dv = reinterpret_cast<uint32_t*>(ws + L.depth_val[0]);
-    switch (g.sh_degree) {
-        case 0: preprocess_fwd_kernel<0><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
-        case 1: preprocess_fwd_kernel<1><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
-        case 2: preprocess_fwd_kernel<2><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
-        default: preprocess_fwd_kernel<3><<<nb, block, 0, s>>>(g, cam, grid, rec, touched, dk, dv); break;
-    }
+hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s) {
+    if (g.n == 0 || views.count == 0) return hipSuccess;
+    if (views.count == 1) launch_fwd<false>(g, views, s);
+    else launch_fwd<true>(g, views, s);
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const CamDev& cam, const uint8_t* ws,
-                                 const Layout& L, const tgs_grads& out, float* pos_stat,
-                                 float* col_stat, uint8_t* visible, hipStream_t s) {
+hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const PrepViews& views,
+                                 const tgs_grads& out, float* pos_stat, float* col_stat,
+                                 uint8_t* visible, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
-    auto* rec = reinterpret_cast<const tgs_record*>(ws + L.records);
-    auto* touched = reinterpret_cast<const uint32_t*>(ws + L.tiles_touched);
-    auto* g2d = reinterpret_cast<const float*>(ws + L.grad2d);
-    switch (g.sh_degree) {
-        case 0: preprocess_bwd_kernel<0><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
-        case 1: preprocess_bwd_kernel<1><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
-        case 2: preprocess_bwd_kernel<2><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
-        default: preprocess_bwd_kernel<3><<<nb, block, 0, s>>>(g, cam, rec, touched, g2d, out, pos_stat, col_stat, visible); break;
-    }
+    if (views.count == 1) launch_bwd<false>(g, views, out, pos_stat, col_stat, visible, s);
+    else launch_bwd<true>(g, views, out, pos_stat, col_stat, visible, s);
     return hipGetLastError();
 }
 

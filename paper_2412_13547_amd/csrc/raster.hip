@@ -1,13 +1,15 @@
 // Dilated compositing, forward and backward (stages (c) and (d1)), and the
 // L1 loss gradient.
 //
-// One workgroup per tile of the DOWNSAMPLED image (Sec. 4.1: pairs live in
-// the downsampled grid; each downsampled pixel is blended at its
-// full-resolution position d i + o, so no thread is spent on an unrendered
-// pixel).  Threads own 1, 2 or 4 pixels of the tile (launch knob): with more
-// pixels per thread the splat records staged in LDS, and the per-splat
-// gradient reduction of the backward, are shared by several pixels.  Every
-// pixel walks its tile's list front to back (Sec. 3 Eq. 2).
+// One workgroup per tile of a DOWNSAMPLED image (Sec. 4.1: pairs live in the
+// downsampled grid; each downsampled pixel is blended at its full-resolution
+// position d i + o, so no thread is spent on an unrendered pixel).  One launch
+// covers the tiles of up to kMaxViews views (a view table passed by value):
+// workgroups are laid out view after view, so a batch of views of uneven size
+// is balanced by the hardware dispatcher like one big image.  16x16 and 8x8
+// tiles give one pixel per thread, 32x32 tiles a 2x2 block per thread.  The
+// tile's list is staged through LDS B splat records at a time; every pixel
+// walks it front to back (Sec. 3 Eq. 2).
 //
 // The backward replays the forward walk in the same order with the same
 // arithmetic (one shared inline routine), so it takes bit-identical skip and
@@ -23,7 +25,6 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr int kXcds = 8;
 
 // alpha = min(0.99, o exp(p)), p = -1/2 (A dx^2 + C dy^2) - B dx dy; false if
 // the entry is skipped (p > 0 or alpha < 1/255).  ga = (u, v, A, B),
@@ -40,37 +41,46 @@ __device__ __forceinline__ bool splat_alpha(const float4 ga, const float4 gb, fl
     return power <= 0.0f && alpha >= kAlphaMin;
 }
 
-// Tile of workgroup b.  order 0: tile = b.  order 1: the tile grid is cut
-// into 2x2 quads; quad q goes to XCD q mod 8 (workgroup b runs on XCD b mod 8)
-// and the 4 tiles of a quad are consecutive workgroups of that XCD, so they
-// run together and share splat records in its L2, while neighbouring quads
-// spread the expensive parts of the image over all XCDs.
-__device__ __forceinline__ int64_t tile_of_block(uint32_t b, const Grid& g, int order) {
-    if (order == 0) return b;
-    const int qx_n = (g.gx + 1) / 2;
-    const uint32_t xcd = b % kXcds, local = b / kXcds;
-    const int64_t q = int64_t(local / 4) * kXcds + xcd;
-    const int r = int(local % 4);
-    const int qy = int(q / qx_n), qx = int(q % qx_n);
-    const int tx = 2 * qx + (r & 1), ty = 2 * qy + (r >> 1);
-    if (tx >= g.gx || ty >= g.gy) return g.num_tiles();          // no tile: exit
-    return int64_t(ty) * g.gx + tx;
-}
-
-__host__ inline uint32_t blocks_for_tiles(const Grid& g, int order) {
-    if (order == 0) return uint32_t(g.num_tiles());
-    const int64_t quads = int64_t((g.gx + 1) / 2) * ((g.gy + 1) / 2);
-    return uint32_t(((quads + kXcds - 1) / kXcds) * kXcds * 4);
-}
-
-// Launch shape: a T x T tile is covered by (T/PX) x (T/PY) threads owning
-// PX x PY pixels each.
-template <int T, int PX_, int PY_>
+// Launch shape: a T x T tile is covered by (T/P) x (T/P) threads owning P x P
+// pixels each; B splat records are staged per LDS round.
+template <int T, int B_>
 struct Shape {
-    static constexpr int PX = PX_, PY = PY_, NP = PX * PY;
-    static constexpr int TX = T / PX, TY = T / PY, NT = TX * TY;   // threads
-    static constexpr int BATCH = NT < 256 ? NT : 256;
+    static constexpr int P = T == 32 ? 2 : 1, NP = P * P;
+    static constexpr int TX = T / P, NT = TX * TX;   // threads
+    static constexpr int B = B_;
 };
+
+// Which view and tile workgroup b works on.
+__device__ __forceinline__ bool locate(const RasterViews& vt, uint32_t b, int& v, int64_t& tile) {
+    if (b >= vt.first_block[vt.count]) return false;
+    v = 0;
+    while (b >= vt.first_block[v + 1]) ++v;
+    tile = int64_t(b - vt.first_block[v]);
+    return true;
+}
+
+// Clamp a tile's range to the pairs that exist: a view whose binning
+// overflowed its capacity reports a pair count above it and renders nothing.
+__device__ __forceinline__ void tile_range(const RasterView& rv, int64_t tile, uint32_t& start,
+                                           uint32_t& end) {
+    const uint32_t pc = *rv.pair_count;
+    const uint32_t lim = pc <= rv.capacity ? pc : 0u;
+    end = min(rv.ranges[2 * tile + 1], lim);
+    start = min(rv.ranges[2 * tile], end);
+}
+
+// Stage records [base, base + cnt) of the list into LDS (all threads).
+template <int NT, int B>
+__device__ __forceinline__ void stage(const RasterView& rv, uint32_t base, int cnt, float4* s_a,
+                                      float4* s_b, float* s_c, uint32_t* s_id) {
+    for (int q = threadIdx.x; q < cnt; q += NT) {
+        const uint32_t id = rv.vals[base + q];
+        if (s_id) s_id[q] = id;
+        s_a[q] = rv.rec[3 * uint64_t(id)];
+        s_b[q] = rv.rec[3 * uint64_t(id) + 1];
+        s_c[q] = rv.rec[3 * uint64_t(id) + 2].x;
+    }
+}
 
 // a + b after exchanging the upper 32 lanes of a with the lower 32 of b:
 // lanes 0-31 get a[i] + a[i+32], lanes 32-63 get b[i-32] + b[i].
@@ -124,33 +134,28 @@ __device__ __forceinline__ float wave_sum9(const float* v, int& comp) {
     return y;
 }
 
-template <int T, int PX, int PY>
-__global__ void __launch_bounds__((Shape<T, PX, PY>::NT))
-raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
-                  const float4* __restrict__ rec, const uint32_t* __restrict__ ranges,
-                  const uint32_t* __restrict__ vals, uint32_t pair_count,
-                  float* __restrict__ image, float* __restrict__ t_final,
-                  uint32_t* __restrict__ last_contrib, uint32_t* __restrict__ n_eval,
-                  uint32_t* __restrict__ n_blend) {
-    using S = Shape<T, PX, PY>;
-    __shared__ float4 s_a[S::BATCH], s_b[S::BATCH];
-    __shared__ float s_c[S::BATCH];
-    const int64_t tile = tile_of_block(blockIdx.x, grid, order);
-    if (tile >= grid.num_tiles()) return;                      // block-uniform
+template <int T, int BATCH>
+__global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_fwd_kernel(RasterViews vt) {
+    using S = Shape<T, BATCH>;
+    __shared__ float4 s_a[BATCH], s_b[BATCH];
+    __shared__ float s_c[BATCH];
+    int v;
+    int64_t tile;
+    if (!locate(vt, blockIdx.x, v, tile)) return;                // block-uniform
+    const RasterView& rv = vt.v[v];
+    const Grid& grid = rv.grid;
     const int tid = threadIdx.x;
     const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
-    const int i0 = tx * T + (tid % S::TX) * S::PX, j0 = ty * T + (tid / S::TX) * S::PY;
-    // ranges come from the sort of this state; clamping them to the pair
-    // count keeps every list read inside the pair buffer
-    const uint32_t end = min(ranges[2 * tile + 1], pair_count);
-    const uint32_t start = min(ranges[2 * tile], end);
+    const int i0 = tx * T + (tid % S::TX) * S::P, j0 = ty * T + (tid / S::TX) * S::P;
+    uint32_t start, end;
+    tile_range(rv, tile, start, end);
     float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
     uint32_t last[S::NP], neval[S::NP], nblend[S::NP];
     bool done[S::NP];
     bool alive = false;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
-        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
+        const int i = i0 + k % S::P, j = j0 + k / S::P;
         done[k] = !(i < grid.w_ds && j < grid.h_ds);
         alive |= !done[k];
         X[k] = float(grid.stride * i + grid.off_x);
@@ -161,16 +166,11 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
         nblend[k] = 0;
         neval[k] = end - start;
     }
-    for (uint32_t base = start; base < end; base += S::BATCH) {
+    for (uint32_t base = start; base < end; base += BATCH) {
         if (__syncthreads_count(alive) == 0) break;
-        if (tid < S::BATCH && base + tid < end) {
-            const uint64_t id = vals[base + tid];
-            s_a[tid] = rec[3 * id];
-            s_b[tid] = rec[3 * id + 1];
-            s_c[tid] = rec[3 * id + 2].x;
-        }
+        const int cnt = min(BATCH, int(end - base));
+        stage<S::NT, BATCH>(rv, base, cnt, s_a, s_b, s_c, nullptr);
         __syncthreads();
-        const int cnt = min(S::BATCH, int(end - base));
         // branch-free per entry: a skipped entry adds exactly 0 and leaves T
         for (int e = 0; e < cnt; ++e) {
             if (__ballot(alive) == 0) break;           // the whole wavefront has stopped
@@ -201,36 +201,35 @@ raster_fwd_kernel(Grid grid, int order, float bg0, float bg1, float bg2,
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
-        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
+        const int i = i0 + k % S::P, j = j0 + k / S::P;
         if (!(i < grid.w_ds && j < grid.h_ds)) continue;
         const uint64_t p = uint64_t(j) * grid.w_ds + i;
-        image[p] = c0[k] + Tr[k] * bg0;
-        image[pix + p] = c1[k] + Tr[k] * bg1;
-        image[2 * pix + p] = c2[k] + Tr[k] * bg2;
-        if (t_final) t_final[p] = Tr[k];
-        if (last_contrib) last_contrib[p] = last[k];
-        if (n_eval) n_eval[p] = neval[k];
-        if (n_blend) n_blend[p] = nblend[k];
+        rv.image[p] = c0[k] + Tr[k] * rv.bg[0];
+        rv.image[pix + p] = c1[k] + Tr[k] * rv.bg[1];
+        rv.image[2 * pix + p] = c2[k] + Tr[k] * rv.bg[2];
+        if (rv.t_final) rv.t_final[p] = Tr[k];
+        if (rv.last_contrib) rv.last_contrib[p] = last[k];
+        if (rv.n_eval) rv.n_eval[p] = neval[k];
+        if (rv.n_blend) rv.n_blend[p] = nblend[k];
     }
 }
 
-template <int T, int PX, int PY>
-__global__ void __launch_bounds__((Shape<T, PX, PY>::NT))
-raster_bwd_kernel(Grid grid, int order, const float4* __restrict__ rec,
-                  const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
-                  uint32_t pair_count, const float* __restrict__ image,
-                  const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
-    using S = Shape<T, PX, PY>;
-    __shared__ float4 s_a[S::BATCH], s_b[S::BATCH];
-    __shared__ float s_c[S::BATCH];
-    __shared__ uint32_t s_id[S::BATCH];
-    const int64_t tile = tile_of_block(blockIdx.x, grid, order);
-    if (tile >= grid.num_tiles()) return;                      // block-uniform
+template <int T, int BATCH>
+__global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_bwd_kernel(RasterViews vt) {
+    using S = Shape<T, BATCH>;
+    __shared__ float4 s_a[BATCH], s_b[BATCH];
+    __shared__ float s_c[BATCH];
+    __shared__ uint32_t s_id[BATCH];
+    int v;
+    int64_t tile;
+    if (!locate(vt, blockIdx.x, v, tile)) return;                // block-uniform
+    const RasterView& rv = vt.v[v];
+    const Grid& grid = rv.grid;
     const int tid = threadIdx.x;
     const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
-    const int i0 = tx * T + (tid % S::TX) * S::PX, j0 = ty * T + (tid / S::TX) * S::PY;
-    const uint32_t end = min(ranges[2 * tile + 1], pair_count);
-    const uint32_t start = min(ranges[2 * tile], end);
+    const int i0 = tx * T + (tid % S::TX) * S::P, j0 = ty * T + (tid / S::TX) * S::P;
+    uint32_t start, end;
+    tile_range(rv, tile, start, end);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
     float X[S::NP], Y[S::NP], Tr[S::NP], p0[S::NP], p1[S::NP], p2[S::NP];
     float g0[S::NP], g1[S::NP], g2[S::NP], im0[S::NP], im1[S::NP], im2[S::NP];
@@ -238,7 +237,7 @@ raster_bwd_kernel(Grid grid, int order, const float4* __restrict__ rec,
     bool alive = false;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
-        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
+        const int i = i0 + k % S::P, j = j0 + k / S::P;
         const bool in = i < grid.w_ds && j < grid.h_ds;
         done[k] = !in;
         alive |= in;
@@ -249,25 +248,19 @@ raster_bwd_kernel(Grid grid, int order, const float4* __restrict__ rec,
         g0[k] = g1[k] = g2[k] = im0[k] = im1[k] = im2[k] = 0.0f;
         if (in) {
             const uint64_t p = uint64_t(j) * grid.w_ds + i;
-            g0[k] = dL_dimage[p];
-            g1[k] = dL_dimage[pix + p];
-            g2[k] = dL_dimage[2 * pix + p];
-            im0[k] = image[p];
-            im1[k] = image[pix + p];
-            im2[k] = image[2 * pix + p];
+            g0[k] = rv.dL[p];
+            g1[k] = rv.dL[pix + p];
+            g2[k] = rv.dL[2 * pix + p];
+            im0[k] = rv.image[p];
+            im1[k] = rv.image[pix + p];
+            im2[k] = rv.image[2 * pix + p];
         }
     }
-    for (uint32_t base = start; base < end; base += S::BATCH) {
+    for (uint32_t base = start; base < end; base += BATCH) {
         if (__syncthreads_count(alive) == 0) break;
-        if (tid < S::BATCH && base + tid < end) {
-            const uint32_t id = vals[base + tid];
-            s_id[tid] = id;
-            s_a[tid] = rec[3 * uint64_t(id)];
-            s_b[tid] = rec[3 * uint64_t(id) + 1];
-            s_c[tid] = rec[3 * uint64_t(id) + 2].x;
-        }
+        const int cnt = min(BATCH, int(end - base));
+        stage<S::NT, BATCH>(rv, base, cnt, s_a, s_b, s_c, s_id);
         __syncthreads();
-        const int cnt = min(S::BATCH, int(end - base));
         for (int e = 0; e < cnt; ++e) {
             if (__ballot(alive) == 0) break;          // the whole wavefront has stopped
             const float4 a = s_a[e], b = s_b[e];
@@ -318,7 +311,7 @@ raster_bwd_kernel(Grid grid, int order, const float4* __restrict__ rec,
             }
             int comp;
             const float s = wave_sum9(gv, comp);
-            if (comp >= 0 && s != 0.0f) atomicAdd(&grad2d[uint64_t(s_id[e]) * kGrad2d + comp], s);
+            if (comp >= 0 && s != 0.0f) atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], s);
         }
     }
 }
@@ -351,64 +344,36 @@ l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restri
     }
 }
 
-template <int T, int PX, int PY>
-void fwd_launch(const Grid& grid, int order, const float bg[3], const float4* rec,
-                const uint32_t* ranges, const uint32_t* vals, uint32_t pc, float* image,
-                float* t_final, uint32_t* last, uint32_t* neval, uint32_t* nblend, hipStream_t s) {
-    raster_fwd_kernel<T, PX, PY><<<dim3(blocks_for_tiles(grid, order)),
-                                   dim3(Shape<T, PX, PY>::NT), 0, s>>>(
-        grid, order, bg[0], bg[1], bg[2], rec, ranges, vals, pc, image, t_final, last, neval,
-        nblend);
+template <int T, int B>
+void launch_both(bool fwd, const RasterViews& vt, hipStream_t s) {
+    const dim3 grid(vt.first_block[vt.count]), block(Shape<T, B>::NT);
+    if (fwd) raster_fwd_kernel<T, B><<<grid, block, 0, s>>>(vt);
+    else raster_bwd_kernel<T, B><<<grid, block, 0, s>>>(vt);
 }
 
-template <int T, int PX, int PY>
-void bwd_launch(const Grid& grid, int order, const float4* rec, const uint32_t* ranges,
-                const uint32_t* vals, uint32_t pc, const float* image, const float* dL,
-                float* g2d, hipStream_t s) {
-    raster_bwd_kernel<T, PX, PY><<<dim3(blocks_for_tiles(grid, order)),
-                                   dim3(Shape<T, PX, PY>::NT), 0, s>>>(
-        grid, order, rec, ranges, vals, pc, image, dL, g2d);
+template <int T>
+void launch_tile(bool fwd, int batch, const RasterViews& vt, hipStream_t s) {
+    if (batch == 64) launch_both<T, 64>(fwd, vt, s);
+    else if (batch == 128) launch_both<T, 128>(fwd, vt, s);
+    else launch_both<T, 256>(fwd, vt, s);
+}
+
+hipError_t launch_raster(bool fwd, int tile, int batch, const RasterViews& vt, hipStream_t s) {
+    if (vt.count == 0 || vt.first_block[vt.count] == 0) return hipSuccess;
+    if (tile == 8) launch_tile<8>(fwd, batch, vt, s);
+    else if (tile == 32) launch_tile<32>(fwd, batch, vt, s);
+    else launch_tile<16>(fwd, batch, vt, s);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const Grid& grid, const RasterTuning& tune, const float bg[3],
-                             const uint8_t* ws, const Layout& L, const uint32_t* pair_vals,
-                             uint32_t pair_count, float* image, float* t_final,
-                             uint32_t* last_contrib, uint32_t* n_eval, uint32_t* n_blend,
-                             hipStream_t s) {
-    const auto* rec = reinterpret_cast<const float4*>(ws + L.records);
-    const auto* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-    if (grid.num_tiles() == 0) return hipSuccess;
-    const int o = tune.order;
-#define TGS_FWD(T, PX, PY) fwd_launch<T, PX, PY>(grid, o, bg, rec, ranges, pair_vals, pair_count, \
-                                                image, t_final, last_contrib, n_eval, n_blend, s)
-    if (grid.tile == 8) TGS_FWD(8, 1, 1);
-    else if (grid.tile == 32) { if (tune.ppt == 2) TGS_FWD(32, 2, 1); else TGS_FWD(32, 2, 2); }
-    else if (tune.ppt == 1) TGS_FWD(16, 1, 1);
-    else if (tune.ppt == 2) TGS_FWD(16, 2, 1);
-    else TGS_FWD(16, 2, 2);
-#undef TGS_FWD
-    return hipGetLastError();
+hipError_t launch_raster_fwd(int tile, int batch, const RasterViews& vt, hipStream_t s) {
+    return launch_raster(true, tile, batch, vt, s);
 }
 
-hipError_t launch_raster_bwd(const Grid& grid, const RasterTuning& tune, const uint8_t* ws,
-                             const Layout& L, const uint32_t* pair_vals, uint32_t pair_count,
-                             const float* image, const float* dL_dimage, float* grad2d,
-                             hipStream_t s) {
-    const auto* rec = reinterpret_cast<const float4*>(ws + L.records);
-    const auto* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-    if (grid.num_tiles() == 0) return hipSuccess;
-    const int o = tune.order;
-#define TGS_BWD(T, PX, PY) bwd_launch<T, PX, PY>(grid, o, rec, ranges, pair_vals, pair_count, \
-                                                image, dL_dimage, grad2d, s)
-    if (grid.tile == 8) TGS_BWD(8, 1, 1);
-    else if (grid.tile == 32) { if (tune.ppt == 2) TGS_BWD(32, 2, 1); else TGS_BWD(32, 2, 2); }
-    else if (tune.ppt == 1) TGS_BWD(16, 1, 1);
-    else if (tune.ppt == 2) TGS_BWD(16, 2, 1);
-    else TGS_BWD(16, 2, 2);
-#undef TGS_BWD
-    return hipGetLastError();
+hipError_t launch_raster_bwd(int tile, int batch, const RasterViews& vt, hipStream_t s) {
+    return launch_raster(false, tile, batch, vt, s);
 }
 
 hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,

@@ -250,3 +250,19 @@ def small_scene(seed: int, n: int, width: int, height: int, sh_degree: int = 3,
         sh[1:] = rng.normal(0.0, 0.1, size=(k - 1, 3, n))
     scene = Scene(_f32(means), _f32(np.exp(log_scales)), _f32(quats), _f32(opac), _f32(sh), sh_degree)
     return scene, cam
+
+
+def small_multiview(seed: int, n: int, sizes, sh_degree: int = 3, spread_angle: float = 0.25):
+    """A small scene seen by several ring cameras of the given (width, height).
+
+    The Gaussians are placed in front of the first camera as in ``small_scene``
+    (sized from the first entry of ``sizes``); camera k sits ``k *
+    spread_angle`` radians further round the ring, so every camera sees most
+    of them.  Returns (scene, cameras).
+    """
+    w0, h0 = sizes[0]
+    scene, cam0 = small_scene(seed, n, w0, h0, sh_degree=sh_degree)
+    ang0 = float(np.random.default_rng(seed).uniform(0.0, 2.0 * math.pi))
+    cams = [cam0] + [ring_camera(w, h, ang0 + k * spread_angle) for k, (w, h) in
+                     enumerate(sizes) if k > 0]
+    return scene, cams

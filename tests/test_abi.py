@@ -137,3 +137,74 @@ def test_create_reports_missing_device():
     h = C.c_void_p()
     assert api.lib().tgs_create(10_000, C.byref(h)) == api.TGS_ERR_NO_DEVICE
     assert not h.value
+
+
+def test_bad_lds_batch_and_flags_rejected():
+    out = api.tgs_sizes()
+    for lb in (32, 100, 512, -1):
+        st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()),
+                                       C.byref(api.options_struct(16, lds_batch=lb)), 0, C.byref(out))
+        assert st == api.TGS_ERR_INVALID_ARG and b"lds_batch" in api.lib().tgs_last_error()
+    for lb in (0, 64, 128, 256):
+        st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()),
+                                       C.byref(api.options_struct(16, lds_batch=lb)), 0, C.byref(out))
+        assert st == api.TGS_OK
+    opt = api.options_struct(16)
+    opt.flags = 1
+    st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()), C.byref(opt),
+                                   0, C.byref(out))
+    assert st == api.TGS_ERR_INVALID_ARG
+
+
+def _batch_args(nv, ws_bytes=1 << 30, stride=1 << 31):
+    cams = (api.tgs_camera * nv)(*[_cam() for _ in range(nv)])
+    dils = (api.tgs_dilation * nv)(*[api.dilation_struct(2, k % 2, 0) for k in range(nv)])
+    states = (api.tgs_state * nv)()
+    io = (api.tgs_view_io * nv)()
+    for k in range(nv):
+        states[k].workspace = (1 << 40) + k * stride
+        states[k].workspace_bytes = ws_bytes
+        states[k].pair_capacity = 1000
+        io[k].image = 1 << 20
+        io[k].dL_dimage = 1 << 20
+        io[k].target = 1 << 20
+    return cams, dils, states, io
+
+
+def test_batch_view_count_and_overlap_rejected_before_device():
+    lib = api.lib()
+    g = _gauss()
+    opt = api.options_struct(16)
+    for nv in (0, 17):
+        cams, dils, states, io = _batch_args(max(nv, 1))
+        r = lib.tgs_batch_forward(None, C.byref(g), nv, cams, dils, C.byref(opt), states, io, None)
+        assert r == api.TGS_ERR_INVALID_ARG and b"views" in lib.tgs_last_error()
+    cams, dils, states, io = _batch_args(3, stride=4096)       # workspaces overlap
+    r = lib.tgs_batch_forward(None, C.byref(g), 3, cams, dils, C.byref(opt), states, io, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"overlap" in lib.tgs_last_error()
+    cams, dils, states, io = _batch_args(3)
+    io[1].image = None
+    r = lib.tgs_batch_forward(None, C.byref(g), 3, cams, dils, C.byref(opt), states, io, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"view 1" in lib.tgs_last_error()
+    cams, dils, states, io = _batch_args(3)
+    dils[2].off_x = 5
+    r = lib.tgs_batch_forward(None, C.byref(g), 3, cams, dils, C.byref(opt), states, io, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"view 2" in lib.tgs_last_error()
+    cams, dils, states, io = _batch_args(3)                  # valid up to the missing context
+    r = lib.tgs_batch_forward(None, C.byref(g), 3, cams, dils, C.byref(opt), states, io, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"context" in lib.tgs_last_error()
+
+
+def test_batch_backward_and_counts_refuse_unbinned_states():
+    lib = api.lib()
+    g = _gauss()
+    cams, dils, states, io = _batch_args(2)
+    grads = api.tgs_grads(1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20)
+    r = lib.tgs_batch_backward(None, C.byref(g), 2, cams, dils, C.byref(api.options_struct(16)),
+                               states, io, C.byref(grads), None, None, None, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"binned" in lib.tgs_last_error()
+    r = lib.tgs_pair_counts(None, 2, states, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"binned" in lib.tgs_last_error()
+    io[0].target = None
+    r = lib.tgs_batch_l1_grad(None, 2, cams, dils, io, None, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"view 0" in lib.tgs_last_error()
