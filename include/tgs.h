@@ -348,6 +348,33 @@ tgs_status tgs_batch_backward(tgs_context* ctx, const tgs_gaussians* g, int32_t 
  * any count exceeds its pair_capacity (that view rendered nothing). */
 tgs_status tgs_pair_counts(tgs_context* ctx, int32_t views, tgs_state* states, void* stream);
 
+/* ---- Fused Adam step (the optimiser of the fitting loop that follows
+ * stage (d2); Adam as in the 3DGS recipe the paper trains with, Tab. 2).
+ *
+ * For every element of every group, with t the step after this call:
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   p <- p - lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+ * The step counter t and the bias corrections live in `state` (device
+ * memory of TGS_ADAM_STATE_BYTES bytes, 16-byte aligned, zero before the
+ * first step, one per optimiser); each call increments it on the device, so
+ * the call can be captured in a graph and replayed. */
+#define TGS_ADAM_STATE_BYTES 16
+#define TGS_MAX_ADAM_GROUPS 8
+
+typedef struct tgs_adam_group {
+    float* param;            /* device [count], updated in place          */
+    const float* grad;       /* device [count]                            */
+    float* exp_avg;          /* device [count], first moment, in place    */
+    float* exp_avg_sq;       /* device [count], second moment, in place   */
+    int64_t count;           /* >= 0                                      */
+    float lr;                /* learning rate of the group, >= 0          */
+} tgs_adam_group;
+
+/* 1 <= n_groups <= TGS_MAX_ADAM_GROUPS; 0 <= beta1, beta2 < 1; eps > 0.
+ * Arrays of different groups must not overlap. */
+tgs_status tgs_adam_step(tgs_context* ctx, const tgs_adam_group* groups, int32_t n_groups,
+                         float beta1, float beta2, float eps, void* state, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

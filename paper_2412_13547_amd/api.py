@@ -23,8 +23,10 @@ EXPORTED = (
     "tgs_l1_grad", "tgs_raster_bwd", "tgs_preprocess_bwd", "tgs_backward",
     "tgs_batch_preprocess_fwd", "tgs_batch_bin_sort", "tgs_batch_raster_fwd",
     "tgs_batch_forward", "tgs_batch_l1_grad", "tgs_batch_raster_bwd", "tgs_batch_preprocess_bwd",
-    "tgs_batch_backward", "tgs_pair_counts",
+    "tgs_batch_backward", "tgs_pair_counts", "tgs_adam_step",
 )
+ADAM_STATE_BYTES = 16
+MAX_ADAM_GROUPS = 8
 
 MAX_VIEWS = 16
 PAIR_COUNT_PENDING = (1 << 64) - 1
@@ -70,6 +72,11 @@ class tgs_state(C.Structure):
                 ("off_depth_order", C.c_uint64),
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
                 ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64)]
+
+
+class tgs_adam_group(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("exp_avg", C.c_void_p),
+                ("exp_avg_sq", C.c_void_p), ("count", C.c_int64), ("lr", C.c_float)]
 
 
 class tgs_view_io(C.Structure):
@@ -118,6 +125,8 @@ def _declare(lib):
                                          _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
                                          _P(tgs_view_io), _P(tgs_grads), vp, vp, vp, vp]),
         "tgs_pair_counts": (C.c_int, [vp, C.c_int32, _P(tgs_state), vp]),
+        "tgs_adam_step": (C.c_int, [vp, _P(tgs_adam_group), C.c_int32, C.c_float, C.c_float,
+                                    C.c_float, vp, vp]),
         "tgs_batch_preprocess_fwd": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
                                                _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
                                                vp]),
@@ -556,3 +565,35 @@ class Batch:
             for k in over:
                 self.views[k].reserve(int(self.states[k].pair_count * slack) + 4096)
         raise TgsError(TGS_ERR_CAPACITY, "pair capacity did not converge")
+
+
+class Adam:
+    """Fused Adam over a list of float32 device tensors (one group each, with
+    its own learning rate); moments and the device step counter are owned
+    here.  ``step(grads)`` is one kernel pair, capturable in a graph."""
+
+    def __init__(self, ctx: Context, params, lrs, betas=(0.9, 0.999), eps=1e-15):
+        import torch
+        if not 1 <= len(params) <= MAX_ADAM_GROUPS or len(lrs) != len(params):
+            raise ValueError(f"1..{MAX_ADAM_GROUPS} groups with one learning rate each")
+        for p in params:
+            assert p.is_contiguous() and p.dtype == torch.float32 and p.is_cuda
+        self.ctx, self.params = ctx, list(params)
+        self.lrs = [float(x) for x in lrs]
+        self.betas, self.eps = (float(betas[0]), float(betas[1])), float(eps)
+        self.exp_avg = [torch.zeros_like(p) for p in self.params]
+        self.exp_avg_sq = [torch.zeros_like(p) for p in self.params]
+        self.state = torch.zeros(ADAM_STATE_BYTES // 4, dtype=torch.int32, device="cuda")
+        self._groups = (tgs_adam_group * len(self.params))()
+
+    @property
+    def step_count(self) -> int:
+        return int(self.state[0].item())
+
+    def step(self, grads, stream=None):
+        for k, (p, g, m, v) in enumerate(zip(self.params, grads, self.exp_avg, self.exp_avg_sq)):
+            assert g.shape == p.shape and g.is_contiguous() and g.dtype == p.dtype
+            self._groups[k] = tgs_adam_group(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(),
+                                             self.lrs[k])
+        check(lib().tgs_adam_step(self.ctx.handle, self._groups, len(self.params), self.betas[0],
+                                  self.betas[1], self.eps, _ptr(self.state), _stream(stream)))

@@ -46,18 +46,18 @@ tgs_status hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, #call);        \
     } while (0)
 
-bool finitef(float x) { return std::isfinite(x); }
+bool is_finite(float x) { return std::isfinite(x); }
 
 tgs_status check_camera(const tgs_camera* cam) {
     if (!cam) return fail(TGS_ERR_INVALID_ARG, "camera is NULL");
     if (cam->width <= 0 || cam->height <= 0)
         return fail(TGS_ERR_INVALID_ARG, "camera size %dx%d must be positive", cam->width, cam->height);
-    if (!(cam->fx > 0) || !(cam->fy > 0) || !finitef(cam->fx) || !finitef(cam->fy))
+    if (!(cam->fx > 0) || !(cam->fy > 0) || !is_finite(cam->fx) || !is_finite(cam->fy))
         return fail(TGS_ERR_INVALID_ARG, "focal lengths must be positive and finite");
-    if (!finitef(cam->cx) || !finitef(cam->cy) || !finitef(cam->near_z))
+    if (!is_finite(cam->cx) || !is_finite(cam->cy) || !is_finite(cam->near_z))
         return fail(TGS_ERR_INVALID_ARG, "principal point and near_z must be finite");
     for (int k = 0; k < 12; ++k)
-        if (!finitef(cam->world_to_cam[k])) return fail(TGS_ERR_INVALID_ARG, "world_to_cam is not finite");
+        if (!is_finite(cam->world_to_cam[k])) return fail(TGS_ERR_INVALID_ARG, "world_to_cam is not finite");
     return TGS_OK;
 }
 
@@ -81,7 +81,7 @@ tgs_status check_options(const tgs_options* opt) {
         return fail(TGS_ERR_INVALID_ARG, "lds_batch %d must be 0, 64, 128 or 256", opt->lds_batch);
     if (opt->flags != 0) return fail(TGS_ERR_INVALID_ARG, "option flags must be 0");
     for (int c = 0; c < 3; ++c)
-        if (!finitef(opt->bg[c])) return fail(TGS_ERR_INVALID_ARG, "background is not finite");
+        if (!is_finite(opt->bg[c])) return fail(TGS_ERR_INVALID_ARG, "background is not finite");
     return TGS_OK;
 }
 
@@ -812,6 +812,35 @@ tgs_status tgs_pair_counts(tgs_context* ctx, int32_t views, tgs_state* states, v
         return fail(TGS_ERR_CAPACITY, "view %d: %llu pairs needed, capacity %llu", over,
                     (unsigned long long)states[over].pair_count,
                     (unsigned long long)states[over].pair_capacity);
+    return TGS_OK;
+}
+
+tgs_status tgs_adam_step(tgs_context* ctx, const tgs_adam_group* groups, int32_t n_groups,
+                         float beta1, float beta2, float eps, void* state, void* stream) {
+    if (!groups) return fail(TGS_ERR_INVALID_ARG, "groups is NULL");
+    if (n_groups < 1 || n_groups > TGS_MAX_ADAM_GROUPS)
+        return fail(TGS_ERR_INVALID_ARG, "n_groups = %d must be in [1, %d]", n_groups,
+                    TGS_MAX_ADAM_GROUPS);
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(TGS_ERR_INVALID_ARG, "betas must lie in [0, 1)");
+    if (!(eps > 0.0f) || !is_finite(eps)) return fail(TGS_ERR_INVALID_ARG, "eps must be positive");
+    if (!state || reinterpret_cast<uintptr_t>(state) % 16 != 0)
+        return fail(TGS_ERR_INVALID_ARG, "state must be a 16-byte aligned device buffer");
+    tgs::AdamGroups t{};
+    t.count = n_groups;
+    for (int k = 0; k < n_groups; ++k) {
+        const tgs_adam_group& G = groups[k];
+        if (G.count < 0) return fail(TGS_ERR_INVALID_ARG, "group %d: count < 0", k);
+        if (!(G.lr >= 0.0f) || !is_finite(G.lr))
+            return fail(TGS_ERR_INVALID_ARG, "group %d: lr must be finite and >= 0", k);
+        if (G.count > 0 && (!G.param || !G.grad || !G.exp_avg || !G.exp_avg_sq))
+            return fail(TGS_ERR_INVALID_ARG, "group %d: a pointer is NULL", k);
+        auto al = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+        t.g[k] = tgs::AdamGroup{G.param, G.grad, G.exp_avg, G.exp_avg_sq, G.count, G.lr,
+                                al(G.param) && al(G.grad) && al(G.exp_avg) && al(G.exp_avg_sq)};
+    }
+    TGS_CHECK(use_device(ctx));
+    TGS_HIP(tgs::launch_adam(t, state, beta1, beta2, eps, static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
 

@@ -165,6 +165,25 @@ hipError_t launch_raster_bwd(int tile, int lds_batch, const RasterViews& views, 
 hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,
                           float* dL_dimage, double* loss, hipStream_t s);
 
+// Fused Adam (optim.hip): a table of parameter groups, the step counter and
+// bias corrections in a small device buffer.
+constexpr int kMaxAdamGroups = 8;
+struct AdamGroup {
+    float* param;
+    const float* grad;
+    float* exp_avg;
+    float* exp_avg_sq;
+    int64_t count;
+    float lr;
+    int vec4;                 // all four arrays 16-byte aligned
+};
+struct AdamGroups {
+    int count;
+    AdamGroup g[kMaxAdamGroups];
+};
+hipError_t launch_adam(const AdamGroups& groups, void* coeffs, float b1, float b2, float eps,
+                       hipStream_t s);
+
 hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
