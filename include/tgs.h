@@ -375,6 +375,29 @@ typedef struct tgs_adam_group {
 tgs_status tgs_adam_step(tgs_context* ctx, const tgs_adam_group* groups, int32_t n_groups,
                          float beta1, float beta2, float eps, void* state, void* stream);
 
+/* ---- Densification selection (Sec. 4.3) from statistics accumulated over
+ * views and iterations (sums of the per-view pos_stat / col_stat and the
+ * number of views that saw each Gaussian, e.g. the sums of `visible`).
+ *
+ * selected[i] = 1 when count[i] > 0 and either pos_sum[i] / count[i] >=
+ * tau_pos or, when color_active != 0, col_sum[i] / count[i] >= tau_col
+ * (the paper sets tau_col = 0.01 tau_pos and activates the appearance branch
+ * in 20% of the densification events; the caller draws that decision).
+ * Means and ratios are computed in float32 with IEEE division.  With
+ * budget >= 0 (the number of Gaussians the convergence-aware schedule of
+ * Sec. 4.2 still allows), only the `budget` candidates with the largest
+ * score max(mean_pos / tau_pos, mean_col / tau_col) stay selected, equal
+ * scores in ascending index; budget = -1 keeps every candidate.
+ * n_selected: device uint32, the number selected.  workspace: device,
+ * 256-byte aligned, at least tgs_densify_query bytes; col_sum may be NULL
+ * when color_active is 0. */
+tgs_status tgs_densify_query(int64_t n, uint64_t* workspace_bytes);
+tgs_status tgs_densify_select(tgs_context* ctx, int64_t n, const float* pos_sum,
+                              const float* col_sum, const int32_t* count, float tau_pos,
+                              float tau_col, int32_t color_active, int64_t budget,
+                              uint8_t* selected, uint32_t* n_selected, void* workspace,
+                              uint64_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

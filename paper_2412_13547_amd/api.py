@@ -23,7 +23,8 @@ EXPORTED = (
     "tgs_l1_grad", "tgs_raster_bwd", "tgs_preprocess_bwd", "tgs_backward",
     "tgs_batch_preprocess_fwd", "tgs_batch_bin_sort", "tgs_batch_raster_fwd",
     "tgs_batch_forward", "tgs_batch_l1_grad", "tgs_batch_raster_bwd", "tgs_batch_preprocess_bwd",
-    "tgs_batch_backward", "tgs_pair_counts", "tgs_adam_step",
+    "tgs_batch_backward", "tgs_pair_counts", "tgs_adam_step", "tgs_densify_query",
+    "tgs_densify_select",
 )
 ADAM_STATE_BYTES = 16
 MAX_ADAM_GROUPS = 8
@@ -127,6 +128,9 @@ def _declare(lib):
         "tgs_pair_counts": (C.c_int, [vp, C.c_int32, _P(tgs_state), vp]),
         "tgs_adam_step": (C.c_int, [vp, _P(tgs_adam_group), C.c_int32, C.c_float, C.c_float,
                                     C.c_float, vp, vp]),
+        "tgs_densify_query": (C.c_int, [C.c_int64, _P(C.c_uint64)]),
+        "tgs_densify_select": (C.c_int, [vp, C.c_int64, vp, vp, vp, C.c_float, C.c_float,
+                                         C.c_int32, C.c_int64, vp, vp, vp, C.c_uint64, vp]),
         "tgs_batch_preprocess_fwd": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
                                                _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
                                                vp]),
@@ -202,7 +206,16 @@ def options_struct(tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0) -> tgs_options:
 
 
 def _ptr(t) -> int | None:
-    return None if t is None else int(t.data_ptr())
+    """Device address of a dense device tensor (None passes NULL).  The C ABI
+    reads plain arrays, so strided views and host tensors are refused."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError(f"tensor of shape {tuple(t.shape)} is not contiguous; "
+                         "libtgs reads dense arrays (call .contiguous())")
+    if not t.is_cuda:
+        raise ValueError("libtgs reads device memory: move the tensor to the GPU")
+    return int(t.data_ptr())
 
 
 @dataclasses.dataclass
@@ -597,3 +610,21 @@ class Adam:
                                              self.lrs[k])
         check(lib().tgs_adam_step(self.ctx.handle, self._groups, len(self.params), self.betas[0],
                                   self.betas[1], self.eps, _ptr(self.state), _stream(stream)))
+
+
+def densify_select(ctx: Context, pos_sum, col_sum, count, tau_pos: float, tau_col: float,
+                   color_active: bool, budget: int = -1, stream=None):
+    """Selection mask (uint8 [n]) and the device count of selected Gaussians."""
+    import torch
+    n = int(pos_sum.numel())
+    need = C.c_uint64()
+    check(lib().tgs_densify_query(n, C.byref(need)))
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device="cuda")
+    base = (int(ws.data_ptr()) + 255) // 256 * 256
+    sel = torch.empty(n, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+    check(lib().tgs_densify_select(ctx.handle, n, _ptr(pos_sum), _ptr(col_sum), _ptr(count),
+                                   float(tau_pos), float(tau_col), int(bool(color_active)),
+                                   int(budget), _ptr(sel), _ptr(cnt), base, int(need.value),
+                                   _stream(stream)))
+    return sel, cnt, ws

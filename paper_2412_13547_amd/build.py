@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtgs.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "preprocess.hip", "sort.hip", "binning.hip", "raster.hip", "optim.hip"]
+SOURCES = ["api.cpp", "preprocess.hip", "sort.hip", "binning.hip", "raster.hip", "optim.hip", "densify.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -844,4 +844,40 @@ tgs_status tgs_adam_step(tgs_context* ctx, const tgs_adam_group* groups, int32_t
     return TGS_OK;
 }
 
+tgs_status tgs_densify_query(int64_t n, uint64_t* workspace_bytes) {
+    if (!workspace_bytes) return fail(TGS_ERR_INVALID_ARG, "workspace_bytes is NULL");
+    if (n < 0) return fail(TGS_ERR_INVALID_ARG, "n < 0");
+    if (n > int64_t(UINT32_MAX) - 1) return fail(TGS_ERR_UNSUPPORTED, "n exceeds 2^32 - 2");
+    *workspace_bytes = tgs::densify_workspace_bytes(n);
+    return TGS_OK;
+}
+
+tgs_status tgs_densify_select(tgs_context* ctx, int64_t n, const float* pos_sum,
+                              const float* col_sum, const int32_t* count, float tau_pos,
+                              float tau_col, int32_t color_active, int64_t budget,
+                              uint8_t* selected, uint32_t* n_selected, void* workspace,
+                              uint64_t workspace_bytes, void* stream) {
+    if (n < 0) return fail(TGS_ERR_INVALID_ARG, "n < 0");
+    if (n > int64_t(UINT32_MAX) - 1) return fail(TGS_ERR_UNSUPPORTED, "n exceeds 2^32 - 2");
+    if (n > 0 && (!pos_sum || !count || !selected || (color_active && !col_sum)))
+        return fail(TGS_ERR_INVALID_ARG, "a statistics or output pointer is NULL");
+    if (!n_selected) return fail(TGS_ERR_INVALID_ARG, "n_selected is NULL");
+    if (!(tau_pos > 0.0f) || !is_finite(tau_pos))
+        return fail(TGS_ERR_INVALID_ARG, "tau_pos must be positive and finite");
+    if (color_active && (!(tau_col > 0.0f) || !is_finite(tau_col)))
+        return fail(TGS_ERR_INVALID_ARG, "tau_col must be positive and finite");
+    if (budget < -1) return fail(TGS_ERR_INVALID_ARG, "budget must be >= -1");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(TGS_ERR_INVALID_ARG, "workspace must be a 256-byte aligned device buffer");
+    if (workspace_bytes < tgs::densify_workspace_bytes(n))
+        return fail(TGS_ERR_INVALID_ARG, "workspace of %llu bytes < %llu required",
+                    (unsigned long long)workspace_bytes,
+                    (unsigned long long)tgs::densify_workspace_bytes(n));
+    TGS_CHECK(use_device(ctx));
+    TGS_HIP(tgs::launch_densify(n, pos_sum, col_sum, count, tau_pos, tau_col, color_active ? 1 : 0,
+                                budget, selected, n_selected, static_cast<uint8_t*>(workspace),
+                                static_cast<hipStream_t>(stream)));
+    return TGS_OK;
+}
+
 }  // extern "C"

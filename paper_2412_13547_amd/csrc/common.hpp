@@ -184,6 +184,12 @@ struct AdamGroups {
 hipError_t launch_adam(const AdamGroups& groups, void* coeffs, float b1, float b2, float eps,
                        hipStream_t s);
 
+// Densification selection (densify.hip).
+uint64_t densify_workspace_bytes(int64_t n);
+hipError_t launch_densify(int64_t n, const float* pos, const float* col, const int32_t* count,
+                          float tau_pos, float tau_col, int color, int64_t budget,
+                          uint8_t* selected, uint32_t* n_selected, uint8_t* ws, hipStream_t s);
+
 hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

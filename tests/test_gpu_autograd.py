@@ -157,7 +157,8 @@ def test_200_iteration_fit_follows_the_checker():
     sc, cam = scenes.small_scene(11, 64, 64, 64, sh_degree=3)
     T = 8
     pert = _perturbed(sc, 12)
-    target = opipe.forward(pert, cam, 1, 0, 0, T)["image"].numpy().astype(np.float32)
+    target = np.ascontiguousarray(opipe.forward(pert, cam, 1, 0, 0, T)["image"].numpy(),
+                                  dtype=np.float32)
     iters = 200
     gl = _fit_gpu(sc, cam, target, iters, T)
     say(f"[gpu] fit: HIP loss {gl[0]:.6f} -> {gl[-1]:.6f}")
@@ -169,3 +170,14 @@ def test_200_iteration_fit_follows_the_checker():
     assert max(rel[:50]) <= 1e-3
     assert max(rel) <= 1e-2
     assert not any(math.isnan(x) for x in gl)
+
+
+def test_binding_refuses_strided_and_host_tensors():
+    sc, cam, tgt = _case()
+    view = api.View(ctx(), sc.n, cam, 2, 1, 0, 16)
+    img = autograd.rasterize(view, *[t.detach() for t in _leaves(sc)], sh_degree=3)
+    hwc = torch.as_tensor(np.ascontiguousarray(tgt.transpose(1, 2, 0))).cuda().permute(2, 0, 1)
+    with pytest.raises(ValueError, match="contiguous"):
+        autograd.l1_loss(view, img, hwc)
+    with pytest.raises(ValueError, match="device memory"):
+        autograd.l1_loss(view, img, torch.as_tensor(tgt))
