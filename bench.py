@@ -29,13 +29,18 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12                    # B/s, MI355X HBM3E
 PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
-# Arithmetic of the method per list entry (FP32 VALU lane-operations):
-#   every examined entry: offset, quadratic form, exp, opacity, clamp, the two
-#   threshold tests and the transmittance product            -> 21
-#   blended entry, forward: weight and colour accumulation       -> 7
-#   blended entry, backward: weight, prefix colour, d/drgb, d/dalpha through
-#   the colour behind, d/d(o, u, v, A, B, C), and the 9-value sum over pixels -> 67
-OPS_EXAMINE, OPS_BLEND_FWD, OPS_BLEND_BWD = 21, 7, 67
+# The least FP32 arithmetic the method needs per list entry and pixel (lane
+# operations, an FMA counts 1; per-splat work such as scaling the conic is
+# not counted):
+#   examined entry (forward up to the stop, backward up to the last blended
+#   entry): offset 2, quadratic form 5, exp 1, opacity product 1, clamp 1,
+#   the two skip tests 2, alpha T 1, T after the entry 1, stop test 1   -> 15
+#   blended entry, forward: colour accumulation 3                        -> 3
+#   blended entry, backward: weight 1, running colour 3, d/drgb 3,
+#   1 - alpha and its reciprocal 2, d/dalpha through the colour behind 12,
+#   clamp test, d/dpower, d/do 3, d/d(u, v, A, B, C) 9, the sums of the
+#   nine values over pixels 9, T update 1                                -> 43
+OPS_EXAMINE, OPS_BLEND_FWD, OPS_BLEND_BWD = 15, 3, 43
 STAGES = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd", "preprocess_bwd")
 
 
@@ -319,7 +324,7 @@ def run_batched(args, api, torch, np):
     res["speedup_vs_per_view_calls"] = res["ms_per_view_calls"] / res["ms_per_step"]
     res["speedup_graph_vs_eager"] = res["ms_eager"] / res["ms_per_step"]
     st = res["stages_ms"]
-    res["roofline_raster_bwd"] = dict(**_alu(OPS_EXAMINE * fwd_e + OPS_BLEND_BWD * blended,
+    res["roofline_raster_bwd"] = dict(**_alu(OPS_EXAMINE * bwd_e + OPS_BLEND_BWD * blended,
                                              st["raster_bwd"]))
     res["roofline_raster_fwd"] = dict(**_alu(OPS_EXAMINE * fwd_e + OPS_BLEND_FWD * blended,
                                              st["raster_fwd"]))
@@ -383,10 +388,10 @@ def main():
     # stage against HBM (bytes the implementation has to move)
     alu = _alu
     n = sc.n
-    roof_bwd = dict(kernel="raster_bwd_kernel<16,1,1>",
-                    **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_BWD * blended, stage["raster_bwd"]),
+    roof_bwd = dict(kernel="raster_bwd_kernel<16,1,256>",
+                    **alu(OPS_EXAMINE * bwd_evals + OPS_BLEND_BWD * blended, stage["raster_bwd"]),
                     traffic=None)
-    roof_fwd = dict(kernel="raster_fwd_kernel<16,1,1>",
+    roof_fwd = dict(kernel="raster_fwd_kernel<16,1,256,false>",
                     **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_FWD * blended, stage["raster_fwd"]))
     sort_bytes = 18.0 * pairs + 200.0 * n
     roof_sort = {"stage": "bin_sort", "bound": "hbm",

@@ -86,6 +86,10 @@ typedef struct tgs_options {
                                 rasterizer: 64, 128 or 256, or 0 for the default
                                 of the tile size.  Speed only; results do not
                                 depend on it.                                    */
+    int32_t pixels_per_thread; /* rasterizer work split: 1, 2 or 4 pixels per
+                                thread (tile 8: 1; tile 16: 1, 2, 4; tile 32:
+                                2, 4), or 0 for the default of the tile size.
+                                Speed only; results do not depend on it.        */
     float bg[3];             /* background colour added with the final T         */
     uint32_t flags;          /* must be 0                                        */
 } tgs_options;

@@ -50,8 +50,8 @@ class tgs_gaussians(C.Structure):
 
 
 class tgs_options(C.Structure):
-    _fields_ = [("tile", C.c_int32), ("lds_batch", C.c_int32), ("bg", C.c_float * 3),
-                ("flags", C.c_uint32)]
+    _fields_ = [("tile", C.c_int32), ("lds_batch", C.c_int32), ("pixels_per_thread", C.c_int32),
+                ("bg", C.c_float * 3), ("flags", C.c_uint32)]
 
 
 class tgs_grads(C.Structure):
@@ -195,10 +195,11 @@ def dilation_struct(stride=1, off_x=0, off_y=0) -> tgs_dilation:
     return tgs_dilation(int(stride), int(off_x), int(off_y))
 
 
-def options_struct(tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0) -> tgs_options:
+def options_struct(tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0, pixels_per_thread=0) -> tgs_options:
     o = tgs_options()
     o.tile = int(tile)
     o.lds_batch = int(lds_batch)
+    o.pixels_per_thread = int(pixels_per_thread)
     for k in range(3):
         o.bg[k] = float(bg[k])
     o.flags = 0
@@ -297,14 +298,14 @@ class View:
 
     def __init__(self, ctx: Context, n: int, cam, stride=1, off_x=0, off_y=0, tile=16,
                  bg=(0.0, 0.0, 0.0), pair_capacity: int | None = None, lds_batch: int = 0,
-                 state: tgs_state | None = None):
+                 state: tgs_state | None = None, pixels_per_thread: int = 0):
         import torch
         self.ctx = ctx
         self.n = int(n)
         self.cam = cam
         self.cam_s = camera_struct(cam)
         self.dil = dilation_struct(stride, off_x, off_y)
-        self.opt = options_struct(tile, bg, lds_batch)
+        self.opt = options_struct(tile, bg, lds_batch, pixels_per_thread)
         self.state = state if state is not None else tgs_state()
         self.workspace = None
         self.sizes = query_sizes(self.n, self.cam_s, self.dil, self.opt, 0)
@@ -454,7 +455,7 @@ class Batch:
     float32 device tensors set with ``set_targets``."""
 
     def __init__(self, ctx: Context, n: int, views, tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0,
-                 pair_capacity=None, counts: bool = False):
+                 pair_capacity=None, counts: bool = False, pixels_per_thread: int = 0):
         import torch
         self._torch = torch
         nv = len(views)
@@ -464,11 +465,12 @@ class Batch:
         self.states = (tgs_state * nv)()
         caps = pair_capacity if isinstance(pair_capacity, (list, tuple)) else [pair_capacity] * nv
         self.views = [View(ctx, n, cam, stride, ox, oy, tile, bg, pair_capacity=caps[k],
-                           lds_batch=lds_batch, state=self.states[k])
+                           lds_batch=lds_batch, state=self.states[k],
+                           pixels_per_thread=pixels_per_thread)
                       for k, (cam, stride, ox, oy) in enumerate(views)]
         self.cams = (tgs_camera * nv)(*[v.cam_s for v in self.views])
         self.dils = (tgs_dilation * nv)(*[v.dil for v in self.views])
-        self.opt = options_struct(tile, bg, lds_batch)
+        self.opt = options_struct(tile, bg, lds_batch, pixels_per_thread)
         self.io = (tgs_view_io * nv)()
         f32, i32 = torch.float32, torch.int32
         self.images = [torch.zeros(v.image_shape, dtype=f32, device="cuda") for v in self.views]

@@ -1,12 +1,13 @@
 """Launch autotuner of the batched rasterizer: times one graph-replayed fitting
 step (forward, L1 gradient, backward of every view) for each tile size T in
-{8, 16, 32} and each LDS batch B in {64, 128, 256}.
+{8, 16, 32}, each work split (pixels per thread P: 1 for T = 8; 1, 2, 4 for
+T = 16; 2, 4 for T = 32) and each LDS batch B in {64, 128, 256}.
 
-B (splat records staged per LDS round) only changes speed, so ``best_lds``
-maps every tile size to its fastest B and can be applied without changing
-any result.  T changes which Gaussians a pixel considers (the tile grid is
-part of the method's definition, Sec. 4.1), so ``best`` -- the fastest (T, B)
-overall -- is a suggestion for callers that accept another tile size.
+P and B only change speed, so ``best_launch`` maps every tile size to its
+fastest (P, B), which can be applied without changing any result.  T changes
+which Gaussians a pixel considers (the tile grid is part of the method's
+definition, Sec. 4.1), so ``best`` -- the fastest (T, P, B) overall -- is a
+suggestion for callers that accept another tile size.
 
     python -m paper_2412_13547_amd.autotune [--n 2000000] [--views 12] [--steps 5]
 
@@ -23,6 +24,7 @@ import sys
 
 TILES = (8, 16, 32)
 LDS_BATCHES = (64, 128, 256)
+SPLITS = {8: (1,), 16: (1, 2, 4), 32: (2, 4)}
 
 
 def _signature(n, views, sh_degree) -> str:
@@ -30,10 +32,10 @@ def _signature(n, views, sh_degree) -> str:
     return f"n={n}|deg={sh_degree}|{vs}"
 
 
-def time_config(api, torch, ctx, dev, views, targets, tile, lds, steps):
-    """Median ms of a graph-replayed batch step for one (tile, lds batch)."""
+def time_config(api, torch, ctx, dev, views, targets, tile, lds, steps, ppt=0):
+    """Median ms of a graph-replayed batch step for one (tile, split, lds batch)."""
     n = dev.n
-    b = api.Batch(ctx, n, views, tile=tile, lds_batch=lds)
+    b = api.Batch(ctx, n, views, tile=tile, lds_batch=lds, pixels_per_thread=ppt)
     b.set_targets(targets)
     b.fit_capacity(dev)
     grads = dev.zeros_like()
@@ -79,18 +81,19 @@ def tune(dev, views, targets, steps=5, tiles=TILES, lds_batches=LDS_BATCHES, cac
     ctx = api.Context(0)
     table = []
     for t in tiles:
-        for lb in lds_batches:
-            ms = time_config(api, torch, ctx, dev, views, targets, t, lb, steps)
-            table.append({"tile": t, "lds_batch": lb, "ms": ms})
-            if log:
-                log(f"# autotune T={t} B={lb}: {ms:.3f} ms")
-    best_lds = {}
+        for ppt in SPLITS[t]:
+            for lb in lds_batches:
+                ms = time_config(api, torch, ctx, dev, views, targets, t, lb, steps, ppt)
+                table.append({"tile": t, "pixels_per_thread": ppt, "lds_batch": lb, "ms": ms})
+                if log:
+                    log(f"# autotune T={t} P={ppt} B={lb}: {ms:.3f} ms")
+    best_launch = {}
     for t in tiles:
-        rows = [r for r in table if r["tile"] == t]
-        best_lds[str(t)] = min(rows, key=lambda r: r["ms"])["lds_batch"]
+        r = min((r for r in table if r["tile"] == t), key=lambda r: r["ms"])
+        best_launch[str(t)] = {"pixels_per_thread": r["pixels_per_thread"],
+                               "lds_batch": r["lds_batch"], "ms": r["ms"]}
     best = min(table, key=lambda r: r["ms"])
-    out = {"table": table, "best_lds": best_lds,
-           "best": {"tile": best["tile"], "lds_batch": best["lds_batch"], "ms": best["ms"]}}
+    out = {"table": table, "best_launch": best_launch, "best": dict(best)}
     if cache:
         stored = {}
         if os.path.exists(cache):

@@ -79,6 +79,14 @@ tgs_status check_options(const tgs_options* opt) {
     if (opt->lds_batch != 0 && opt->lds_batch != 64 && opt->lds_batch != 128 &&
         opt->lds_batch != 256)
         return fail(TGS_ERR_INVALID_ARG, "lds_batch %d must be 0, 64, 128 or 256", opt->lds_batch);
+    const int ppt = opt->pixels_per_thread;
+    const bool ppt_ok = ppt == 0 || (opt->tile == 8 && ppt == 1) ||
+                        (opt->tile == 16 && (ppt == 1 || ppt == 2 || ppt == 4)) ||
+                        (opt->tile == 32 && (ppt == 2 || ppt == 4));
+    if (!ppt_ok)
+        return fail(TGS_ERR_INVALID_ARG,
+                    "pixels_per_thread %d not available for tile %d (8: 1; 16: 1, 2, 4; 32: 2, 4)",
+                    ppt, opt->tile);
     if (opt->flags != 0) return fail(TGS_ERR_INVALID_ARG, "option flags must be 0");
     for (int c = 0; c < 3; ++c)
         if (!is_finite(opt->bg[c])) return fail(TGS_ERR_INVALID_ARG, "background is not finite");
@@ -167,6 +175,10 @@ tgs_status use_device(tgs_context* ctx) {
     return TGS_OK;
 }
 
+// Buffer holding the dispatch order after launch_tile_order (the number of
+// radix passes over 32-bit keys is fixed, so the index is too).
+int tile_order_buffer() { return tgs::radix_sort_passes(32) % 2; }
+
 // The table entry of one view for the preprocess kernels.
 tgs::PrepView prep_view(const tgs_camera& cam, const tgs::Grid& grid, uint8_t* ws,
                         const tgs::Layout& L) {
@@ -193,6 +205,7 @@ tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const
     v.ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
     v.vals = reinterpret_cast<const uint32_t*>(ws + L.pair_vals);
     v.pair_count = reinterpret_cast<const uint32_t*>(ws + L.row_start) + grid.gy;
+    v.order = reinterpret_cast<const uint32_t*>(ws + L.tile_val[tile_order_buffer()]);
     v.g2d = reinterpret_cast<float*>(ws + L.grad2d);
     return v;
 }
@@ -206,6 +219,10 @@ void add_raster_view(tgs::RasterViews& t, const tgs::RasterView& v) {
 
 int lds_batch_of(const tgs_options& opt) {
     return opt.lds_batch ? opt.lds_batch : tgs::default_lds_batch(opt.tile);
+}
+
+int ppt_of(const tgs_options& opt) {
+    return opt.pixels_per_thread ? opt.pixels_per_thread : tgs::default_pixels_per_thread(opt.tile);
 }
 
 // Depth sort and the pair counts per (tile row, chunk), up to the row starts
@@ -236,6 +253,9 @@ tgs_status enqueue_emit(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid
                         hipStream_t strm) {
     TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, capacity, strm));
     TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, capacity, strm));
+    int res = 0;
+    TGS_HIP(tgs::launch_tile_order(ws, L, grid, &res, strm));
+    if (res != tile_order_buffer()) return fail(TGS_ERR_HIP, "tile order in an unexpected buffer");
     return TGS_OK;
 }
 
@@ -281,10 +301,14 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.row_vals = take(cap * 4);
     L.pair_vals = take(cap * 4);
     L.col_hist = take(hist * 4);
-    L.ranges = take(uint64_t(grid.num_tiles()) * 8);
+    const uint64_t nt = uint64_t(grid.num_tiles());
+    L.ranges = take(nt * 8);
+    for (int b = 0; b < 2; ++b) L.tile_key[b] = take(nt * 4);
+    for (int b = 0; b < 2; ++b) L.tile_val[b] = take(nt * 4);
     L.grad2d = take(un * kGrad2d * 4);
-    L.sort_counts = take(radix_counts_elems(un) * 4);
-    uint64_t most = radix_counts_elems(un);
+    const uint64_t sorted = un > nt ? un : nt;       // the depth sort and the tile order
+    L.sort_counts = take(radix_counts_elems(sorted) * 4);
+    uint64_t most = radix_counts_elems(sorted);
     if (rowtot > most) most = rowtot;
     if (hist > most) most = hist;
     L.scan_partials = take(scan_partials_elems(most) * 8);
@@ -293,6 +317,8 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
 }
 
 int default_lds_batch(int tile) { return tile == 8 ? 64 : 256; }
+
+int default_pixels_per_thread(int tile) { return tile == 32 ? 4 : 1; }
 
 CamDev make_cam(const tgs_camera& c) {
     CamDev d{};
@@ -464,7 +490,7 @@ tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     v.n_blend = n_blend;
     tgs::RasterViews t{};
     add_raster_view(t, v);
-    TGS_HIP(tgs::launch_raster_fwd(opt->tile, lds_batch_of(*opt), t,
+    TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), t,
                                    static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
@@ -514,7 +540,7 @@ tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(v.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
     tgs::RasterViews t{};
     add_raster_view(t, v);
-    TGS_HIP(tgs::launch_raster_bwd(opt->tile, lds_batch_of(*opt), t, strm));
+    TGS_HIP(tgs::launch_raster_bwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), t, strm));
     return TGS_OK;
 }
 
@@ -685,7 +711,7 @@ tgs_status tgs_batch_raster_fwd(tgs_context* ctx, int64_t n, int32_t views, cons
         rv.n_blend = io[v].n_blend;
         add_raster_view(rt, rv);
     }
-    TGS_HIP(tgs::launch_raster_fwd(opt->tile, lds_batch_of(*opt), rt,
+    TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), rt,
                                    static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
@@ -745,7 +771,7 @@ tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views, cons
         TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(rv.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
         add_raster_view(rt, rv);
     }
-    TGS_HIP(tgs::launch_raster_bwd(opt->tile, lds_batch_of(*opt), rt, strm));
+    TGS_HIP(tgs::launch_raster_bwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), rt, strm));
     return TGS_OK;
 }
 

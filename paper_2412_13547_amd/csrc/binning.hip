@@ -366,6 +366,17 @@ col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict
     }
 }
 
+// Dispatch key of every tile: decreasing list length, so the longest lists
+// start first and the short ones fill in behind them.
+__global__ void __launch_bounds__(256)
+tile_cost_kernel(const uint32_t* __restrict__ ranges, uint32_t num_tiles,
+                 uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= num_tiles) return;
+    keys[t] = ~(ranges[2 * t + 1] - ranges[2 * t]);
+    vals[t] = t;
+}
+
 size_t scatter_lds_bytes(int gx) {
     return size_t(kSlice) * 4 + size_t(kScatterWaves * gx + 2 * gx + kScatterWaves) * 4 +
            size_t(kSlice) * 2;
@@ -408,6 +419,20 @@ hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order,
         reinterpret_cast<const uint32_t*>(ws + L.rowtot), nchunks, capacity,
         reinterpret_cast<uint16_t*>(ws + L.row_cols), reinterpret_cast<uint32_t*>(ws + L.row_vals));
     return hipGetLastError();
+}
+
+hipError_t launch_tile_order(uint8_t* ws, const Layout& L, const Grid& grid, int* result,
+                             hipStream_t s) {
+    const uint32_t nt = uint32_t(grid.num_tiles());
+    auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+    uint32_t* keys[2] = {u32(L.tile_key[0]), u32(L.tile_key[1])};
+    uint32_t* vals[2] = {u32(L.tile_val[0]), u32(L.tile_val[1])};
+    tile_cost_kernel<<<dim3((nt + 255) / 256), dim3(256), 0, s>>>(u32(L.ranges), nt, keys[0],
+                                                                  vals[0]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return radix_sort(keys, vals, nt, 32, u32(L.sort_counts),
+                      reinterpret_cast<uint64_t*>(ws + L.scan_partials), result, s);
 }
 
 hipError_t prepare_binning_kernels() {

@@ -25,61 +25,79 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
 
-// alpha = min(0.99, o exp(p)), p = -1/2 (A dx^2 + C dy^2) - B dx dy; false if
-// the entry is skipped (p > 0 or alpha < 1/255).  ga = (u, v, A, B),
-// gb = (C, o, r, g).  G and alpha are computed either way (branch-free
-// callers select on the result).  Compiled without FP contraction: forward
-// and backward evaluate exactly the same operations.
-__device__ __forceinline__ bool splat_alpha(const float4 ga, const float4 gb, float X, float Y,
-                                            float& dx, float& dy, float& G, float& alpha) {
-    dx = ga.x - X;
-    dy = ga.y - Y;
-    const float power = -0.5f * (ga.z * dx * dx + gb.x * dy * dy) - ga.w * dx * dy;
-    G = __builtin_amdgcn_exp2f(power * kLog2e);
-    alpha = fminf(kAlphaMax, gb.y * G);
-    return power <= 0.0f && alpha >= kAlphaMin;
+// Splat constants as staged in LDS.  The conic is pre-scaled so that the
+// exponent comes out in base 2 with no extra multiply:
+//   qa = -A log2(e) / 2,  qb = -B log2(e),  qc = -C log2(e) / 2,
+//   log2(e) * power = dx (qa dx + qb dy) + qc dy dy,   dx = u - X, dy = v - Y.
+// ga = (u, v, qa, qb), gb = (qc, o, r, g).
+__device__ __forceinline__ void stage_conic(const float4 r0, const float4 r1, float4& ga,
+                                            float4& gb) {
+    constexpr float kHalf = -0.5f * kLog2e, kFull = -kLog2e;
+    ga = make_float4(r0.x, r0.y, r0.z * kHalf, r0.w * kFull);
+    gb = make_float4(r1.x * kHalf, r1.y, r1.z, r1.w);
 }
 
-// Launch shape: a T x T tile is covered by (T/P) x (T/P) threads owning P x P
-// pixels each; B splat records are staged per LDS round.
-template <int T, int B_>
+// alpha = min(0.99, o 2^(log2e power)); false if the entry is skipped
+// (power > 0 or alpha < 1/255; o G >= 1/255 is the same test since
+// 0.99 > 1/255).  G, alpha and the partial t = qb dy are
+// computed either way (branch-free callers select on the result).  Forward
+// and backward evaluate exactly these operations (explicit FMAs, no
+// contraction elsewhere), so they take bit-identical decisions.
+__device__ __forceinline__ bool splat_alpha(const float4 ga, const float4 gb, float X, float Y,
+                                            float& dx, float& dy, float& t, float& G,
+                                            float& raw, float& alpha) {
+    dx = ga.x - X;
+    dy = ga.y - Y;
+    t = ga.w * dy;
+    const float p2 = fmaf(dx, fmaf(ga.z, dx, t), (gb.x * dy) * dy);
+    G = __builtin_amdgcn_exp2f(p2);
+    raw = gb.y * G;
+    alpha = fminf(kAlphaMax, raw);
+    return p2 <= 0.0f && raw >= kAlphaMin;
+}
+
+// Launch shape (the work split): a T x T tile is covered by (T/PX) x (T/PY)
+// threads owning PX x PY pixels each (PPT = PX PY = 1, 2 or 4); each LDS
+// read of a splat then serves PPT pixels.
+// Each wavefront covers an 8 x 8 block of threads, so its pixels form a
+// compact square whose walks end at similar depths (a wavefront iterates
+// until its last pixel saturates).
+template <int T, int PPT>
 struct Shape {
-    static constexpr int P = T == 32 ? 2 : 1, NP = P * P;
-    static constexpr int TX = T / P, NT = TX * TX;   // threads
-    static constexpr int B = B_;
+    static constexpr int PX = PPT >= 2 ? 2 : 1, PY = PPT == 4 ? 2 : 1, NP = PX * PY;
+    static constexpr int TX = T / PX, TY = T / PY, NT = TX * TY;   // threads
+    static_assert(TX % 8 == 0 && TY % 8 == 0, "threads must tile into 8 x 8 wavefronts");
+    // thread -> (column, row) of its first pixel within the tile
+    __device__ static int px(int tid) { return ((tid >> 6) % (TX / 8) * 8 + (tid & 7)) * PX; }
+    __device__ static int py(int tid) { return ((tid >> 6) / (TX / 8) * 8 + ((tid >> 3) & 7)) * PY; }
 };
 
-// Which view and tile workgroup b works on.
+// Which view and tile workgroup b works on: the views' workgroups are laid
+// out one view after the other, and within a view the tiles are dispatched
+// in the view's order (longest lists first).
 __device__ __forceinline__ bool locate(const RasterViews& vt, uint32_t b, int& v, int64_t& tile) {
     if (b >= vt.first_block[vt.count]) return false;
     v = 0;
     while (b >= vt.first_block[v + 1]) ++v;
-    tile = int64_t(b - vt.first_block[v]);
+    const uint32_t k = b - vt.first_block[v];
+    const uint32_t* order = vt.v[v].order;
+    tile = int64_t(order ? uint32_t(__builtin_amdgcn_readfirstlane(int(order[k]))) : k);
     return true;
 }
 
 // Clamp a tile's range to the pairs that exist: a view whose binning
 // overflowed its capacity reports a pair count above it and renders nothing.
+// The bounds are made wave-uniform (scalar registers).
 __device__ __forceinline__ void tile_range(const RasterView& rv, int64_t tile, uint32_t& start,
                                            uint32_t& end) {
     const uint32_t pc = *rv.pair_count;
     const uint32_t lim = pc <= rv.capacity ? pc : 0u;
-    end = min(rv.ranges[2 * tile + 1], lim);
-    start = min(rv.ranges[2 * tile], end);
-}
-
-// Stage records [base, base + cnt) of the list into LDS (all threads).
-template <int NT, int B>
-__device__ __forceinline__ void stage(const RasterView& rv, uint32_t base, int cnt, float4* s_a,
-                                      float4* s_b, float* s_c, uint32_t* s_id) {
-    for (int q = threadIdx.x; q < cnt; q += NT) {
-        const uint32_t id = rv.vals[base + q];
-        if (s_id) s_id[q] = id;
-        s_a[q] = rv.rec[3 * uint64_t(id)];
-        s_b[q] = rv.rec[3 * uint64_t(id) + 1];
-        s_c[q] = rv.rec[3 * uint64_t(id) + 2].x;
-    }
+    const uint32_t e = min(rv.ranges[2 * tile + 1], lim);
+    const uint32_t s = min(rv.ranges[2 * tile], e);
+    start = uint32_t(__builtin_amdgcn_readfirstlane(int(s)));
+    end = uint32_t(__builtin_amdgcn_readfirstlane(int(e)));
 }
 
 // a + b after exchanging the upper 32 lanes of a with the lower 32 of b:
@@ -134,9 +152,10 @@ __device__ __forceinline__ float wave_sum9(const float* v, int& comp) {
     return y;
 }
 
-template <int T, int BATCH>
-__global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_fwd_kernel(RasterViews vt) {
-    using S = Shape<T, BATCH>;
+// COUNTS adds the per-pixel counters last_contrib, n_eval and n_blend.
+template <int T, int PPT, int BATCH, bool COUNTS>
+__global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterViews vt) {
+    using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH];
     __shared__ float s_c[BATCH];
     int v;
@@ -146,7 +165,7 @@ __global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_fwd_kernel(Raste
     const Grid& grid = rv.grid;
     const int tid = threadIdx.x;
     const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
-    const int i0 = tx * T + (tid % S::TX) * S::P, j0 = ty * T + (tid / S::TX) * S::P;
+    const int i0 = tx * T + S::px(tid), j0 = ty * T + S::py(tid);
     uint32_t start, end;
     tile_range(rv, tile, start, end);
     float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
@@ -155,7 +174,7 @@ __global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_fwd_kernel(Raste
     bool alive = false;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
-        const int i = i0 + k % S::P, j = j0 + k / S::P;
+        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
         done[k] = !(i < grid.w_ds && j < grid.h_ds);
         alive |= !done[k];
         X[k] = float(grid.stride * i + grid.off_x);
@@ -169,56 +188,85 @@ __global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_fwd_kernel(Raste
     for (uint32_t base = start; base < end; base += BATCH) {
         if (__syncthreads_count(alive) == 0) break;
         const int cnt = min(BATCH, int(end - base));
-        stage<S::NT, BATCH>(rv, base, cnt, s_a, s_b, s_c, nullptr);
+        for (int q = tid; q < cnt; q += S::NT) {
+            const uint32_t id = rv.vals[base + q];
+            const float4* r = rv.rec + 3 * uint64_t(id);
+            stage_conic(r[0], r[1], s_a[q], s_b[q]);
+            s_c[q] = r[2].x;
+        }
         __syncthreads();
         // branch-free per entry: a skipped entry adds exactly 0 and leaves T
-        for (int e = 0; e < cnt; ++e) {
-            if (__ballot(alive) == 0) break;           // the whole wavefront has stopped
+        auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
             const float bb = s_c[e];
-            const uint32_t pos = base - start + uint32_t(e) + 1;
             alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                float dx, dy, G, alpha;
-                const bool hit = splat_alpha(a, b, X[k], Y[k], dx, dy, G, alpha) && !done[k];
-                const float Tn = Tr[k] * (1.0f - alpha);
-                const bool stop = hit && Tn < kTMin;
-                const bool blend = hit && !stop;
-                const float w = blend ? alpha * Tr[k] : 0.0f;
-                c0[k] += b.z * w;
-                c1[k] += b.w * w;
-                c2[k] += bb * w;
-                Tr[k] = blend ? Tn : Tr[k];
-                last[k] = blend ? pos : last[k];
-                nblend[k] += blend ? 1u : 0u;
-                neval[k] = stop ? pos : neval[k];
+                float dx, dy, t, G, raw, alpha;
+                const bool hit = splat_alpha(a, b, X[k], Y[k], dx, dy, t, G, raw, alpha) && !done[k];
+                const float w0 = alpha * Tr[k];
+                const bool keep = Tr[k] - w0 >= kTMin;      // T after this entry
+                const bool blend = hit && keep;
+                const bool stop = hit && !keep;
+                const float w = blend ? w0 : 0.0f;
+                c0[k] = fmaf(b.z, w, c0[k]);
+                c1[k] = fmaf(b.w, w, c1[k]);
+                c2[k] = fmaf(bb, w, c2[k]);
+                Tr[k] = Tr[k] - w;
+                if constexpr (COUNTS) {
+                    const uint32_t pos = base - start + uint32_t(e) + 1;
+                    last[k] = blend ? pos : last[k];
+                    nblend[k] += blend ? 1u : 0u;
+                    neval[k] = stop ? pos : neval[k];
+                }
                 done[k] = done[k] || stop;
                 alive = alive || !done[k];
             }
+        };
+        // the wavefront leaves as soon as all its pixels have stopped, checked
+        // every fourth entry (entries after a stop change nothing)
+        int e = 0;
+        for (; e + 4 <= cnt; e += 4) {
+            if (__ballot(alive) == 0) break;
+            entry(e);
+            entry(e + 1);
+            entry(e + 2);
+            entry(e + 3);
+        }
+        for (; e < cnt; ++e) {
+            if (__ballot(alive) == 0) break;
+            entry(e);
         }
     }
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
-        const int i = i0 + k % S::P, j = j0 + k / S::P;
+        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
         if (!(i < grid.w_ds && j < grid.h_ds)) continue;
         const uint64_t p = uint64_t(j) * grid.w_ds + i;
-        rv.image[p] = c0[k] + Tr[k] * rv.bg[0];
-        rv.image[pix + p] = c1[k] + Tr[k] * rv.bg[1];
-        rv.image[2 * pix + p] = c2[k] + Tr[k] * rv.bg[2];
+        rv.image[p] = fmaf(Tr[k], rv.bg[0], c0[k]);
+        rv.image[pix + p] = fmaf(Tr[k], rv.bg[1], c1[k]);
+        rv.image[2 * pix + p] = fmaf(Tr[k], rv.bg[2], c2[k]);
         if (rv.t_final) rv.t_final[p] = Tr[k];
-        if (rv.last_contrib) rv.last_contrib[p] = last[k];
-        if (rv.n_eval) rv.n_eval[p] = neval[k];
-        if (rv.n_blend) rv.n_blend[p] = nblend[k];
+        if constexpr (COUNTS) {
+            if (rv.last_contrib) rv.last_contrib[p] = last[k];
+            if (rv.n_eval) rv.n_eval[p] = neval[k];
+            if (rv.n_blend) rv.n_blend[p] = nblend[k];
+        }
     }
 }
 
-template <int T, int BATCH>
-__global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_bwd_kernel(RasterViews vt) {
-    using S = Shape<T, BATCH>;
-    __shared__ float4 s_a[BATCH], s_b[BATCH];
-    __shared__ float s_c[BATCH];
+// Per blended entry the lane's contribution to the nine sums, as moments
+// that the wave reduces first; the constant factors of each component
+// (ln 2 for u and v, -1/2, -1, -1/2 for A, B, C) are applied once per wave
+// to the reduced sums:
+//   dL/du = ln2 sum dp (qa2 dx + qb dy),  dL/dv = ln2 sum dp (qc2 dy + qb dx),
+//   dL/dA = -1/2 sum dp dx^2,  dL/dB = -sum dp dx dy,  dL/dC = -1/2 sum dp dy^2,
+// with dp = dL/dpower, qa2 = 2 qa, qc2 = 2 qc.
+template <int T, int PPT, int BATCH>
+__global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterViews vt) {
+    using S = Shape<T, PPT>;
+    __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
     __shared__ uint32_t s_id[BATCH];
     int v;
     int64_t tile;
@@ -227,7 +275,7 @@ __global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_bwd_kernel(Raste
     const Grid& grid = rv.grid;
     const int tid = threadIdx.x;
     const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
-    const int i0 = tx * T + (tid % S::TX) * S::P, j0 = ty * T + (tid / S::TX) * S::P;
+    const int i0 = tx * T + S::px(tid), j0 = ty * T + S::py(tid);
     uint32_t start, end;
     tile_range(rv, tile, start, end);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
@@ -237,7 +285,7 @@ __global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_bwd_kernel(Raste
     bool alive = false;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
-        const int i = i0 + k % S::P, j = j0 + k / S::P;
+        const int i = i0 + k % S::PX, j = j0 + k / S::PX;
         const bool in = i < grid.w_ds && j < grid.h_ds;
         done[k] = !in;
         alive |= in;
@@ -256,62 +304,91 @@ __global__ void __launch_bounds__((Shape<T, BATCH>::NT)) raster_bwd_kernel(Raste
             im2[k] = rv.image[2 * pix + p];
         }
     }
+    // factor of the component this lane owns after wave_sum9
+    const int lane = __lane_id();
+    const int own = (lane & 7) == 0 ? (lane >> 3) : (lane == 1 ? 8 : -1);
+    const float scale = own == 0 || own == 1 ? kLn2
+                        : own == 2 || own == 4 ? -0.5f
+                        : own == 3 ? -1.0f : 1.0f;
     for (uint32_t base = start; base < end; base += BATCH) {
         if (__syncthreads_count(alive) == 0) break;
         const int cnt = min(BATCH, int(end - base));
-        stage<S::NT, BATCH>(rv, base, cnt, s_a, s_b, s_c, s_id);
+        for (int q = tid; q < cnt; q += S::NT) {
+            const uint32_t id = rv.vals[base + q];
+            const float4* r = rv.rec + 3 * uint64_t(id);
+            float4 ga, gb;
+            stage_conic(r[0], r[1], ga, gb);
+            s_a[q] = ga;
+            s_b[q] = gb;
+            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, 0.0f);
+            s_id[q] = id;
+        }
         __syncthreads();
-        for (int e = 0; e < cnt; ++e) {
-            if (__ballot(alive) == 0) break;          // the whole wavefront has stopped
+        auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
-            const float bb = s_c[e];
             // decisions, exactly as in the forward
-            float dx[S::NP], dy[S::NP], G[S::NP], alpha[S::NP];
+            float dx[S::NP], dy[S::NP], t[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
             bool blend[S::NP];
             bool any = false;
             alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const bool hit = splat_alpha(a, b, X[k], Y[k], dx[k], dy[k], G[k], alpha[k]) && !done[k];
-                const bool stop = hit && Tr[k] * (1.0f - alpha[k]) < kTMin;
-                blend[k] = hit && !stop;
+                const bool hit =
+                    splat_alpha(a, b, X[k], Y[k], dx[k], dy[k], t[k], G[k], raw[k], alpha[k]) && !done[k];
+                const bool keep = Tr[k] - alpha[k] * Tr[k] >= kTMin;
+                const bool stop = hit && !keep;
+                blend[k] = hit && keep;
                 any = any || blend[k];
                 done[k] = done[k] || stop;
                 alive = alive || !done[k];
             }
-            if (__ballot(any) == 0) continue;          // no pixel of the wavefront blends it
+            if (__ballot(any) == 0) return;            // no pixel of the wavefront blends it
+            const float4 c = s_c[e];                  // (b, qa2, qc2, -)
             float gv[kGrad2d];
-#pragma unroll
-            for (int c = 0; c < kGrad2d; ++c) gv[c] = 0.0f;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
                 const float T0 = Tr[k];
                 const float w = blend[k] ? alpha[k] * T0 : 0.0f;
-                p0[k] += b.z * w;
-                p1[k] += b.w * w;
-                p2[k] += bb * w;
-                gv[6] += w * g0[k];
-                gv[7] += w * g1[k];
-                gv[8] += w * g2[k];
+                p0[k] = fmaf(b.z, w, p0[k]);
+                p1[k] = fmaf(b.w, w, p1[k]);
+                p2[k] = fmaf(c.x, w, p2[k]);
                 // d image / d alpha = rgb T - (colour behind) / (1 - alpha)
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[k]);
-                const float dal = g0[k] * (b.z * T0 - (im0[k] - p0[k]) * inv) +
-                                  g1[k] * (b.w * T0 - (im1[k] - p1[k]) * inv) +
-                                  g2[k] * (bb * T0 - (im2[k] - p2[k]) * inv);
+                const float dal = g0[k] * fmaf(p0[k] - im0[k], inv, b.z * T0) +
+                                  g1[k] * fmaf(p1[k] - im1[k], inv, b.w * T0) +
+                                  g2[k] * fmaf(p2[k] - im2[k], inv, c.x * T0);
                 // no gradient through the 0.99 clamp
-                const bool live = blend[k] && !(b.y * G[k] > kAlphaMax);
+                const bool live = blend[k] && !(raw[k] > kAlphaMax);
                 const float dp = live ? alpha[k] * dal : 0.0f;
-                gv[5] += live ? G[k] * dal : 0.0f;
-                gv[0] -= dp * (a.z * dx[k] + a.w * dy[k]);
-                gv[1] -= dp * (b.x * dy[k] + a.w * dx[k]);
-                gv[2] -= 0.5f * dp * dx[k] * dx[k];
-                gv[3] -= dp * dx[k] * dy[k];
-                gv[4] -= 0.5f * dp * dy[k] * dy[k];
-                Tr[k] = blend[k] ? T0 * (1.0f - alpha[k]) : T0;
+                const float pdx = dp * dx[k], pdy = dp * dy[k];
+                const float m[kGrad2d] = {
+                    fmaf(c.y, dx[k], t[k]) * dp,            // (qa2 dx + qb dy) dp
+                    fmaf(c.z, dy[k], a.w * dx[k]) * dp,     // (qc2 dy + qb dx) dp
+                    pdx * dx[k], pdx * dy[k], pdy * dy[k],
+                    live ? G[k] * dal : 0.0f,
+                    w * g0[k], w * g1[k], w * g2[k]};
+#pragma unroll
+                for (int q = 0; q < kGrad2d; ++q) gv[q] = k == 0 ? m[q] : gv[q] + m[q];
+                Tr[k] = T0 - w;
             }
             int comp;
-            const float s = wave_sum9(gv, comp);
-            if (comp >= 0 && s != 0.0f) atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], s);
+            const float sum = wave_sum9(gv, comp);
+            if (comp >= 0 && sum != 0.0f)
+                atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], sum * scale);
+        };
+        // the wavefront leaves once all its pixels have stopped, checked every
+        // fourth entry (entries after a stop change nothing)
+        int e = 0;
+        for (; e + 4 <= cnt; e += 4) {
+            if (__ballot(alive) == 0) break;
+            entry(e);
+            entry(e + 1);
+            entry(e + 2);
+            entry(e + 3);
+        }
+        for (; e < cnt; ++e) {
+            if (__ballot(alive) == 0) break;
+            entry(e);
         }
     }
 }
@@ -344,36 +421,53 @@ l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restri
     }
 }
 
-template <int T, int B>
+bool wants_counts(const RasterViews& vt) {
+    for (int k = 0; k < vt.count; ++k)
+        if (vt.v[k].last_contrib || vt.v[k].n_eval || vt.v[k].n_blend) return true;
+    return false;
+}
+
+template <int T, int PPT, int B>
 void launch_both(bool fwd, const RasterViews& vt, hipStream_t s) {
-    const dim3 grid(vt.first_block[vt.count]), block(Shape<T, B>::NT);
-    if (fwd) raster_fwd_kernel<T, B><<<grid, block, 0, s>>>(vt);
-    else raster_bwd_kernel<T, B><<<grid, block, 0, s>>>(vt);
+    const dim3 grid(vt.first_block[vt.count]), block(Shape<T, PPT>::NT);
+    if (!fwd) raster_bwd_kernel<T, PPT, B><<<grid, block, 0, s>>>(vt);
+    else if (wants_counts(vt)) raster_fwd_kernel<T, PPT, B, true><<<grid, block, 0, s>>>(vt);
+    else raster_fwd_kernel<T, PPT, B, false><<<grid, block, 0, s>>>(vt);
 }
 
-template <int T>
-void launch_tile(bool fwd, int batch, const RasterViews& vt, hipStream_t s) {
-    if (batch == 64) launch_both<T, 64>(fwd, vt, s);
-    else if (batch == 128) launch_both<T, 128>(fwd, vt, s);
-    else launch_both<T, 256>(fwd, vt, s);
+template <int T, int PPT>
+void launch_batch(bool fwd, int batch, const RasterViews& vt, hipStream_t s) {
+    if (batch == 64) launch_both<T, PPT, 64>(fwd, vt, s);
+    else if (batch == 128) launch_both<T, PPT, 128>(fwd, vt, s);
+    else launch_both<T, PPT, 256>(fwd, vt, s);
 }
 
-hipError_t launch_raster(bool fwd, int tile, int batch, const RasterViews& vt, hipStream_t s) {
+// Work splits compiled per tile size: T = 8 one pixel per thread (a single
+// wavefront); T = 16 one, two or four; T = 32 two or four.
+hipError_t launch_raster(bool fwd, int tile, int ppt, int batch, const RasterViews& vt,
+                         hipStream_t s) {
     if (vt.count == 0 || vt.first_block[vt.count] == 0) return hipSuccess;
-    if (tile == 8) launch_tile<8>(fwd, batch, vt, s);
-    else if (tile == 32) launch_tile<32>(fwd, batch, vt, s);
-    else launch_tile<16>(fwd, batch, vt, s);
+    if (tile == 8) {
+        launch_batch<8, 1>(fwd, batch, vt, s);
+    } else if (tile == 32) {
+        if (ppt == 2) launch_batch<32, 2>(fwd, batch, vt, s);
+        else launch_batch<32, 4>(fwd, batch, vt, s);
+    } else {
+        if (ppt == 2) launch_batch<16, 2>(fwd, batch, vt, s);
+        else if (ppt == 4) launch_batch<16, 4>(fwd, batch, vt, s);
+        else launch_batch<16, 1>(fwd, batch, vt, s);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_raster_fwd(int tile, int batch, const RasterViews& vt, hipStream_t s) {
-    return launch_raster(true, tile, batch, vt, s);
+hipError_t launch_raster_fwd(int tile, int ppt, int batch, const RasterViews& vt, hipStream_t s) {
+    return launch_raster(true, tile, ppt, batch, vt, s);
 }
 
-hipError_t launch_raster_bwd(int tile, int batch, const RasterViews& vt, hipStream_t s) {
-    return launch_raster(false, tile, batch, vt, s);
+hipError_t launch_raster_bwd(int tile, int ppt, int batch, const RasterViews& vt, hipStream_t s) {
+    return launch_raster(false, tile, ppt, batch, vt, s);
 }
 
 hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,

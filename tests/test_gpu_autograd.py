@@ -126,7 +126,7 @@ def _fit_gpu(sc, cam, target, iters, T):
     return losses
 
 
-def _fit_oracle(sc, cam, target, iters, T):
+def _fit_oracle(sc, cam, target, iters, T, probe=None, probe_every=20):
     t64 = lambda a: torch.as_tensor(np.asarray(a, np.float64)).clone()
     P = dict(means=t64(sc.means), log_scales=t64(np.log(sc.scales)), quats=t64(sc.quats),
              logit=t64(np.log(sc.opacities.astype(np.float64) / (1 - sc.opacities))), sh=t64(sc.sh))
@@ -140,6 +140,8 @@ def _fit_oracle(sc, cam, target, iters, T):
                              P["sh"].numpy(), sc.sh_degree)
         res = opipe.forward_backward(scene, cam, target, 2, ox, oy, T)
         g = res["grads"]
+        if probe is not None and k % probe_every == 0:
+            probe(k, scene, (ox, oy), g)
         P["means"].grad = g["means"].T.contiguous()
         P["log_scales"].grad = (g["scales"].T * s).contiguous()
         P["quats"].grad = g["quats"].T.contiguous()
@@ -152,8 +154,14 @@ def _fit_oracle(sc, cam, target, iters, T):
 
 def test_200_iteration_fit_follows_the_checker():
     """Fit a 64-Gaussian scene (64x64, stride 2, phases cycling) to a target
-    the checker renders from a perturbed copy; the loss curves of the HIP path
-    (float32) and the checker (float64) must agree at every iteration."""
+    the checker renders from a perturbed copy.
+
+    Teacher-forced: every 20 iterations the HIP path's gradients, taken at the
+    checker's own parameters of that iteration, match the checker's (1e-3 of
+    the norm).  Free-running: the two loss curves agree to 1e-3 over the first
+    50 iterations and stay within a 3e-2 band to 200; near convergence the
+    sign-dominated L1 gradient amplifies float32 rounding of the trajectory
+    chaotically (1e-2 has been observed), so the late band is looser."""
     sc, cam = scenes.small_scene(11, 64, 64, 64, sh_degree=3)
     T = 8
     pert = _perturbed(sc, 12)
@@ -162,13 +170,32 @@ def test_200_iteration_fit_follows_the_checker():
     iters = 200
     gl = _fit_gpu(sc, cam, target, iters, T)
     say(f"[gpu] fit: HIP loss {gl[0]:.6f} -> {gl[-1]:.6f}")
-    ol = _fit_oracle(sc, cam, target, iters, T)
+    view = api.View(ctx(), sc.n, cam, 2, 0, 0, T)
+    tg = torch.as_tensor(target).cuda()
+    worst = []
+
+    def probe(k, scene, offs, g_oracle):
+        view.set_offsets(*offs)
+        leaves = _leaves(scene)
+        img = autograd.rasterize(view, *leaves, sh_degree=scene.sh_degree)
+        autograd.l1_loss(view, img, tg).backward()
+        want = dict(means=g_oracle["means"].T, scales=g_oracle["scales"].T,
+                    quats=g_oracle["quats"].T, opacities=g_oracle["opacities"],
+                    sh=g_oracle["sh"].permute(1, 2, 0))
+        for name, t in zip(PARAMS, leaves):
+            got = t.grad.cpu().to(F64)
+            rel = float(torch.linalg.norm(got - want[name]) / torch.linalg.norm(want[name]))
+            worst.append(rel)
+            assert rel <= 1e-3, (k, name, rel)
+
+    ol = _fit_oracle(sc, cam, target, iters, T, probe=probe)
     rel = [abs(a - b) / b for a, b in zip(gl, ol)]
     say(f"[gpu] fit: checker loss {ol[0]:.6f} -> {ol[-1]:.6f}; max rel diff {max(rel):.2e} "
-        f"(first 50: {max(rel[:50]):.2e})")
+        f"(first 50: {max(rel[:50]):.2e}); teacher-forced gradients: worst {max(worst):.2e} "
+        f"over {len(worst)} checks")
     assert gl[-1] < 0.8 * gl[0] and ol[-1] < 0.8 * ol[0]
     assert max(rel[:50]) <= 1e-3
-    assert max(rel) <= 1e-2
+    assert max(rel) <= 3e-2
     assert not any(math.isnan(x) for x in gl)
 
 
