@@ -4,11 +4,17 @@ cycling through the 4 phases), against the plain full-resolution path on the
 same view.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-plain]
+                    [--no-batched | --only-batched]
 
 One step = preprocess -> pairs + sort + ranges -> dilated blend -> L1 loss
 gradient against the full-resolution target -> blend backward -> preprocess
 backward with densification statistics, on inputs already resident in HBM.
 Prints ONE JSON line (diagnostics go to stderr).
+
+Unless --no-batched, the JSON line also carries "batched": the 12-view batch
+(2M Gaussians, views of mixed resolution and stride) stepped by the batched
+calls and replayed from one captured graph, against the same views through
+the single-view calls and against the plain full-resolution batch.
 
 Gaussian-pixel evaluations: forward = list entries examined per rendered
 pixel until its walk ends (stop entry included); backward = entries up to the
@@ -56,8 +62,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device copy (reference kernel for HBM counters)")
-    ap.add_argument("--batched", action="store_true",
-                    help="also run the 12-view batch (2M Gaussians, mixed resolutions and strides)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 12-view batch (2M Gaussians, mixed resolutions and strides)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the 12-view batch (for profiling); prints its own JSON")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--lds-batch", type=int, default=0)
     return ap.parse_args()
@@ -354,6 +362,9 @@ def main():
         del a, b
         log("# calibration copy: 1 GiB read + 1 GiB written")
 
+    if args.only_batched:
+        print(json.dumps(run_batched(args, api, torch, np)), flush=True)
+        return
     sc, cam, tgt = scenes.workload(args.workload, n=args.n)
     w = scenes.WORKLOADS[args.workload]
     stride = w.get("stride", 1)
@@ -421,8 +432,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dil, args.cpu_seconds)
-    if args.batched:
-        del dil
+    if not args.no_batched:
+        del dil, dev, target
         torch.cuda.empty_cache()
         out["batched"] = run_batched(args, api, torch, np)
     print(json.dumps(out), flush=True)

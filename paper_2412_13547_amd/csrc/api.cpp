@@ -175,10 +175,6 @@ tgs_status use_device(tgs_context* ctx) {
     return TGS_OK;
 }
 
-// Buffer holding the dispatch order after launch_tile_order (the number of
-// radix passes over 32-bit keys is fixed, so the index is too).
-int tile_order_buffer() { return tgs::radix_sort_passes(32) % 2; }
-
 // The table entry of one view for the preprocess kernels.
 tgs::PrepView prep_view(const tgs_camera& cam, const tgs::Grid& grid, uint8_t* ws,
                         const tgs::Layout& L) {
@@ -205,7 +201,6 @@ tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const
     v.ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
     v.vals = reinterpret_cast<const uint32_t*>(ws + L.pair_vals);
     v.pair_count = reinterpret_cast<const uint32_t*>(ws + L.row_start) + grid.gy;
-    v.order = reinterpret_cast<const uint32_t*>(ws + L.tile_val[tile_order_buffer()]);
     v.g2d = reinterpret_cast<float*>(ws + L.grad2d);
     return v;
 }
@@ -253,9 +248,6 @@ tgs_status enqueue_emit(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid
                         hipStream_t strm) {
     TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, capacity, strm));
     TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, capacity, strm));
-    int res = 0;
-    TGS_HIP(tgs::launch_tile_order(ws, L, grid, &res, strm));
-    if (res != tile_order_buffer()) return fail(TGS_ERR_HIP, "tile order in an unexpected buffer");
     return TGS_OK;
 }
 
@@ -301,14 +293,10 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.row_vals = take(cap * 4);
     L.pair_vals = take(cap * 4);
     L.col_hist = take(hist * 4);
-    const uint64_t nt = uint64_t(grid.num_tiles());
-    L.ranges = take(nt * 8);
-    for (int b = 0; b < 2; ++b) L.tile_key[b] = take(nt * 4);
-    for (int b = 0; b < 2; ++b) L.tile_val[b] = take(nt * 4);
+    L.ranges = take(uint64_t(grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
-    const uint64_t sorted = un > nt ? un : nt;       // the depth sort and the tile order
-    L.sort_counts = take(radix_counts_elems(sorted) * 4);
-    uint64_t most = radix_counts_elems(sorted);
+    L.sort_counts = take(radix_counts_elems(un) * 4);
+    uint64_t most = radix_counts_elems(un);
     if (rowtot > most) most = rowtot;
     if (hist > most) most = hist;
     L.scan_partials = take(scan_partials_elems(most) * 8);

@@ -32,9 +32,11 @@
 namespace tgs {
 namespace {
 
-constexpr int kScatterThreads = 512;
+constexpr int kScatterThreads = 256;
 constexpr int kScatterWaves = kScatterThreads / 64;
 constexpr int kScatterRounds = kSlice / kScatterThreads;   // pairs per thread
+constexpr int kScatterCols = kMaxCols / kScatterThreads;   // columns per thread in the scan
+constexpr uint32_t kDirectCols = 8;   // widest row span written lane by lane
 
 __device__ __forceinline__ int wave_min(int x) {
     for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
@@ -147,6 +149,21 @@ emit_rows_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ or
             const uint32_t base = uint32_t(__builtin_amdgcn_readlane(int(my_base), ty - r0));
             const uint32_t next = uint32_t(__builtin_amdgcn_readlane(int(my_next), ty - r0));
             const uint32_t len = min(tot, next - base);    // never past this segment
+            const uint32_t mine = (ty >= r.ylo && ty < r.yhi) ? w : 0u;
+            const uint32_t wmax = uint32_t(wave_max(int(mine)));
+            if (wmax <= kDirectCols) {
+                // every lane writes its own (at most kDirectCols) pairs
+                for (uint32_t c = 0; c < wmax; ++c) {
+                    const uint32_t e = ex + c;
+                    if (c < mine && e < len) {
+                        cols[uint64_t(base) + e] = uint16_t(r.xlo + int(c));
+                        vals[uint64_t(base) + e] = id;
+                    }
+                }
+                continue;
+            }
+            // wide splats: the wavefront writes 64 consecutive pairs per round,
+            // each lane finding its pair's Gaussian by binary search
             s_pref[wv][lane] = ex;
             for (uint32_t e = lane; e < len; e += 64) {
                 int lo = 0, hi = 64;                   // largest lo with s_pref[lo] <= e
@@ -325,10 +342,14 @@ col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict
     }
     __syncthreads();
     // per column: total over waves (wave counts become wave prefixes), then
-    // the columns' local starts by a block scan (two columns per thread)
-    uint32_t tot2[2] = {0u, 0u};
-    for (int j = 0; j < 2; ++j) {
-        const int c = 2 * tid + j;
+    // the columns' local starts by a block scan (kScatterCols columns per thread)
+    constexpr int CPT = kScatterCols;
+    uint32_t tot[CPT];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int c = CPT * tid + j;
+        tot[j] = 0;
         if (c < gx) {
             uint32_t t = 0;
             for (int w = 0; w < W; ++w) {
@@ -336,17 +357,20 @@ col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict
                 s_wcnt[w * gx + c] = t;
                 t += v;
             }
-            tot2[j] = t;
+            tot[j] = t;
         }
+        mine += tot[j];
     }
     uint32_t all;
-    const uint32_t ex = block_exclusive_sum<kScatterThreads>(tot2[0] + tot2[1], s_w, all);
-    for (int j = 0; j < 2; ++j) {
-        const int c = 2 * tid + j;
+    uint32_t ex = block_exclusive_sum<kScatterThreads>(mine, s_w, all);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int c = CPT * tid + j;
         if (c < gx) {
-            s_start[c] = ex + (j ? tot2[0] : 0u);
+            s_start[c] = ex;
             s_gbase[c] = hist[uint64_t(blockIdx.x) * gx + c];
         }
+        ex += tot[j];
     }
     __syncthreads();
 #pragma unroll
@@ -364,17 +388,6 @@ col_scatter_kernel(const uint16_t* __restrict__ cols, const uint32_t* __restrict
         const uint32_t c = s_col[i];
         out[s_gbase[c] + (i - s_start[c])] = s_val[i];
     }
-}
-
-// Dispatch key of every tile: decreasing list length, so the longest lists
-// start first and the short ones fill in behind them.
-__global__ void __launch_bounds__(256)
-tile_cost_kernel(const uint32_t* __restrict__ ranges, uint32_t num_tiles,
-                 uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= num_tiles) return;
-    keys[t] = ~(ranges[2 * t + 1] - ranges[2 * t]);
-    vals[t] = t;
 }
 
 size_t scatter_lds_bytes(int gx) {
@@ -419,20 +432,6 @@ hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order,
         reinterpret_cast<const uint32_t*>(ws + L.rowtot), nchunks, capacity,
         reinterpret_cast<uint16_t*>(ws + L.row_cols), reinterpret_cast<uint32_t*>(ws + L.row_vals));
     return hipGetLastError();
-}
-
-hipError_t launch_tile_order(uint8_t* ws, const Layout& L, const Grid& grid, int* result,
-                             hipStream_t s) {
-    const uint32_t nt = uint32_t(grid.num_tiles());
-    auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
-    uint32_t* keys[2] = {u32(L.tile_key[0]), u32(L.tile_key[1])};
-    uint32_t* vals[2] = {u32(L.tile_val[0]), u32(L.tile_val[1])};
-    tile_cost_kernel<<<dim3((nt + 255) / 256), dim3(256), 0, s>>>(u32(L.ranges), nt, keys[0],
-                                                                  vals[0]);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return radix_sort(keys, vals, nt, 32, u32(L.sort_counts),
-                      reinterpret_cast<uint64_t*>(ws + L.scan_partials), result, s);
 }
 
 hipError_t prepare_binning_kernels() {

@@ -26,7 +26,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 // binning: pairs per column-sort slice, and the widest tile grid supported
-constexpr int kSlice = 8192;
+constexpr int kSlice = 4096;
 constexpr int kMaxCols = 1024;
 
 enum RecordFlags : uint32_t {
@@ -55,8 +55,6 @@ struct Layout {
     uint64_t pair_vals;        // uint32[capacity], Gaussian of each pair, final order
     uint64_t col_hist;         // uint32[gx * max_slices], column histograms, then scanned
     uint64_t ranges;           // uint32[num_tiles][2]
-    uint64_t tile_key[2];      // uint32[num_tiles], sort keys of the dispatch order
-    uint64_t tile_val[2];      // uint32[num_tiles], tiles by decreasing list length
     uint64_t grad2d;           // float[n][9]
     uint64_t sort_counts;      // uint32, radix digit counts
     uint64_t scan_partials;    // uint64, scan block sums
@@ -135,11 +133,6 @@ hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint6
 // One-time kernel attributes (the column scatter of the widest grid needs
 // more than 64 KiB of LDS).
 hipError_t prepare_binning_kernels();
-// Tiles in decreasing order of list length (ties by tile index), the order in
-// which the rasterizers dispatch them; *result receives the buffer index of
-// tile_val holding it.
-hipError_t launch_tile_order(uint8_t* ws, const Layout& L, const Grid& grid, int* result,
-                             hipStream_t s);
 
 // One view of a raster launch.
 struct RasterView {
@@ -150,7 +143,6 @@ struct RasterView {
     const uint32_t* ranges;   // [num_tiles][2]
     const uint32_t* vals;     // pair values in (tile, depth, index) order
     const uint32_t* pair_count;   // device: pairs binned; above capacity = overflow
-    const uint32_t* order;    // dispatch order of the tiles (NULL: row-major)
     float* image;             // forward out / backward in
     float* t_final;           // forward, optional
     uint32_t* last_contrib;   // forward, optional

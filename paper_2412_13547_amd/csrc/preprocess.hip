@@ -264,7 +264,8 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
 // Parameter gradients of Gaussian i in one view, written to (dm, ds, dq);
 // gr = dL/d(u, v, A, B, C, o, r, g, b).  The SH coefficients are read from
 // sh_g ([K*3][n]); their gradients are added to dsh_acc (ACC) or written to
-// dsh_g (single view).
+// dsh_g (single view, zero where !vis: every lane stores, so each store of
+// the wavefront covers whole cache lines).
 template <int DEG, bool ACC>
 __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const float m[3],
                                                     const float s[3], const float q[4],
@@ -272,10 +273,11 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
                                                     int64_t i, uint32_t flags,
                                                     const float gr[kGrad2d], float dm_out[3],
                                                     float ds_out[3], float dq_out[4],
-                                                    float* dsh_acc) {
+                                                    float* dsh_acc, bool vis = true) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
     Proj p;
+    if constexpr (!ACC) p = Proj{};      // lanes the view does not see compute too (and discard)
     project(cam, m, s, q, p);
     float dm[3] = {0.0f, 0.0f, 0.0f};
 
@@ -294,7 +296,7 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
             for (int c = 0; c < 3; ++c) {
                 const float d = Y[k] * graw[c];
                 if constexpr (ACC) dsh_acc[k * 3 + c] += d;
-                else dsh_g[(k * 3 + c) * n + i] = d;
+                else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
                 acc += sh_g[(k * 3 + c) * n + i] * graw[c];
             }
             w[k] = acc;
@@ -390,7 +392,10 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
     for (int k = 0; k < 3; ++k) dm_out[k] = dm[k];
 }
 
-// One thread per Gaussian, one view.
+// One thread per Gaussian, one view.  Gaussians the view does not see get
+// zeros; they run the same arithmetic (on whatever their parameters give)
+// and select zero at the stores, so every store instruction covers the
+// whole wavefront.
 template <int DEG>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     tgs_gaussians g, PrepViews views, tgs_grads out, float* __restrict__ pos_stat,
@@ -403,30 +408,20 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     const PrepView& pv = views.v[0];
     const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
     const uint32_t flags = __float_as_uint(r2.w);
-    if (!(pv.touched[i] > 0 && !(flags & kCulled))) {
-        for (int k = 0; k < 3; ++k) out.means[k * n + i] = 0.0f;
-        for (int k = 0; k < 3; ++k) out.scales[k * n + i] = 0.0f;
-        for (int k = 0; k < 4; ++k) out.quats[k * n + i] = 0.0f;
-        out.opacities[i] = 0.0f;
-        for (int k = 0; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
-        if (pos_stat) pos_stat[i] = 0.0f;
-        if (col_stat) col_stat[i] = 0.0f;
-        if (visible) visible[i] = 0;
-        return;
-    }
+    const bool vis = pv.touched[i] > 0 && !(flags & kCulled);
     float gr[kGrad2d];
-    for (int k = 0; k < kGrad2d; ++k) gr[k] = pv.g2d[i * kGrad2d + k];
+    for (int k = 0; k < kGrad2d; ++k) gr[k] = vis ? pv.g2d[i * kGrad2d + k] : 0.0f;
     float m[3], s[3], q[4];
     for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
     for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
     for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
     float dm[3], ds[3], dq[4];
     preprocess_grad_one<DEG, false>(pv.cam, m, s, q, g.sh, out.sh, n, i, flags, gr, dm, ds, dq,
-                                    nullptr);
+                                    nullptr, vis);
     for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
-    for (int k = 0; k < 4; ++k) out.quats[k * n + i] = dq[k];
-    for (int k = 0; k < 3; ++k) out.scales[k * n + i] = ds[k];
-    for (int k = 0; k < 3; ++k) out.means[k * n + i] = dm[k];
+    for (int k = 0; k < 4; ++k) out.quats[k * n + i] = vis ? dq[k] : 0.0f;
+    for (int k = 0; k < 3; ++k) out.scales[k * n + i] = vis ? ds[k] : 0.0f;
+    for (int k = 0; k < 3; ++k) out.means[k * n + i] = vis ? dm[k] : 0.0f;
     out.opacities[i] = gr[5];
     if (pos_stat) {
         const float px = gr[0] * (0.5f * float(pv.cam.width));
@@ -434,7 +429,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
         pos_stat[i] = sqrtf(px * px + py * py);
     }
     if (col_stat) col_stat[i] = sqrtf(gr[6] * gr[6] + gr[7] * gr[7] + gr[8] * gr[8]);
-    if (visible) visible[i] = 1;
+    if (visible) visible[i] = vis ? 1 : 0;
 }
 
 // One thread per Gaussian, several views: the gradients of every view are

@@ -75,15 +75,12 @@ struct Shape {
 };
 
 // Which view and tile workgroup b works on: the views' workgroups are laid
-// out one view after the other, and within a view the tiles are dispatched
-// in the view's order (longest lists first).
+// out one view after the other, tiles row-major within a view.
 __device__ __forceinline__ bool locate(const RasterViews& vt, uint32_t b, int& v, int64_t& tile) {
     if (b >= vt.first_block[vt.count]) return false;
     v = 0;
     while (b >= vt.first_block[v + 1]) ++v;
-    const uint32_t k = b - vt.first_block[v];
-    const uint32_t* order = vt.v[v].order;
-    tile = int64_t(order ? uint32_t(__builtin_amdgcn_readfirstlane(int(order[k]))) : k);
+    tile = int64_t(b - vt.first_block[v]);
     return true;
 }
 
