@@ -231,22 +231,24 @@ tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& gr
     uint32_t* dvals[2] = {u32(L.depth_val[0]), u32(L.depth_val[1])};
     TGS_HIP(tgs::radix_sort(dkeys, dvals, uint64_t(n), 32, u32(L.sort_counts), partials, dres, strm));
     *order = dvals[*dres];
-    // pairs per (tile row, chunk of the depth order); scan -> row buckets
-    const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_chunks(n);
-    TGS_HIP(tgs::launch_row_counts(ws, L, *order, n, grid, strm));
-    TGS_HIP(tgs::exclusive_scan_u32(u32(L.rowtot), u32(L.rowtot), nrow, partials, true, strm));
+    // entries and pairs per (tile row, block of the depth order); scans ->
+    // every block's place in every row
+    const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_blocks(n);
+    TGS_HIP(tgs::launch_counts(ws, L, *order, n, grid, strm));
+    TGS_HIP(tgs::exclusive_scan_u32(u32(L.ecnt), u32(L.ecnt), nrow, partials, true, strm));
+    TGS_HIP(tgs::exclusive_scan_u32(u32(L.pcnt), u32(L.pcnt), nrow, partials, true, strm));
     TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, strm));
     return TGS_OK;
 }
 
-// Emission into row buckets, then a stable counting sort by column per row,
-// which also yields the per-tile ranges.  `slices` bounds the column-sort
-// slices from above; the kernels skip all work when the device pair count
-// exceeds the capacity.
+// Entries into row buckets, then a stable counting sort by column per slice
+// of every row, which writes the pairs and the per-tile ranges.  `slices`
+// bounds the column-sort slices from above; the kernels skip all work when
+// the device pair count exceeds the capacity.
 tgs_status enqueue_emit(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
                         const uint32_t* order, uint64_t slices, uint32_t capacity,
                         hipStream_t strm) {
-    TGS_HIP(tgs::launch_emit_rows(ws, L, order, n, grid, capacity, strm));
+    TGS_HIP(tgs::launch_entries(ws, L, order, n, grid, capacity, strm));
     TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, capacity, strm));
     return TGS_OK;
 }
@@ -280,24 +282,30 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     };
     const uint64_t un = uint64_t(n);
     const uint64_t gy = uint64_t(grid.gy), gx = uint64_t(grid.gx);
-    const uint64_t rowtot = gy * bin_chunks(n) + 1;
-    const uint64_t hist = gx * bin_max_slices(cap, grid.gy);
+    const uint64_t table = gy * bin_blocks(n) + 1;
+    const uint64_t slices = bin_max_slices(cap, grid.gy);
+    const uint64_t hist = gx * slices;
     L.records = take(un * kRecordBytes);
     L.tiles_touched = take(un * 4);
     for (int b = 0; b < 2; ++b) L.depth_key[b] = take(un * 4);
     for (int b = 0; b < 2; ++b) L.depth_val[b] = take(un * 4);
-    L.rowtot = take(rowtot * 4);
+    L.ecnt = take(table * 4);
+    L.pcnt = take(table * 4);
     L.row_start = take((gy + 1) * 4);
+    L.erow = take((gy + 1) * 4);
     L.first_slice = take((gy + 1) * 4);
-    L.row_cols = take(cap * 2);
-    L.row_vals = take(cap * 4);
+    L.slice_entry = take(slices * 4);
+    L.slice_row = take(slices * 4);
+    L.ent_id = take(cap * 4);
+    L.ent_pp = take(cap * 4);
+    L.ent_x = take(cap * 4);
     L.pair_vals = take(cap * 4);
     L.col_hist = take(hist * 4);
     L.ranges = take(uint64_t(grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
     uint64_t most = radix_counts_elems(un);
-    if (rowtot > most) most = rowtot;
+    if (table > most) most = table;
     if (hist > most) most = hist;
     L.scan_partials = take(scan_partials_elems(most) * 8);
     L.total = o;

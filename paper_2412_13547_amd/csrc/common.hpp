@@ -47,11 +47,16 @@ Grid make_grid(const tgs_camera& cam, const tgs_dilation& dil, int tile);
 struct Layout {
     uint64_t records, tiles_touched;
     uint64_t depth_key[2], depth_val[2];
-    uint64_t rowtot;           // uint32[gy * chunks + 1], pairs per (row, chunk), then scanned
-    uint64_t row_start;        // uint32[gy + 1]
+    uint64_t ecnt;             // uint32[gy * blocks + 1], entries per (row, block), then scanned
+    uint64_t pcnt;             // uint32[gy * blocks + 1], pairs per (row, block), then scanned
+    uint64_t row_start;        // uint32[gy + 1], first pair of every row
+    uint64_t erow;             // uint32[gy + 1], first entry of every row
     uint64_t first_slice;      // uint32[gy + 1]
-    uint64_t row_cols;         // uint16[capacity], column of each pair, row-bucketed
-    uint64_t row_vals;         // uint32[capacity], Gaussian of each pair, row-bucketed
+    uint64_t slice_entry;      // uint32[max_slices], entry holding a slice's first pair
+    uint64_t slice_row;        // uint32[max_slices], tile row of each slice
+    uint64_t ent_id;           // uint32[capacity], Gaussian of each entry (row-bucketed)
+    uint64_t ent_pp;           // uint32[capacity], first pair of each entry
+    uint64_t ent_x;            // uint32[capacity], xlo | xhi << 16 of each entry
     uint64_t pair_vals;        // uint32[capacity], Gaussian of each pair, final order
     uint64_t col_hist;         // uint32[gx * max_slices], column histograms, then scanned
     uint64_t ranges;           // uint32[num_tiles][2]
@@ -115,17 +120,17 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
 uint64_t scan_partials_elems(uint64_t count);
 
 // binning (binning.hip).  The pair count lives on the device (row_start[gy]);
-// the emission and the column sort do nothing when it exceeds `capacity`
-// (and the column sort then writes empty ranges), so the stage can be
-// enqueued without reading the count back.
-uint32_t bin_chunks(int64_t n);
+// the entry emission and the column sort do nothing when it exceeds
+// `capacity` (and the column sort then writes empty ranges), so the stage
+// can be enqueued without reading the count back.
+uint32_t bin_blocks(int64_t n);
 uint64_t bin_max_slices(uint64_t pairs, int gy);
-hipError_t launch_row_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                             const Grid& grid, hipStream_t s);
+hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
+                         const Grid& grid, hipStream_t s);
 hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid& grid,
                             hipStream_t s);
-hipError_t launch_emit_rows(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                            const Grid& grid, uint32_t capacity, hipStream_t s);
+hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
+                          const Grid& grid, uint32_t capacity, hipStream_t s);
 // Stable counting sort of every row bucket by column, and the tile ranges;
 // `slices` bounds the number of column-sort slices from above.
 hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
