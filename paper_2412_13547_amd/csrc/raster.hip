@@ -265,6 +265,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
     __shared__ uint32_t s_id[BATCH];
+    // multi-wavefront tiles add their wavefronts' sums in LDS and flush each
+    // batch with one set of global atomics per entry
+    constexpr bool kBlockSum = S::NT > 64;
+    __shared__ float s_g[kBlockSum ? BATCH * kGrad2d : 1];
     int v;
     int64_t tile;
     if (!locate(vt, blockIdx.x, v, tile)) return;                // block-uniform
@@ -320,6 +324,8 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, 0.0f);
             s_id[q] = id;
         }
+        if constexpr (kBlockSum)
+            for (int q = tid; q < cnt * kGrad2d; q += S::NT) s_g[q] = 0.0f;
         __syncthreads();
         auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
@@ -370,8 +376,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             }
             int comp;
             const float sum = wave_sum9(gv, comp);
-            if (comp >= 0 && sum != 0.0f)
-                atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], sum * scale);
+            if (comp >= 0 && sum != 0.0f) {
+                if constexpr (kBlockSum) atomicAdd(&s_g[e * kGrad2d + comp], sum * scale);
+                else atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], sum * scale);
+            }
         };
         // the wavefront leaves once all its pixels have stopped, checked every
         // fourth entry (entries after a stop change nothing)
@@ -386,6 +394,14 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         for (; e < cnt; ++e) {
             if (__ballot(alive) == 0) break;
             entry(e);
+        }
+        if constexpr (kBlockSum) {
+            __syncthreads();
+            for (int q = tid; q < cnt * kGrad2d; q += S::NT) {
+                const float g = s_g[q];
+                if (g != 0.0f)
+                    atomicAdd(&rv.g2d[uint64_t(s_id[q / kGrad2d]) * kGrad2d + q % kGrad2d], g);
+            }
         }
     }
 }
