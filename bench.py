@@ -11,6 +11,10 @@ gradient against the full-resolution target -> blend backward -> preprocess
 backward with densification statistics, on inputs already resident in HBM.
 Prints ONE JSON line (diagnostics go to stderr).
 
+Unless --no-autograd, it carries "autograd": a training step through the
+torch.autograd functions (1M Gaussians, 2560x1440, stride 2, fused Adam)
+against the same step at stride 1.
+
 Unless --no-batched, the JSON line also carries "batched": the 12-view batch
 (2M Gaussians, views of mixed resolution and stride) stepped by the batched
 calls and replayed from one captured graph, against the same views through
@@ -67,6 +71,10 @@ def parse():
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 12-view batch (for profiling); prints its own JSON")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-autograd", action="store_true",
+                    help="skip the autograd training step (1M Gaussians, 1440p, stride 2)")
+    ap.add_argument("--only-autograd", action="store_true",
+                    help="run only the autograd training step; prints its own JSON")
     ap.add_argument("--lds-batch", type=int, default=0)
     return ap.parse_args()
 
@@ -339,6 +347,55 @@ def run_batched(args, api, torch, np):
     return res
 
 
+def run_autograd(args, api, torch, np, steps=20):
+    """The training step through the autograd functions: parameters (means,
+    log-scales, raw quaternions, opacity logits, SH) -> activations -> dilated
+    image -> L1 loss -> backward -> fused Adam, phases cycling; against the
+    same step at stride 1."""
+    from paper_2412_13547_amd import autograd, scenes
+    w = scenes.WORKLOADS[4]
+    sc, cam, tgt = scenes.workload(4, n=args.n)
+    target = torch.as_tensor(tgt).cuda()
+    del tgt
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).cuda().requires_grad_(True)
+    P = [f(sc.means), f(np.log(sc.scales)), f(sc.quats),
+         f(np.log(sc.opacities / (1.0 - sc.opacities))), f(sc.sh)]
+    deg, n = sc.sh_degree, sc.n
+    del sc
+    ctx = api.Context(0)
+    res = {"workload": w["name"], "gaussians": n, "width": cam.width, "height": cam.height}
+    for stride in (w["stride"], 1):
+        view = api.View(ctx, n, cam, stride, 0, 0, 16)
+        adam = api.Adam(ctx, [p.detach() for p in P], [1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3])
+        stats = autograd.Stats(n)
+
+        def step(k):
+            view.set_offsets(*scenes.phase_offsets(k, stride))
+            img = autograd.rasterize(view, P[0], torch.exp(P[1]), P[2], torch.sigmoid(P[3]),
+                                     P[4], sh_degree=deg, stats=stats)
+            loss = autograd.l1_loss(view, img, target)
+            grads = torch.autograd.grad(loss, P)
+            adam.step([g.contiguous() for g in grads])
+        for k in range(3):
+            step(k)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(ev):
+            a.record()
+            step(3 + k)
+            b.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        key = "dilated" if stride > 1 else "plain"
+        res[key] = {"stride": stride, "ms_per_step": ms}
+        log(f"# autograd {key}: {ms:.3f} ms/step")
+        del view, adam, stats
+        torch.cuda.empty_cache()
+    res["speedup_vs_plain"] = res["plain"]["ms_per_step"] / res["dilated"]["ms_per_step"]
+    return res
+
+
 def _alu(ops, t_ms):
     a = ops / (t_ms / 1000.0) / 1e12
     return {"bound": "alu", "achieved": a, "peak": PEAK_VALU / 1e12, "unit": "T lane-ops/s",
@@ -362,6 +419,9 @@ def main():
         del a, b
         log("# calibration copy: 1 GiB read + 1 GiB written")
 
+    if getattr(args, "only_autograd", False):
+        print(json.dumps(run_autograd(args, api, torch, np)), flush=True)
+        return
     if args.only_batched:
         print(json.dumps(run_batched(args, api, torch, np)), flush=True)
         return
@@ -436,6 +496,9 @@ def main():
         del dil, dev, target
         torch.cuda.empty_cache()
         out["batched"] = run_batched(args, api, torch, np)
+    if not args.no_autograd:
+        torch.cuda.empty_cache()
+        out["autograd"] = run_autograd(args, api, torch, np)
     print(json.dumps(out), flush=True)
 
 

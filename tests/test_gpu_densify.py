@@ -34,3 +34,16 @@ def test_selection_matches_checker(n, color, budget):
     assert sel.cpu().numpy().tolist() == want.tolist()
     if n == 5000 and budget == 37:
         say(f"[gpu] densify n={n} color={color}: {wk} selected, bit-exact")
+
+
+def test_densifier_respects_the_budget_remainder():
+    from paper_2412_13547_amd.densify import BudgetSchedule, Densifier
+    pos, col, cnt = _stats(5000, 7)
+    sched = BudgetSchedule(n_init=5000, n_max=5100, start=0, end=100)
+    d = Densifier(ctx(), sched, tau_pos=2.5, seed=1)
+    g = lambda a: torch.as_tensor(a).cuda()
+    room = sched.budget(50) - 5000
+    mask, k, color = d.select(50, 5000, g(pos), g(col), g(cnt))
+    want, wk = oden.select(pos, col, cnt, 2.5, 0.025, color, room)
+    assert k == wk <= room
+    assert mask.cpu().numpy().tolist() == want.tolist()
