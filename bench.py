@@ -23,7 +23,7 @@ the single-view calls and against the plain full-resolution batch.
 Gaussian-pixel evaluations: forward = list entries examined per rendered
 pixel until its walk ends (stop entry included); backward = entries up to the
 pixel's last blended one.  Both are counted by the kernels themselves
-(per-pixel outputs checked against the CPU checker in the tests).
+(per-pixel outputs checked against the CPU oracle in the tests).
 """
 from __future__ import annotations
 
@@ -166,7 +166,7 @@ class Runner:
 
 
 def cpu_baseline(runner, seconds):
-    """The CPU checker timed on a bounded sample of tiles of the same view:
+    """The CPU oracle timed on a bounded sample of tiles of the same view:
     forward + backward of randomly drawn tiles until ~`seconds` elapse."""
     import numpy as np
     import torch
@@ -202,7 +202,7 @@ def cpu_baseline(runner, seconds):
     return {"value": evals / el, "unit": "Gaussian-pixel evals/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"{tiles} random non-empty tiles of phase (0,0): float64 blend forward + "
-                      f"backward of the checker, {el:.1f} s; evals counted as in the metric"}
+                      f"backward of the oracle, {el:.1f} s; evals counted as in the metric"}
 
 
 def _time_events(torch, fn, steps):
@@ -396,6 +396,24 @@ def run_autograd(args, api, torch, np, steps=20):
     return res
 
 
+def measured_traffic(kernel_source: str, record: str):
+    """HBM bytes per launch (fetch + write) from a committed counter record,
+    or None when the kernel's source has changed since it was taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(os.path.join(ROOT, record)):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()
+        if fields.get("source_sha256") != sha:
+            return None
+        return float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _alu(ops, t_ms):
     a = ops / (t_ms / 1000.0) / 1e12
     return {"bound": "alu", "achieved": a, "peak": PEAK_VALU / 1e12, "unit": "T lane-ops/s",
@@ -461,10 +479,14 @@ def main():
     n = sc.n
     roof_bwd = dict(kernel="raster_bwd_kernel<16,1,256>",
                     **alu(OPS_EXAMINE * bwd_evals + OPS_BLEND_BWD * blended, stage["raster_bwd"]),
-                    traffic=None)
+                    traffic=measured_traffic("paper_2412_13547_amd/csrc/raster.hip",
+                                             "profiles/raster_bwd_dilated4k_traffic.txt"))
     roof_fwd = dict(kernel="raster_fwd_kernel<16,1,256,false>",
                     **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_FWD * blended, stage["raster_fwd"]))
-    sort_bytes = 18.0 * pairs + 200.0 * n
+    # the least the stage must move: the pair list (4 B per pair) and, per
+    # Gaussian, its rectangle inputs (u, v, radius: 12 B) and depth key and
+    # index written and read by the depth sort (16 B)
+    sort_bytes = 4.0 * pairs + 28.0 * n
     roof_sort = {"stage": "bin_sort", "bound": "hbm",
                  "achieved": sort_bytes / (stage["bin_sort"] / 1000.0) / 1e9,
                  "peak": PEAK_HBM / 1e9, "unit": "GB/s"}

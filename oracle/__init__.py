@@ -1,4 +1,4 @@
-"""CPU FP64 checker for the dilated differentiable Gaussian-splat rasterizer.
+"""CPU FP64 oracle for the dilated differentiable Gaussian-splat rasterizer.
 
 TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke entry point and the
 benchmark's CPU-baseline leg may import this package.  The HIP library never

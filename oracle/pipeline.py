@@ -1,4 +1,4 @@
-"""The checker's stages chained end to end: preprocess -> bin -> raster -> L1 -> backward.
+"""The oracle's stages chained end to end: preprocess -> bin -> raster -> L1 -> backward.
 
 One iteration of the paper's dilated fitting loop for one view and one offset
 (Sec. 4.1, last paragraph: stride d, one offset per iteration), minus the

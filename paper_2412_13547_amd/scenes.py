@@ -1,7 +1,7 @@
 """Seeded synthetic inputs: Gaussian scenes, pinhole cameras and target images.
 
 This module only draws random numbers and lays them out; it holds none of the
-rasterizer's arithmetic.  Both the HIP path and the CPU checker consume what it
+rasterizer's arithmetic.  Both the HIP path and the CPU oracle consume what it
 produces, so it imports nothing from either.
 
 Layout (structure of arrays, float32, the order the library expects):
@@ -227,7 +227,7 @@ def small_scene(seed: int, n: int, width: int, height: int, sh_degree: int = 3,
                 scale_mean: float = -2.3, depth=(2.0, 5.0), spread: float = 0.6) -> tuple[Scene, Camera]:
     """A small scene in front of a ring camera, sized so every Gaussian covers a few tiles.
 
-    Used by the parity tests at sizes the CPU checker finishes in seconds.
+    Used by the parity tests at sizes the CPU oracle finishes in seconds.
     """
     rng = np.random.default_rng(seed)
     ang = float(rng.uniform(0.0, 2.0 * math.pi))

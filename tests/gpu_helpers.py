@@ -1,5 +1,5 @@
 """Shared helpers of the GPU parity tests: run the HIP path through the C ABI
-and compare each stage with the CPU checker fed the HIP path's own upstream
+and compare each stage with the CPU oracle fed the HIP path's own upstream
 outputs (stage isolation)."""
 from __future__ import annotations
 
@@ -78,7 +78,7 @@ def run_gpu(scene, cam, stride=1, off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0),
 
 
 def records_to_oracle(rec32: torch.Tensor) -> dict:
-    """GPU float32 records -> the checker's float64 record dict (exact upcast)."""
+    """GPU float32 records -> the oracle's float64 record dict (exact upcast)."""
     r = rec32.to(F64)
     bits = rec32.view(torch.int32)
     flags = bits[:, 11]

@@ -1,7 +1,7 @@
 """torch.autograd layer: gradients through ``rasterize`` / ``l1_loss`` equal
 the direct C-ABI backward; recomputation and interleaved forwards give the
 same gradients; the batched function sums views; a 200-iteration fit follows
-the checker's own fit (float64, same optimiser) iteration by iteration."""
+the oracle's own fit (float64, same optimiser) iteration by iteration."""
 import math
 
 import numpy as np
@@ -152,12 +152,12 @@ def _fit_oracle(sc, cam, target, iters, T, probe=None, probe_every=20):
     return losses
 
 
-def test_200_iteration_fit_follows_the_checker():
+def test_200_iteration_fit_follows_the_oracle():
     """Fit a 64-Gaussian scene (64x64, stride 2, phases cycling) to a target
-    the checker renders from a perturbed copy.
+    the oracle renders from a perturbed copy.
 
     Teacher-forced: every 20 iterations the HIP path's gradients, taken at the
-    checker's own parameters of that iteration, match the checker's (1e-3 of
+    oracle's own parameters of that iteration, match the oracle's (1e-3 of
     the norm).  Free-running: the two loss curves agree to 1e-3 over the first
     50 iterations and stay within a 3e-2 band to 200; near convergence the
     sign-dominated L1 gradient amplifies float32 rounding of the trajectory
@@ -190,7 +190,7 @@ def test_200_iteration_fit_follows_the_checker():
 
     ol = _fit_oracle(sc, cam, target, iters, T, probe=probe)
     rel = [abs(a - b) / b for a, b in zip(gl, ol)]
-    say(f"[gpu] fit: checker loss {ol[0]:.6f} -> {ol[-1]:.6f}; max rel diff {max(rel):.2e} "
+    say(f"[gpu] fit: oracle loss {ol[0]:.6f} -> {ol[-1]:.6f}; max rel diff {max(rel):.2e} "
         f"(first 50: {max(rel[:50]):.2e}); teacher-forced gradients: worst {max(worst):.2e} "
         f"over {len(worst)} checks")
     assert gl[-1] < 0.8 * gl[0] and ol[-1] < 0.8 * ol[0]

@@ -1,4 +1,4 @@
-"""The batched multi-view path against the single-view path and the checker.
+"""The batched multi-view path against the single-view path and the oracle.
 
 A batch renders several views (each with its own resolution, stride and
 offsets) of one Gaussian set with one preprocess launch, per-view binning and
@@ -9,7 +9,7 @@ bit-exact against the single-view calls (the same kernels and arithmetic);
 summed gradients and statistics within the gradient tolerance of the sum of
 the single-view results (float atomics make neither side bit-reproducible);
 each view's blend backward and the summed preprocess backward against the
-checker (stage isolation); graph replays match the eager step.
+oracle (stage isolation); graph replays match the eager step.
 """
 import numpy as np
 import pytest
@@ -97,9 +97,9 @@ def test_batch_gradients_are_sums_of_single_views():
     assert int(r["vis"].max()) == len(singles)
 
 
-def test_batch_backward_against_checker():
+def test_batch_backward_against_oracle():
     """Each view's blend backward, then the summed preprocess backward, by the
-    checker from the HIP path's own upstream outputs."""
+    oracle from the HIP path's own upstream outputs."""
     r = _setup()
     sc = r["sc"]
     params = opre.params(sc, requires_grad=True)

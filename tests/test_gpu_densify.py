@@ -1,4 +1,4 @@
-"""Densification selection kernel against the checker: masks and counts
+"""Densification selection kernel against the oracle: masks and counts
 bit-exact, with and without the appearance branch and the budget, on
 statistics with many exact ties and values at the thresholds."""
 import numpy as np
@@ -24,7 +24,7 @@ def _stats(n, seed):
 @pytest.mark.parametrize("n", [0, 1, 777, 5000])
 @pytest.mark.parametrize("color", [False, True])
 @pytest.mark.parametrize("budget", [-1, 0, 37, 100000])
-def test_selection_matches_checker(n, color, budget):
+def test_selection_matches_oracle(n, color, budget):
     pos, col, cnt = _stats(n, 100 + n)
     want, wk = oden.select(pos, col, cnt, 2.5, 0.025, color, budget)
     g = lambda a: torch.as_tensor(a).cuda()

@@ -1,13 +1,13 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (T = 16, default launch knobs): 1080p with 500k Gaussians (plain) and
-4K with 3M Gaussians at stride 2.  The checker cannot redo these views whole,
+4K with 3M Gaussians at stride 2.  The oracle cannot redo these views whole,
 so it checks sampled outputs it can compute one by one, plus properties that
 hold at any size:
 
 * binning: for sampled tiles, the list is the brute-force set of Gaussians
   whose rectangle (from the HIP path's own u, v, radius) holds the tile,
   ordered by (depth bits, index) -- bit-exact; ranges partition the pairs;
-* blend forward: sampled tiles re-rendered by the checker;
+* blend forward: sampled tiles re-rendered by the oracle;
 * blend backward: the upstream gradient is confined to the sampled tiles, so
   the full launch runs but only checkable pixels contribute;
 * preprocess forward / backward: a sampled subset of Gaussians.

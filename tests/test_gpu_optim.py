@@ -1,4 +1,4 @@
-"""Fused Adam kernel against the checker's Adam: every step is taken by both
+"""Fused Adam kernel against the oracle's Adam: every step is taken by both
 from the kernel's previous float32 state (teacher forcing), on groups of
 ragged sizes, one of them misaligned for vector access; graph replays."""
 import numpy as np
@@ -25,9 +25,9 @@ def _groups(seed):
 
 
 def _check_step(adam, grads, t, prev):
-    """Moments against the checker from the previous state, with bounds of a
+    """Moments against the oracle from the previous state, with bounds of a
     few float32 roundings of the terms (b1 m and (1 - b1) g may cancel); the
-    parameter against the checker's update from the kernel's own new moments."""
+    parameter against the oracle's update from the kernel's own new moments."""
     f32 = lambda x: float(np.float32(x))     # the kernel receives float32 hyperparameters
     b1, b2, eps = f32(adam.betas[0]), f32(adam.betas[1]), f32(adam.eps)
     for k, g in enumerate(grads):
@@ -50,7 +50,7 @@ def _check_step(adam, grads, t, prev):
         assert bool(((p_new - want).abs() <= 12 * ulp * step.abs() + ulp * p0.abs() + 1e-38).all()), (t, k)
 
 
-def test_adam_matches_checker_step_by_step():
+def test_adam_matches_oracle_step_by_step():
     rng, params = _groups(3)
     lrs = [1e-3, 1e-2, 0.5, 1e-3, 0.0]
     adam = api.Adam(ctx(), [p.contiguous() for p in params], lrs, betas=(0.9, 0.999), eps=1e-15)

@@ -1,9 +1,9 @@
-"""GPU parity of every stage against the CPU checker (stage isolation: each
-checker stage is fed the HIP path's own upstream outputs, upcast to float64).
+"""GPU parity of every stage against the CPU oracle (stage isolation: each
+oracle stage is fed the HIP path's own upstream outputs, upcast to float64).
 
 Bars: sort keys, pair lists, tile ranges, tiles_touched bit-exact;
 last_contrib / n_eval exact except at pixels whose float decision lies within
-a hair of its threshold (the checker flags them); images within 1e-4 absolute;
+a hair of its threshold (the oracle flags them); images within 1e-4 absolute;
 gradients within 1e-3 relative (norm-wise and element-wise)."""
 import math
 
@@ -62,7 +62,7 @@ def _oracle_raster(g):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_preprocess_matches_checker(name):
+def test_preprocess_matches_oracle(name):
     sc, cam, _, g = _case(name)
     o = opre.preprocess(opre.params(sc), opre.camera(cam))
     rec = records_to_oracle(g["records"])
@@ -107,7 +107,7 @@ def test_binning_sort_ranges_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_raster_forward_matches_checker(name):
+def test_raster_forward_matches_oracle(name):
     sc, cam, _, g = _case(name)
     _, o = _oracle_raster(g)
     flag = o["flag"]
@@ -123,7 +123,7 @@ def test_raster_forward_matches_checker(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_raster_backward_matches_checker(name):
+def test_raster_backward_matches_oracle(name):
     sc, cam, _, g = _case(name)
     rec, o = _oracle_raster(g)
     dL = g["dL"].to(F64) * (~o["flag"]).to(F64)[None]
@@ -139,7 +139,7 @@ def test_raster_backward_matches_checker(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_preprocess_backward_matches_checker(name):
+def test_preprocess_backward_matches_oracle(name):
     sc, cam, _, g = _case(name)
     c = opre.camera(cam)
     o = opre.preprocess(opre.params(sc), c)
@@ -169,7 +169,7 @@ def test_preprocess_backward_matches_checker(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_statistics_match_checker(name):
+def test_statistics_match_oracle(name):
     sc, cam, _, g = _case(name)
     g2d = g["grad2d"].to(F64)
     vis = g["tiles_touched"] > 0
@@ -180,8 +180,8 @@ def test_statistics_match_checker(name):
 
 
 @pytest.mark.parametrize("name", ["tiny128-d1-T16", "sh3-160x120-d2-o10-T16", "sh2-101x77-d3-o21-T8-bg"])
-def test_end_to_end_against_pure_checker(name):
-    """No stage isolation: the whole HIP path against the float64 checker."""
+def test_end_to_end_against_pure_oracle(name):
+    """No stage isolation: the whole HIP path against the float64 oracle."""
     sc, cam, tgt, g = _case(name)
     make, d, ox, oy, T, bg = CASES[name]
     o = opipe.forward_backward(sc, cam, tgt, d, ox, oy, T, bg)

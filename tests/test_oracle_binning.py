@@ -1,4 +1,4 @@
-"""Pins of the checker's dilated binning (Sec. 4.1 Eq. 3-4) and (tile | depth)
+"""Pins of the oracle's dilated binning (Sec. 4.1 Eq. 3-4) and (tile | depth)
 sort: brute-force tile membership, interval-intersection tile rectangles,
 invariants of the sorted list and ranges, offset independence."""
 import math

@@ -1,4 +1,4 @@
-"""Pins of the checker's densification selection: thresholds at equality,
+"""Pins of the oracle's densification selection: thresholds at equality,
 the appearance branch, unseen Gaussians, the budget's ordering and ties."""
 import numpy as np
 

@@ -1,4 +1,4 @@
-"""Pins of the checker's gradients and densification statistics: central finite
+"""Pins of the oracle's gradients and densification statistics: central finite
 differences (h = 1e-6, float64) of its own forward at the raster stage, the
 preprocess stage and end to end, plus invariants (quaternion-scale invariance,
 linearity, zero upstream gradient) and the loss phase average of Sec. 4.1."""

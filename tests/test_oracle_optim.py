@@ -1,4 +1,4 @@
-"""Pins of the checker's Adam against closed forms of the update."""
+"""Pins of the oracle's Adam against closed forms of the update."""
 import torch
 
 from oracle import optim

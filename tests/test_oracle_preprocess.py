@@ -1,4 +1,4 @@
-"""Pins of the checker's preprocess (Sec. 3 Eq. 1, Sec. 4.1 covariance at the
+"""Pins of the oracle's preprocess (Sec. 3 Eq. 1, Sec. 4.1 covariance at the
 original focal length with the low-pass term) to library routines, closed
 forms, Monte-Carlo projection and invariants."""
 import math

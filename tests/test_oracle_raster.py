@@ -1,4 +1,4 @@
-"""Pins of the checker's compositing (Sec. 3 Eq. 2 on the dilated pixel set of
+"""Pins of the oracle's compositing (Sec. 3 Eq. 2 on the dilated pixel set of
 Sec. 4.1): hand-derived closed forms (tests/golden), a plain per-pixel loop over
 all Gaussians, invariants, and the full-render special cases."""
 import json

@@ -1,4 +1,4 @@
-"""Pins of the checker's SH basis (colour model of Sec. 3) to a library routine,
+"""Pins of the oracle's SH basis (colour model of Sec. 3) to a library routine,
 to orthonormality under an exact quadrature and to hand-evaluated values."""
 import math
 
