@@ -223,7 +223,8 @@ int ppt_of(const tgs_options& opt) {
 // Depth sort and the pair counts per (tile row, chunk), up to the row starts
 // and the device pair count.  Returns the depth-sort result buffer.
 tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
-                          hipStream_t strm, int* dres, const uint32_t** order) {
+                          uint64_t max_slices, hipStream_t strm, int* dres,
+                          const uint32_t** order) {
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
     auto* partials = reinterpret_cast<uint64_t*>(ws + L.scan_partials);
     // Gaussians by depth key (stable; culled and off-screen ones last)
@@ -237,7 +238,7 @@ tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& gr
     TGS_HIP(tgs::launch_counts(ws, L, *order, n, grid, strm));
     TGS_HIP(tgs::exclusive_scan_u32(u32(L.ecnt), u32(L.ecnt), nrow, partials, true, strm));
     TGS_HIP(tgs::exclusive_scan_u32(u32(L.pcnt), u32(L.pcnt), nrow, partials, true, strm));
-    TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, strm));
+    TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, max_slices, strm));
     return TGS_OK;
 }
 
@@ -294,8 +295,8 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.row_start = take((gy + 1) * 4);
     L.erow = take((gy + 1) * 4);
     L.first_slice = take((gy + 1) * 4);
-    L.slice_entry = take(slices * 4);
-    L.slice_row = take(slices * 4);
+    L.slice_desc = take(slices * 16);
+    L.slice_e1 = take(slices * 4);
     L.ent_id = take(cap * 4);
     L.ent_pp = take(cap * 4);
     L.ent_x = take(cap * 4);
@@ -442,7 +443,9 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     auto strm = static_cast<hipStream_t>(stream);
     int dres = 0;
     const uint32_t* order = nullptr;
-    if ((s = enqueue_counts(ws, L, grid, g->n, strm, &dres, &order)) != TGS_OK) return s;
+    const uint64_t max_slices = tgs::bin_max_slices(st->pair_capacity, grid.gy);
+    if ((s = enqueue_counts(ws, L, grid, g->n, max_slices, strm, &dres, &order)) != TGS_OK)
+        return s;
     // row starts (and the pair count) back to the host: the column sort is
     // then launched with exactly as many slices as there are
     TGS_HIP(hipMemcpyAsync(ctx->pinned, ws + L.row_start, (uint64_t(grid.gy) + 1) * 4,
@@ -678,9 +681,9 @@ tgs_status tgs_batch_bin_sort(tgs_context* ctx, const tgs_gaussians* g, int32_t 
         const uint32_t cap = uint32_t(st.pair_capacity);
         int dres = 0;
         const uint32_t* order = nullptr;
-        TGS_CHECK(enqueue_counts(ws, Ls[v], grids[v], g->n, strm, &dres, &order));
-        TGS_CHECK(enqueue_emit(ws, Ls[v], grids[v], g->n, order, tgs::bin_max_slices(cap, grids[v].gy),
-                               cap, strm));
+        const uint64_t max_slices = tgs::bin_max_slices(cap, grids[v].gy);
+        TGS_CHECK(enqueue_counts(ws, Ls[v], grids[v], g->n, max_slices, strm, &dres, &order));
+        TGS_CHECK(enqueue_emit(ws, Ls[v], grids[v], g->n, order, max_slices, cap, strm));
         publish_offsets(&st, Ls[v], grids[v], dres);
         st.pair_count = TGS_PAIR_COUNT_PENDING;
         st.key_bits = uint32_t(key_bits_for(grids[v].num_tiles()));

@@ -38,10 +38,8 @@ namespace tgs {
 namespace {
 
 constexpr int kBinThreads = 256;                           // Gaussians per count/entry block
-constexpr int kScatterThreads = 512;
-constexpr int kScatterWaves = kScatterThreads / 64;
-constexpr int kScatterRounds = kSlice / kScatterThreads;   // pairs per thread
-constexpr int kScatterCols = kMaxCols / kScatterThreads;   // columns per thread in the scan
+constexpr int kEntryBatch = 2;                             // 64-entry batches loaded at once
+constexpr int kScatterWaves = 8;                           // wavefronts per scatter block
 constexpr int kHistThreads = 256;
 constexpr int kHistCols = kMaxCols / kHistThreads;
 
@@ -117,11 +115,13 @@ count_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order,
 
 // row_start[r] = first pair of row r (row_start[gy] = pair count),
 // erow[r] = first entry of row r, first_slice[r] = first column-sort slice
-// of row r (prefix of ceil(pairs / kSlice)).
+// of row r (prefix of ceil(pairs / kSlice)); the last slice of a row ends at
+// the row's last entry (slice_e1).
 __global__ void __launch_bounds__(256)
 row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict__ pscan,
-                 uint32_t nblk, int gy, uint32_t* __restrict__ row_start,
-                 uint32_t* __restrict__ erow, uint32_t* __restrict__ first_slice) {
+                 uint32_t nblk, int gy, uint32_t max_slices, uint32_t* __restrict__ row_start,
+                 uint32_t* __restrict__ erow, uint32_t* __restrict__ first_slice,
+                 uint32_t* __restrict__ slice_e1) {
     __shared__ uint32_t carry;
     __shared__ uint32_t wsum[4];
     if (threadIdx.x == 0) carry = 0;
@@ -145,6 +145,8 @@ row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict_
             all += wsum[w];
         }
         if (ty <= gy) first_slice[ty] = before + ex;
+        if (ty < gy && ns > 0 && before + ex + ns <= max_slices)
+            slice_e1[before + ex + ns - 1] = escan[uint64_t(ty + 1) * nblk];
         __syncthreads();
         if (threadIdx.x == 0) carry += all;
         __syncthreads();
@@ -155,16 +157,16 @@ row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict_
 // (first pair of the entry), ent_x (xlo | xhi << 16).  One block scan per row
 // ranks the block's entries and pairs at once (packed: pairs << 12 | 1; a
 // block holds 256 entries and at most 256 * 1024 pairs of a row).  The entry
-// that holds the first pair of a column-sort slice records itself in
-// slice_entry.
+// that holds the first pair of a column-sort slice writes the slice's
+// descriptor and closes the slice before it.
 __global__ void __launch_bounds__(kBinThreads)
 entry_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order, int64_t n,
              Grid grid, uint32_t nblk, const uint32_t* __restrict__ escan,
              const uint32_t* __restrict__ pscan, const uint32_t* __restrict__ row_start,
              const uint32_t* __restrict__ first_slice, uint32_t capacity,
              uint32_t* __restrict__ ent_id, uint32_t* __restrict__ ent_pp,
-             uint32_t* __restrict__ ent_x, uint32_t* __restrict__ slice_entry,
-             uint32_t* __restrict__ slice_row) {
+             uint32_t* __restrict__ ent_x, uint4* __restrict__ slice_desc,
+             uint32_t* __restrict__ slice_e1) {
     __shared__ uint32_t s_w[2][kBinThreads / 64];
     __shared__ int s_lim[2][kBinThreads / 64];
     if (row_start[grid.gy] > capacity) return;          // overflow: block-uniform
@@ -204,34 +206,46 @@ entry_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order,
             ent_id[e] = id;
             ent_pp[e] = p;
             ent_x[e] = xpack;
-            // slices of the row that begin inside [p, p + w)
-            const uint32_t rel = p - row_start[r];
+            // slices of the row that begin inside [p, p + w): their
+            // descriptors, and the end of the slice before each (entries
+            // overlapping a slice boundary belong to both slices; row_setup
+            // ends every row's last slice)
+            const uint32_t rs = row_start[r];
+            const uint32_t rel = p - rs;
             const uint32_t k0 = (rel + kSlice - 1) / kSlice, k1 = (rel + w - 1) / kSlice;
-            for (uint32_t k = k0; k <= k1; ++k) {
-                slice_entry[first_slice[r] + k] = e;
-                slice_row[first_slice[r] + k] = uint32_t(r);
+            if (k0 <= k1) {
+                const uint32_t re = row_start[r + 1];
+                const uint32_t fs = first_slice[r], ns = first_slice[r + 1] - fs;
+                for (uint32_t k = k0; k <= k1; ++k) {
+                    const uint32_t a = rs + k * kSlice;
+                    slice_desc[fs + k] = make_uint4(e, a, min(a + uint32_t(kSlice), re),
+                                                    uint32_t(r) | (k + 1 == ns ? 1u << 31 : 0u));
+                    if (k > 0) slice_e1[fs + k - 1] = e + 1;
+                }
             }
         }
     }
 }
 
-// Locate slice b: its row (recorded by entry_kernel), index within the row,
-// pair range and the range of entries that may overlap it.
-struct Slice { int ty; uint32_t k, start, end, e0, e1; };
+// Slice b: its row, pair range and the range of entries that may overlap it
+// (the descriptor written by entry_kernel; e1 includes the entry that
+// straddles into the next slice).  False when b is past the slices or the
+// pairs overflowed the capacity.
+struct Slice { int ty; bool last; uint32_t start, end, e0, e1; };
 
 __device__ __forceinline__ bool find_slice(uint32_t b, const uint32_t* first_slice,
-                                           const uint32_t* row_start, const uint32_t* erow,
-                                           const uint32_t* slice_entry, const uint32_t* slice_row,
-                                           int gy, uint32_t capacity, Slice& s) {
-    if (row_start[gy] > capacity || b >= first_slice[gy]) return false;
-    const int lo = int(slice_row[b]);
-    s.ty = lo;
-    s.k = b - first_slice[lo];
-    s.start = row_start[lo] + s.k * kSlice;
-    s.end = min(s.start + uint32_t(kSlice), row_start[lo + 1]);
-    s.e0 = slice_entry[b];
-    // the next slice's first entry may straddle the boundary: include it
-    s.e1 = b + 1 < first_slice[lo + 1] ? slice_entry[b + 1] + 1 : erow[lo + 1];
+                                           const uint32_t* row_start, const uint4* slice_desc,
+                                           const uint32_t* slice_e1, int gy, uint32_t capacity,
+                                           Slice& s) {
+    const uint32_t total = row_start[gy], nsl = first_slice[gy];
+    const uint4 d = slice_desc[b];
+    s.e1 = slice_e1[b];
+    if (total > capacity || b >= nsl) return false;
+    s.e0 = d.x;
+    s.start = d.y;
+    s.end = d.z;
+    s.ty = int(d.w & 0x7FFFFFFFu);
+    s.last = (d.w >> 31) != 0;
     return true;
 }
 
@@ -251,14 +265,13 @@ __device__ __forceinline__ bool clip_entry(uint32_t pp, uint32_t xpack, uint32_t
 __global__ void __launch_bounds__(kHistThreads)
 slice_hist_kernel(const uint32_t* __restrict__ ent_pp, const uint32_t* __restrict__ ent_x,
                   const uint32_t* __restrict__ first_slice, const uint32_t* __restrict__ row_start,
-                  const uint32_t* __restrict__ erow, const uint32_t* __restrict__ slice_entry,
-                  const uint32_t* __restrict__ slice_row, Grid grid, uint32_t capacity,
-                  uint32_t* __restrict__ hist) {
+                  const uint4* __restrict__ slice_desc, const uint32_t* __restrict__ slice_e1,
+                  Grid grid, uint32_t capacity, uint32_t* __restrict__ hist) {
     __shared__ int32_t d[kMaxCols + 1];
     __shared__ uint32_t s_w[kHistThreads / 64];
     Slice s;
-    if (!find_slice(blockIdx.x, first_slice, row_start, erow, slice_entry, slice_row, grid.gy,
-                    capacity, s))
+    if (!find_slice(blockIdx.x, first_slice, row_start, slice_desc, slice_e1, grid.gy, capacity,
+                    s))
         return;                                         // block-uniform
     const int gx = grid.gx, tid = threadIdx.x;
     for (int c = tid; c <= gx; c += kHistThreads) d[c] = 0;
@@ -352,132 +365,175 @@ col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_
     }
 }
 
-// Per slice: expand the entries into the slice's pairs (column, Gaussian) in
-// LDS, rank them per column in input order, stage them by column in LDS and
-// write each to its final slot.
-__global__ void __launch_bounds__(kScatterThreads)
+// Per slice: a lane per column, one wavefront per (group of 64 columns,
+// part of the slice's entries).  A wavefront walks its part's entries in
+// depth order; an entry covering the lane's column appends (Gaussian, output
+// slot) to the column's run in LDS, so every run is in depth order without
+// ranking.  Runs are laid out in column order (local slot of column c = the
+// slice's pairs in columns < c), the parts of a column one after the other:
+// a part's first slot in a column follows the earlier parts' pairs there,
+// counted from difference arrays (+1 at an entry's first column, -1 after
+// its last) that the wavefronts fill before the walk.  The walk reads each
+// covering entry into scalar registers (readlane over the ballot of the
+// entries that touch the group), so per entry and wavefront it costs one
+// LDS write.  At the end each wavefront copies a share of its group's runs
+// out; a run's consecutive local slots go to consecutive output slots.
+//
+// The count of (slice b, column c) is base[b + 1][c] - base[b][c] for the
+// bases col_scan wrote, or the tile's end minus base[b][c] for the row's last
+// slice (an empty tile has end 0 and count 0).
+struct ScatterShape {
+    int groups, parts;
+};
+
+__host__ __device__ inline ScatterShape scatter_shape(int gx) {
+    const int groups = (gx + 63) / 64;
+    const int parts = groups >= kScatterWaves ? 1 : kScatterWaves / groups;
+    return ScatterShape{groups, parts};
+}
+
+__global__ void __launch_bounds__(1024)
 slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __restrict__ ent_pp,
                      const uint32_t* __restrict__ ent_x, const uint32_t* __restrict__ first_slice,
-                     const uint32_t* __restrict__ row_start, const uint32_t* __restrict__ erow,
-                     const uint32_t* __restrict__ slice_entry,
-                     const uint32_t* __restrict__ slice_row, const uint32_t* __restrict__ hist,
-                     Grid grid, int col_bits, uint32_t capacity, uint32_t* __restrict__ out) {
-    constexpr int W = kScatterWaves, R = kScatterRounds, PER_WAVE = 64 * R;
+                     const uint32_t* __restrict__ row_start, const uint4* __restrict__ slice_desc,
+                     const uint32_t* __restrict__ slice_e1, const uint32_t* __restrict__ base,
+                     const uint32_t* __restrict__ ranges, Grid grid, uint32_t max_slices,
+                     uint32_t capacity, uint32_t* __restrict__ out) {
     extern __shared__ uint32_t smem[];
     const int gx = grid.gx;
-    uint32_t* s_val = smem;                              // [kSlice]
-    uint32_t* s_wcnt = s_val + kSlice;                   // [W][gx]: counts, then wave prefixes
-    uint32_t* s_start = s_wcnt + W * gx;                 // [gx]: first local slot of a column
-    uint32_t* s_gbase = s_start + gx;                    // [gx]: first output slot of a column
-    uint32_t* s_w = s_gbase + gx;                        // [W]
-    uint16_t* s_col = reinterpret_cast<uint16_t*>(s_w + W);   // [kSlice]
+    const ScatterShape sh = scatter_shape(gx);
+    const int waves = sh.groups * sh.parts;
+    uint2* s_pair = reinterpret_cast<uint2*>(smem);                // [kSlice] (Gaussian, output slot)
+    int32_t* s_diff = reinterpret_cast<int32_t*>(s_pair + kSlice); // [waves][65]
+    uint32_t* s_gtot = reinterpret_cast<uint32_t*>(s_diff + 65 * waves);  // [groups]
+    const int w = int(threadIdx.x >> 6), lane = __lane_id();
+    const int g = w % sh.groups, p = w / sh.groups;
+    const uint32_t b = blockIdx.x;
+    const uint32_t cbeg = 64u * uint32_t(g), col = cbeg + uint32_t(lane);
+    const bool col_ok = col < uint32_t(gx);
+    // the slice and this column's bases (independent loads)
+    uint32_t c_base = 0, c_next = 0;
+    if (col_ok) {
+        c_base = base[uint64_t(b) * gx + col];
+        if (b + 1 < max_slices) c_next = base[uint64_t(b + 1) * gx + col];
+    }
     Slice s;
-    if (!find_slice(blockIdx.x, first_slice, row_start, erow, slice_entry, slice_row, grid.gy,
-                    capacity, s))
-        return;                                         // block-uniform
-    const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
-    const uint32_t count = s.end - s.start;
-    constexpr int CPT = kScatterCols;
-    // output bases of this thread's columns, loaded early
-    uint32_t gbase[CPT];
+    if (!find_slice(b, first_slice, row_start, slice_desc, slice_e1, grid.gy, capacity, s))
+        return;                                                    // block-uniform
+    // this part's entries [pe0, pe1)
+    const uint32_t ne = s.e1 - s.e0, per = (ne + uint32_t(sh.parts) - 1) / uint32_t(sh.parts);
+    const uint32_t pe0 = s.e0 + min(ne, uint32_t(p) * per);
+    const uint32_t pe1 = s.e0 + min(ne, uint32_t(p + 1) * per);
+    uint32_t pp[kEntryBatch], xp[kEntryBatch], id[kEntryBatch];
+    auto load = [&](uint32_t e) {
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int c = CPT * tid + j;
-        gbase[j] = c < gx ? hist[uint64_t(blockIdx.x) * gx + c] : 0u;
+        for (int j = 0; j < kEntryBatch; ++j) {
+            const uint32_t ee = e + 64u * uint32_t(j) + uint32_t(lane);
+            const bool ok = ee < pe1;
+            pp[j] = ok ? ent_pp[ee] : 0u;
+            xp[j] = ok ? ent_x[ee] : 0u;
+            id[j] = ok ? ent_id[ee] : 0u;
+        }
+    };
+    load(pe0);
+    if (s.last && col_ok) {
+        c_next = ranges[2 * (uint64_t(s.ty) * gx + col) + 1];
+        if (c_next == 0) c_next = c_base;
     }
-    for (int b = tid; b < W * gx; b += kScatterThreads) s_wcnt[b] = 0;
-    // the slice's pairs, in row-bucket order, expanded from its entries
-    for (uint32_t e = s.e0 + tid; e < s.e1; e += kScatterThreads) {
-        uint32_t c0, c1, p0;
-        if (clip_entry(ent_pp[e], ent_x[e], s.start, s.end, c0, c1, p0)) {
-            const uint32_t id = ent_id[e];
-            for (uint32_t c = c0, i = p0 - s.start; c < c1; ++c, ++i) {
-                s_val[i] = id;
-                s_col[i] = uint16_t(c);
+    const uint32_t cnt = col_ok ? c_next - c_base : 0u;
+    for (int i = int(threadIdx.x); i < 65 * waves; i += int(blockDim.x)) s_diff[i] = 0;
+    if (p == 0) {
+        const uint32_t t = wave_total(cnt);
+        if (lane == 0) s_gtot[g] = t;
+    }
+    __syncthreads();
+    // the columns [lo, hi) of the group that entry j of the batch at e
+    // covers in the slice (lo == hi: none)
+    auto cover = [&](int j, uint32_t e, uint32_t& lo, uint32_t& hi) {
+        const uint32_t ee = e + 64u * uint32_t(j) + uint32_t(lane);
+        uint32_t c0 = 0, c1 = 0, p0;
+        const bool in = ee < pe1 && clip_entry(pp[j], xp[j], s.start, s.end, c0, c1, p0);
+        lo = max(c0, cbeg) - cbeg;
+        hi = min(c1, cbeg + 64u);
+        hi = in && hi > cbeg ? hi - cbeg : 0u;
+        if (hi < lo) hi = lo;
+    };
+    // difference array of this wavefront's part over the group's columns
+    int32_t* diff = s_diff + 65 * w;
+    constexpr uint32_t kBatch = 64u * kEntryBatch;
+    for (uint32_t e = pe0; e < pe1; e += kBatch) {
+        if (e != pe0) load(e);
+#pragma unroll
+        for (int j = 0; j < kEntryBatch; ++j) {
+            if (e + 64u * uint32_t(j) >= pe1) break;               // wave-uniform
+            uint32_t lo, hi;
+            cover(j, e, lo, hi);
+            if (lo < hi) {
+                atomicAdd(&diff[lo], 1);
+                atomicAdd(&diff[hi], -1);
             }
         }
     }
     __syncthreads();
-    uint32_t myv[R];
-    uint32_t mycol[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t idx = uint32_t(wv * PER_WAVE + r * 64 + lane);
-        const bool valid = idx < count;
-        mycol[r] = valid ? uint32_t(s_col[idx]) : 0u;
-        myv[r] = valid ? s_val[idx] : 0u;
+    // first local slot and first output slot of the column in this part
+    uint32_t before = 0;
+    for (int h = 0; h < g; ++h) before += s_gtot[h];
+    uint32_t gtot;
+    uint32_t slot = before + wave_exclusive_sum(cnt, gtot);
+    uint32_t dst = c_base;
+    for (int q = 0; q < p; ++q) {
+        const uint32_t c = wave_inclusive_sum(uint32_t(s_diff[65 * (q * sh.groups + g) + lane]));
+        slot += c;
+        dst += c;
     }
-    // ranks within the wavefront's PER_WAVE consecutive pairs, in input order
-    uint32_t myrank[R];
-    uint32_t* wc = s_wcnt + wv * gx;
+    // the walk: the entries covering part of the group, in depth order,
+    // read into scalar registers (readlane over the ballot of the batch)
+    uint2* pv = s_pair + slot;                                     // next slot of the column
+    const bool reload = pe1 - pe0 > kBatch;
+    for (uint32_t e = pe0; e < pe1; e += kBatch) {
+        if (reload) load(e);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t idx = uint32_t(wv * PER_WAVE + r * 64 + lane);
-        const bool valid = idx < count;
-        const uint32_t c = mycol[r];
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < col_bits; ++b) {
-            const bool bit = (c >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t below = uint32_t(__popcll(peers & lanemask_lt()));
-        const uint32_t before = valid ? wc[c] : 0u;
-        myrank[r] = before + below;
-        if (valid && below == 0) wc[c] = before + uint32_t(__popcll(peers));
-    }
-    __syncthreads();
-    // per column: total over waves (wave counts become wave prefixes), then
-    // the columns' local starts by a block scan (kScatterCols columns per thread)
-    uint32_t tot[CPT];
-    uint32_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int c = CPT * tid + j;
-        tot[j] = 0;
-        if (c < gx) {
-            uint32_t t = 0;
-            for (int w = 0; w < W; ++w) {
-                const uint32_t v = s_wcnt[w * gx + c];
-                s_wcnt[w * gx + c] = t;
-                t += v;
+        for (int j = 0; j < kEntryBatch; ++j) {
+            if (e + 64u * uint32_t(j) >= pe1) break;               // wave-uniform
+            uint32_t lo, hi;
+            cover(j, e, lo, hi);
+            const uint32_t packed = lo | ((hi - lo) << 8);
+            uint64_t m = __ballot(lo < hi);
+            while (m) {
+                const int k = __builtin_ctzll(m);
+                m &= m - 1;
+                const uint32_t pk = uint32_t(__builtin_amdgcn_readlane(int(packed), k));
+                const uint32_t gid = uint32_t(__builtin_amdgcn_readlane(int(id[j]), k));
+                if (uint32_t(lane) - (pk & 0xFFu) < (pk >> 8)) {
+                    *pv++ = make_uint2(gid, dst);
+                    ++dst;
+                }
             }
-            tot[j] = t;
-        }
-        mine += tot[j];
-    }
-    uint32_t all;
-    uint32_t ex = block_exclusive_sum<kScatterThreads>(mine, s_w, all);
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int c = CPT * tid + j;
-        if (c < gx) {
-            s_start[c] = ex;
-            s_gbase[c] = gbase[j];
-        }
-        ex += tot[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t idx = uint32_t(wv * PER_WAVE + r * 64 + lane);
-        if (idx < count) {
-            const uint32_t c = mycol[r];
-            const uint32_t pos = s_start[c] + s_wcnt[wv * gx + c] + myrank[r];
-            s_val[pos] = myv[r];
-            s_col[pos] = uint16_t(c);
         }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < count; i += kScatterThreads) {
-        const uint32_t c = s_col[i];
-        out[s_gbase[c] + (i - s_start[c])] = s_val[i];
+    // a share of the group's runs, local slots [before, before + gtot) (the
+    // counts of a consistent column sort keep them within kSlice)
+    const uint32_t share = (gtot + uint32_t(sh.parts) - 1) / uint32_t(sh.parts);
+    const uint32_t i0 = before + min(gtot, uint32_t(p) * share);
+    const uint32_t i1 = min(before + min(gtot, uint32_t(p + 1) * share), uint32_t(kSlice));
+    for (uint32_t i = i0 + uint32_t(lane); i < i1; i += 256u) {
+        uint2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t ii = i + 64u * uint32_t(q);
+            v[q] = ii < i1 ? s_pair[ii] : make_uint2(0u, capacity);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v[q].y < capacity) out[v[q].y] = v[q].x;
     }
 }
 
 size_t scatter_lds_bytes(int gx) {
-    return size_t(kSlice) * 4 + size_t(kScatterWaves * gx + 2 * gx + kScatterWaves) * 4 +
-           size_t(kSlice) * 2;
+    const ScatterShape sh = scatter_shape(gx);
+    const size_t waves = size_t(sh.groups) * sh.parts;
+    return size_t(kSlice) * 8 + waves * 65 * 4 + size_t(sh.groups) * 4;
 }
 
 }  // namespace
@@ -499,12 +555,12 @@ hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* ord
 }
 
 hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid& grid,
-                            hipStream_t s) {
-    row_setup_kernel<<<1, 256, 0, s>>>(reinterpret_cast<const uint32_t*>(ws + L.ecnt),
-                                       reinterpret_cast<const uint32_t*>(ws + L.pcnt), bin_blocks(n),
-                                       grid.gy, reinterpret_cast<uint32_t*>(ws + L.row_start),
-                                       reinterpret_cast<uint32_t*>(ws + L.erow),
-                                       reinterpret_cast<uint32_t*>(ws + L.first_slice));
+                            uint64_t max_slices, hipStream_t s) {
+    auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+    row_setup_kernel<<<1, 256, 0, s>>>(u32(L.ecnt), u32(L.pcnt), bin_blocks(n), grid.gy,
+                                       uint32_t(std::min<uint64_t>(max_slices, 0xFFFFFFFFu)),
+                                       u32(L.row_start), u32(L.erow), u32(L.first_slice),
+                                       u32(L.slice_e1));
     return hipGetLastError();
 }
 
@@ -516,14 +572,15 @@ hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, i
     entry_kernel<<<dim3(nblk), dim3(kBinThreads), 0, s>>>(
         reinterpret_cast<const float4*>(ws + L.records), order, n, grid, nblk, u32(L.ecnt),
         u32(L.pcnt), u32(L.row_start), u32(L.first_slice), capacity, u32(L.ent_id),
-        u32(L.ent_pp), u32(L.ent_x), u32(L.slice_entry), u32(L.slice_row));
+        u32(L.ent_pp), u32(L.ent_x), reinterpret_cast<uint4*>(ws + L.slice_desc), u32(L.slice_e1));
     return hipGetLastError();
 }
 
 hipError_t prepare_binning_kernels() {
+    size_t most = 0;
+    for (int gx = 1; gx <= kMaxCols; gx += 64) most = std::max(most, scatter_lds_bytes(gx));
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&slice_scatter_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(scatter_lds_bytes(kMaxCols)));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(most));
 }
 
 hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,
@@ -531,24 +588,22 @@ hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint6
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
     const uint32_t* fs = u32(L.first_slice);
     const uint32_t* rs = u32(L.row_start);
-    const uint32_t* er = u32(L.erow);
-    const uint32_t* se = u32(L.slice_entry);
-    const uint32_t* sr = u32(L.slice_row);
+    const auto* sd = reinterpret_cast<const uint4*>(ws + L.slice_desc);
+    const uint32_t* e1 = u32(L.slice_e1);
     uint32_t* hist = u32(L.col_hist);
     if (slices > 0) {
         slice_hist_kernel<<<dim3(unsigned(slices)), dim3(kHistThreads), 0, s>>>(
-            u32(L.ent_pp), u32(L.ent_x), fs, rs, er, se, sr, grid, capacity, hist);
+            u32(L.ent_pp), u32(L.ent_x), fs, rs, sd, e1, grid, capacity, hist);
     }
     col_scan_kernel<<<dim3(unsigned(grid.gy)), dim3(1024), 0, s>>>(hist, fs, rs, grid, capacity,
                                                                   u32(L.ranges));
     if (slices > 0) {
-        int bits = 1;
-        while ((1 << bits) < grid.gx) ++bits;
-        // LDS above the default 64 KiB is enabled once by prepare_binning_kernels
-        slice_scatter_kernel<<<dim3(unsigned(slices)), dim3(kScatterThreads),
-                               scatter_lds_bytes(grid.gx), s>>>(
-            u32(L.ent_id), u32(L.ent_pp), u32(L.ent_x), fs, rs, er, se, sr, hist, grid, bits,
-            capacity, u32(L.pair_vals));
+        const ScatterShape sh = scatter_shape(grid.gx);
+        const unsigned threads = 64u * unsigned(sh.groups * sh.parts);
+        slice_scatter_kernel<<<dim3(unsigned(slices)), dim3(threads), scatter_lds_bytes(grid.gx),
+                               s>>>(u32(L.ent_id), u32(L.ent_pp), u32(L.ent_x), fs, rs, sd, e1,
+                                    hist, u32(L.ranges), grid, uint32_t(slices), capacity,
+                                    u32(L.pair_vals));
     }
     return hipGetLastError();
 }

@@ -52,8 +52,9 @@ struct Layout {
     uint64_t row_start;        // uint32[gy + 1], first pair of every row
     uint64_t erow;             // uint32[gy + 1], first entry of every row
     uint64_t first_slice;      // uint32[gy + 1]
-    uint64_t slice_entry;      // uint32[max_slices], entry holding a slice's first pair
-    uint64_t slice_row;        // uint32[max_slices], tile row of each slice
+    uint64_t slice_desc;       // uint4[max_slices]: first entry, first pair, end pair,
+                               //   tile row | last-slice-of-row << 31
+    uint64_t slice_e1;         // uint32[max_slices], one past the slice's last entry
     uint64_t ent_id;           // uint32[capacity], Gaussian of each entry (row-bucketed)
     uint64_t ent_pp;           // uint32[capacity], first pair of each entry
     uint64_t ent_x;            // uint32[capacity], xlo | xhi << 16 of each entry
@@ -128,7 +129,7 @@ uint64_t bin_max_slices(uint64_t pairs, int gy);
 hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
                          const Grid& grid, hipStream_t s);
 hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid& grid,
-                            hipStream_t s);
+                            uint64_t max_slices, hipStream_t s);
 hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
                           const Grid& grid, uint32_t capacity, hipStream_t s);
 // Stable counting sort of every row bucket by column, and the tile ranges;

@@ -406,24 +406,34 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     }
 }
 
+// L1 loss of Eq. 1-2 over the dilated image and its gradient.  Blocks walk
+// rows of the strided image (the rows of a pixel phase), so the image and
+// dL accesses are contiguous; one double atomic per block adds the block's
+// share of the loss (a bounded number of atomics on one address).
+constexpr unsigned kL1MaxBlocks = 2048;
+
 __global__ void __launch_bounds__(256)
 l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restrict__ target,
                float* __restrict__ dL, double* __restrict__ loss) {
     __shared__ double wsum[4];
-    const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
-    const uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t w = uint32_t(grid.w_ds), h = uint32_t(grid.h_ds);
+    const uint64_t pix = uint64_t(w) * h;
+    const uint64_t full = uint64_t(grid.width) * grid.height;
+    const float inv = 1.0f / float(3 * pix);
     double s = 0.0;
-    if (p < pix) {
-        const int i = int(p % uint64_t(grid.w_ds)), j = int(p / uint64_t(grid.w_ds));
-        const uint64_t X = uint64_t(grid.stride) * i + grid.off_x;
+    for (uint32_t j = blockIdx.x; j < h; j += gridDim.x) {
         const uint64_t Y = uint64_t(grid.stride) * j + grid.off_y;
-        const uint64_t full = uint64_t(grid.width) * grid.height;
-        const float inv = 1.0f / float(3 * pix);
-        for (int c = 0; c < 3; ++c) {
-            const float diff = image[c * pix + p] - target[c * full + Y * grid.width + X];
-            const float sg = diff > 0.0f ? 1.0f : (diff < 0.0f ? -1.0f : 0.0f);
-            dL[c * pix + p] = sg * inv;
-            s += fabs(double(diff));
+        const float* trow = target + Y * grid.width + grid.off_x;
+        for (uint32_t i = threadIdx.x; i < w; i += blockDim.x) {
+            const uint64_t p = uint64_t(j) * w + i;
+            const uint64_t X = uint64_t(grid.stride) * i;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float diff = image[c * pix + p] - trow[c * full + X];
+                const float sg = diff > 0.0f ? 1.0f : (diff < 0.0f ? -1.0f : 0.0f);
+                dL[c * pix + p] = sg * inv;
+                s += fabs(double(diff));
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
@@ -491,8 +501,8 @@ hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* tar
         if (e != hipSuccess) return e;
     }
     if (pix == 0) return hipSuccess;
-    l1_grad_kernel<<<dim3(unsigned((pix + 255) / 256)), dim3(256), 0, s>>>(grid, image, target,
-                                                                           dL_dimage, loss);
+    const unsigned blocks = unsigned(std::min<uint64_t>(uint64_t(grid.h_ds), kL1MaxBlocks));
+    l1_grad_kernel<<<dim3(blocks), dim3(256), 0, s>>>(grid, image, target, dL_dimage, loss);
     return hipGetLastError();
 }
 
