@@ -202,9 +202,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
                 float dx, dy, t, G, raw, alpha;
                 const bool hit = splat_alpha(a, b, X[k], Y[k], dx, dy, t, G, raw, alpha) && !done[k];
                 const float w0 = alpha * Tr[k];
-                const bool keep = Tr[k] - w0 >= kTMin;      // T after this entry
-                const bool blend = hit && keep;
-                const bool stop = hit && !keep;
+                // T after this entry below the floor: the pixel stops here;
+                // otherwise it blends (one comparison: stop implies hit)
+                const bool stop = hit && Tr[k] - w0 < kTMin;
+                const bool blend = hit != stop;
                 const float w = blend ? w0 : 0.0f;
                 c0[k] = fmaf(b.z, w, c0[k]);
                 c1[k] = fmaf(b.w, w, c1[k]);
@@ -338,9 +339,8 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             for (int k = 0; k < S::NP; ++k) {
                 const bool hit =
                     splat_alpha(a, b, X[k], Y[k], dx[k], dy[k], t[k], G[k], raw[k], alpha[k]) && !done[k];
-                const bool keep = Tr[k] - alpha[k] * Tr[k] >= kTMin;
-                const bool stop = hit && !keep;
-                blend[k] = hit && keep;
+                const bool stop = hit && Tr[k] - alpha[k] * Tr[k] < kTMin;
+                blend[k] = hit != stop;
                 any = any || blend[k];
                 done[k] = done[k] || stop;
                 alive = alive || !done[k];
