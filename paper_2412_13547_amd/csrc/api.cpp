@@ -183,6 +183,7 @@ tgs::PrepView prep_view(const tgs_camera& cam, const tgs::Grid& grid, uint8_t* w
     v.grid = grid;
     v.rec = reinterpret_cast<tgs_record*>(ws + L.records);
     v.touched = reinterpret_cast<uint32_t*>(ws + L.tiles_touched);
+    v.rects = reinterpret_cast<uint2*>(ws + L.rects);
     v.depth_key = reinterpret_cast<uint32_t*>(ws + L.depth_key[0]);
     v.depth_val = reinterpret_cast<uint32_t*>(ws + L.depth_val[0]);
     v.g2d = reinterpret_cast<const float*>(ws + L.grad2d);
@@ -288,6 +289,8 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     const uint64_t hist = gx * slices;
     L.records = take(un * kRecordBytes);
     L.tiles_touched = take(un * 4);
+    L.rects = take(un * 8);
+    L.srect = take(un * 8);
     for (int b = 0; b < 2; ++b) L.depth_key[b] = take(un * 4);
     for (int b = 0; b < 2; ++b) L.depth_val[b] = take(un * 4);
     L.ecnt = take(table * 4);

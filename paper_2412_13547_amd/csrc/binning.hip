@@ -53,20 +53,12 @@ __device__ __forceinline__ int wave_max(int x) {
     return x;
 }
 
-// The tile rectangle of the Gaussian at depth position s (empty when culled,
-// off-screen or s >= n).
-__device__ __forceinline__ Rect rect_of(const float4* rec, const uint32_t* order, int64_t s,
-                                        int64_t n, const Grid& grid, uint32_t& id) {
-    Rect r{0, 0, 0, 0};
-    id = 0;
-    if (s < n) {
-        id = order[s];
-        const float4 a = rec[3 * uint64_t(id)];
-        const int radius = __float_as_int(rec[3 * uint64_t(id) + 2].z);
-        if (radius > 0) r = tile_rect(a.x, a.y, radius, grid);
-        if (r.xhi <= r.xlo || r.yhi <= r.ylo) r = Rect{0, 0, 0, 0};
-    }
-    return r;
+// The packed tile rectangle (written by the preprocess, empty when culled or
+// off the grid) of the Gaussian at depth position s, gathered by id and kept
+// in depth order for the entry kernel; empty for s >= n.
+__device__ __forceinline__ uint2 gather_rect(const uint2* rects, const uint32_t* order, int64_t s,
+                                             int64_t n) {
+    return s < n ? rects[order[s]] : make_uint2(0u, 0u);
 }
 
 // Block-wide exclusive scan (blockDim.x = NT, one value per thread).
@@ -91,16 +83,19 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t* s_
 // ecnt[r * nblk + blk], pcnt[r * nblk + blk] (row-major, so one flat scan
 // gives the row starts and every block's offset inside every row).
 __global__ void __launch_bounds__(kBinThreads)
-count_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order, int64_t n,
-             Grid grid, uint32_t nblk, uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt) {
+count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order, int64_t n,
+             Grid grid, uint32_t nblk, uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt,
+             uint2* __restrict__ srect) {
     extern __shared__ uint32_t lds[];
     const int gy = grid.gy;
     uint32_t* ce = lds;           // [gy]
     uint32_t* cp = lds + gy;      // [gy]
     for (int r = threadIdx.x; r < gy; r += kBinThreads) ce[r] = cp[r] = 0;
     __syncthreads();
-    uint32_t id;
-    const Rect rc = rect_of(rec, order, int64_t(blockIdx.x) * kBinThreads + threadIdx.x, n, grid, id);
+    const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
+    const uint2 packed = gather_rect(rects, order, s, n);
+    if (s < n) srect[s] = packed;
+    const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
     for (int r = rc.ylo; r < rc.yhi; ++r) {
         atomicAdd(&ce[r], 1u);
@@ -160,7 +155,7 @@ row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict_
 // that holds the first pair of a column-sort slice writes the slice's
 // descriptor and closes the slice before it.
 __global__ void __launch_bounds__(kBinThreads)
-entry_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order, int64_t n,
+entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order, int64_t n,
              Grid grid, uint32_t nblk, const uint32_t* __restrict__ escan,
              const uint32_t* __restrict__ pscan, const uint32_t* __restrict__ row_start,
              const uint32_t* __restrict__ first_slice, uint32_t capacity,
@@ -171,10 +166,12 @@ entry_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ order,
     __shared__ int s_lim[2][kBinThreads / 64];
     if (row_start[grid.gy] > capacity) return;          // overflow: block-uniform
     const int wv = threadIdx.x >> 6;
-    uint32_t id;
-    const Rect rc = rect_of(rec, order, int64_t(blockIdx.x) * kBinThreads + threadIdx.x, n, grid, id);
+    const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
+    const uint32_t id = s < n ? order[s] : 0u;
+    const uint2 packed = s < n ? srect[s] : make_uint2(0u, 0u);
+    const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
-    const uint32_t xpack = uint32_t(rc.xlo) | (uint32_t(rc.xhi) << 16);
+    const uint32_t xpack = packed.x;
     // rows the block touches
     const int lo = wave_min(rc.yhi > rc.ylo ? rc.ylo : grid.gy), hi = wave_max(rc.yhi);
     if (__lane_id() == 0) {
@@ -548,8 +545,9 @@ hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* ord
     if (nblk > 0) {
         auto* w = const_cast<uint8_t*>(ws);
         count_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy) * 8, s>>>(
-            reinterpret_cast<const float4*>(ws + L.records), order, n, grid, nblk,
-            reinterpret_cast<uint32_t*>(w + L.ecnt), reinterpret_cast<uint32_t*>(w + L.pcnt));
+            reinterpret_cast<const uint2*>(ws + L.rects), order, n, grid, nblk,
+            reinterpret_cast<uint32_t*>(w + L.ecnt), reinterpret_cast<uint32_t*>(w + L.pcnt),
+            reinterpret_cast<uint2*>(w + L.srect));
     }
     return hipGetLastError();
 }
@@ -570,7 +568,7 @@ hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, i
     if (nblk == 0) return hipSuccess;
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
     entry_kernel<<<dim3(nblk), dim3(kBinThreads), 0, s>>>(
-        reinterpret_cast<const float4*>(ws + L.records), order, n, grid, nblk, u32(L.ecnt),
+        reinterpret_cast<const uint2*>(ws + L.srect), order, n, grid, nblk, u32(L.ecnt),
         u32(L.pcnt), u32(L.row_start), u32(L.first_slice), capacity, u32(L.ent_id),
         u32(L.ent_pp), u32(L.ent_x), reinterpret_cast<uint4*>(ws + L.slice_desc), u32(L.slice_e1));
     return hipGetLastError();

@@ -46,6 +46,8 @@ Grid make_grid(const tgs_camera& cam, const tgs_dilation& dil, int tile);
 // Byte offsets of the sub-buffers of one view's workspace.
 struct Layout {
     uint64_t records, tiles_touched;
+    uint64_t rects;            // uint2[n], tile rectangle per Gaussian (packed, empty if culled)
+    uint64_t srect;            // uint2[n], the same in depth order
     uint64_t depth_key[2], depth_val[2];
     uint64_t ecnt;             // uint32[gy * blocks + 1], entries per (row, block), then scanned
     uint64_t pcnt;             // uint32[gy * blocks + 1], pairs per (row, block), then scanned
@@ -90,6 +92,7 @@ struct PrepView {
     Grid grid;
     tgs_record* rec;          // forward out / backward in
     uint32_t* touched;        // forward out / backward in
+    uint2* rects;             // forward out: packed tile rectangle (pack_rect)
     uint32_t* depth_key;      // forward out
     uint32_t* depth_val;      // forward out
     const float* g2d;         // backward in
@@ -211,6 +214,16 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // holding a downsampled pixel in [u_ds - r_ds, u_ds + r_ds].  Evaluated in
 // IEEE double in a fixed order so every stage gets the same integers.
 struct Rect { int xlo, xhi, ylo, yhi; };
+
+// A rectangle in 8 bytes: (xlo | xhi << 16, ylo | yhi << 16); grids are far
+// below 65536 tiles a side.
+__host__ __device__ inline uint2 pack_rect(const Rect& r) {
+    return make_uint2(uint32_t(r.xlo) | (uint32_t(r.xhi) << 16),
+                      uint32_t(r.ylo) | (uint32_t(r.yhi) << 16));
+}
+__host__ __device__ inline Rect unpack_rect(uint2 p) {
+    return Rect{int(p.x & 0xFFFFu), int(p.x >> 16), int(p.y & 0xFFFFu), int(p.y >> 16)};
+}
 __host__ __device__ inline Rect tile_rect(float u, float v, int radius, const Grid& g) {
     const double d = double(g.stride), T = double(g.tile);
     const double half = 0.5 * double(g.stride - 1);

@@ -180,12 +180,13 @@ __device__ __forceinline__ bool finite_all(const float* x, int k) {
     return ok;
 }
 
-// The record of one Gaussian in one view; returns the tiles it overlaps.
+// The record of one Gaussian in one view and its packed tile rectangle
+// (empty when culled or off the grid); returns the tiles it overlaps.
 template <int DEG>
 __device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid& grid, bool ok,
                                                    const float m[3], const float s[3],
                                                    const float q[4], float op, const float* sh,
-                                                   float4 out[3]) {
+                                                   float4 out[3], uint2& rect) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     Proj p;
     ok = ok && project(cam, m, s, q, p);
@@ -201,6 +202,7 @@ __device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid
         radius = int(ceilf(3.0f * sqrtf(lam)));
         ok = radius > 0;
     }
+    rect = make_uint2(0u, 0u);
     if (!ok) {
         out[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -227,7 +229,9 @@ __device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid
     out[1] = make_float4(C, op, rgb[0], rgb[1]);
     out[2] = make_float4(rgb[2], p.tz, __int_as_float(radius), __uint_as_float(flags));
     const Rect rc = tile_rect(p.u, p.v, radius, grid);
-    return uint32_t(rc.xhi - rc.xlo) * uint32_t(rc.yhi - rc.ylo);
+    const uint32_t nt = uint32_t(rc.xhi - rc.xlo) * uint32_t(rc.yhi - rc.ylo);
+    if (nt > 0) rect = pack_rect(rc);
+    return nt;
 }
 
 // One thread per Gaussian: the parameters are read once and the record of
@@ -250,12 +254,14 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
     for (int v = 0; v < nv; ++v) {
         const PrepView& pv = views.v[v];
         float4 r[3];
-        const uint32_t nt = preprocess_one<DEG>(pv.cam, pv.grid, ok, m, s, q, op, sh, r);
+        uint2 rect;
+        const uint32_t nt = preprocess_one<DEG>(pv.cam, pv.grid, ok, m, s, q, op, sh, r, rect);
         float4* dst = reinterpret_cast<float4*>(pv.rec + i);
         dst[0] = r[0];
         dst[1] = r[1];
         dst[2] = r[2];
         pv.touched[i] = nt;
+        pv.rects[i] = rect;
         pv.depth_key[i] = nt > 0 ? __float_as_uint(r[2].y) : 0xFFFFFFFFu;
         pv.depth_val[i] = uint32_t(i);
     }
