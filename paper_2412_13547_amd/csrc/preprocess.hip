@@ -303,7 +303,8 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
                 const float d = Y[k] * graw[c];
                 if constexpr (ACC) dsh_acc[k * 3 + c] += d;
                 else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
-                acc += sh_g[(k * 3 + c) * n + i] * graw[c];
+                // a Gaussian the view does not see skips the read (result unused)
+                acc += (vis ? sh_g[(k * 3 + c) * n + i] : 0.0f) * graw[c];
             }
             w[k] = acc;
         }
@@ -417,10 +418,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     const bool vis = pv.touched[i] > 0 && !(flags & kCulled);
     float gr[kGrad2d];
     for (int k = 0; k < kGrad2d; ++k) gr[k] = vis ? pv.g2d[i * kGrad2d + k] : 0.0f;
+    // parameters only of Gaussians the view sees: the others' gradients and
+    // statistics are zero, and their lanes' results are discarded
     float m[3], s[3], q[4];
-    for (int k = 0; k < 3; ++k) m[k] = g.means[k * n + i];
-    for (int k = 0; k < 3; ++k) s[k] = g.scales[k * n + i];
-    for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
+    for (int k = 0; k < 3; ++k) m[k] = vis ? g.means[k * n + i] : 0.0f;
+    for (int k = 0; k < 3; ++k) s[k] = vis ? g.scales[k * n + i] : 1.0f;
+    for (int k = 0; k < 4; ++k) q[k] = vis ? g.quats[k * n + i] : 1.0f;
     float dm[3], ds[3], dq[4];
     preprocess_grad_one<DEG, false>(pv.cam, m, s, q, g.sh, out.sh, n, i, flags, gr, dm, ds, dq,
                                     nullptr, vis);

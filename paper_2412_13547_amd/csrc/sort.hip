@@ -187,16 +187,26 @@ hipError_t exclusive_scan(const In* in, const uint32_t* gather, Out* out, uint64
     return hipGetLastError();
 }
 
-__global__ void fill_kernel(uint32_t* p, uint32_t value, uint64_t count) {
+// 16-byte stores over the aligned body, single words for the head and tail.
+__global__ void fill_kernel(uint32_t* p, uint32_t value, uint64_t head, uint64_t n4,
+                            uint64_t count) {
     const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = value;
+    if (i < n4) reinterpret_cast<uint4*>(p + head)[i] = make_uint4(value, value, value, value);
+    if (i < head) p[i] = value;
+    const uint64_t t = head + 4 * n4 + i;
+    if (i < 4 && t < count) p[t] = value;
 }
 
 }  // namespace
 
 hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    fill_kernel<<<dim3(unsigned((count + 255) / 256)), dim3(256), 0, s>>>(p, value, count);
+    const uint64_t mis = (reinterpret_cast<uintptr_t>(p) / 4) % 4;
+    const uint64_t head = std::min<uint64_t>(count, mis == 0 ? 0 : 4 - mis);
+    const uint64_t n4 = (count - head) / 4;
+    const uint64_t threads = std::max<uint64_t>(n4, 4);
+    fill_kernel<<<dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s>>>(p, value, head, n4,
+                                                                              count);
     return hipGetLastError();
 }
 
