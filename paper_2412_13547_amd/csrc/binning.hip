@@ -41,6 +41,7 @@ constexpr int kBinThreads = 256;                           // Gaussians per coun
 constexpr int kEntryBatch = 2;                             // 64-entry batches loaded at once
 constexpr int kScatterWaves = 8;                           // wavefronts per scatter block
 constexpr int kHistThreads = 256;
+constexpr int kColBatch = 16;                              // slices loaded together in col_scan
 constexpr int kHistCols = kMaxCols / kHistThreads;
 
 __device__ __forceinline__ int wave_min(int x) {
@@ -328,8 +329,16 @@ col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_
     const bool act = g < groups;
     const uint32_t seg = (ns + groups - 1) / groups;
     const uint32_t k0 = act ? min(ns, uint32_t(g) * seg) : 0, k1 = act ? min(ns, k0 + seg) : 0;
+    // kColBatch independent loads in flight per thread
     uint32_t sum = 0;
-    for (uint32_t k = k0; k < k1; ++k) sum += hist[uint64_t(s0 + k) * gx + tx];
+    for (uint32_t k = k0; k < k1; k += kColBatch) {
+        uint32_t v[kColBatch];
+#pragma unroll
+        for (int q = 0; q < kColBatch; ++q)       // clamped: no branch between the loads
+            v[q] = hist[uint64_t(s0 + min(k + q, k1 - 1)) * gx + tx];
+#pragma unroll
+        for (int q = 0; q < kColBatch; ++q) sum += k + q < k1 ? v[q] : 0u;
+    }
     s_seg[t] = sum;
     __syncthreads();
     // column totals; segment sums -> exclusive prefixes over segments
@@ -353,11 +362,16 @@ col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_
     __syncthreads();
     if (act) {
         uint32_t run = s_start[tx] + s_seg[t];
-        for (uint32_t k = k0; k < k1; ++k) {
-            const uint64_t at = uint64_t(s0 + k) * gx + tx;
-            const uint32_t v = hist[at];
-            hist[at] = run;
-            run += v;
+        for (uint32_t k = k0; k < k1; k += kColBatch) {
+            uint32_t v[kColBatch];
+#pragma unroll
+            for (int q = 0; q < kColBatch; ++q)
+                v[q] = hist[uint64_t(s0 + min(k + q, k1 - 1)) * gx + tx];
+#pragma unroll
+            for (int q = 0; q < kColBatch; ++q) {
+                if (k + q < k1) hist[uint64_t(s0 + k + q) * gx + tx] = run;
+                run += v[q];
+            }
         }
     }
 }
