@@ -165,7 +165,23 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
              uint32_t* __restrict__ slice_e1) {
     __shared__ uint32_t s_w[2][kBinThreads / 64];
     __shared__ int s_lim[2][kBinThreads / 64];
-    if (row_start[grid.gy] > capacity) return;          // overflow: block-uniform
+    // per row: this block's first entry and pair, the row's first pair and
+    // first slice (loaded once, so the row loop never waits on memory)
+    extern __shared__ uint32_t s_row[];
+    const int gy = grid.gy;
+    uint32_t* s_e = s_row;
+    uint32_t* s_p = s_row + (gy + 1);
+    uint32_t* s_rs = s_row + 2 * (gy + 1);
+    uint32_t* s_fs = s_row + 3 * (gy + 1);
+    if (row_start[gy] > capacity) return;               // overflow: block-uniform
+    for (int r = threadIdx.x; r <= gy; r += kBinThreads) {
+        if (r < gy) {
+            s_e[r] = escan[uint64_t(r) * nblk + blockIdx.x];
+            s_p[r] = pscan[uint64_t(r) * nblk + blockIdx.x];
+        }
+        s_rs[r] = row_start[r];
+        s_fs[r] = first_slice[r];
+    }
     const int wv = threadIdx.x >> 6;
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
     const uint32_t id = s < n ? order[s] : 0u;
@@ -174,13 +190,13 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
     const uint32_t xpack = packed.x;
     // rows the block touches
-    const int lo = wave_min(rc.yhi > rc.ylo ? rc.ylo : grid.gy), hi = wave_max(rc.yhi);
+    const int lo = wave_min(rc.yhi > rc.ylo ? rc.ylo : gy), hi = wave_max(rc.yhi);
     if (__lane_id() == 0) {
         s_lim[0][wv] = lo;
         s_lim[1][wv] = hi;
     }
     __syncthreads();
-    int r0 = grid.gy, r1 = 0;
+    int r0 = gy, r1 = 0;
     for (int k = 0; k < kBinThreads / 64; ++k) {
         r0 = min(r0, s_lim[0][k]);
         r1 = max(r1, s_lim[1][k]);
@@ -198,9 +214,8 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
         for (int k = 0; k < wv; ++k) before += sw[k];
         if (in) {
             const uint32_t rank = before + ex;
-            const uint64_t at = uint64_t(r) * nblk + blockIdx.x;
-            const uint32_t e = escan[at] + (rank & 0xFFFu);
-            const uint32_t p = pscan[at] + (rank >> 12);
+            const uint32_t e = s_e[r] + (rank & 0xFFFu);
+            const uint32_t p = s_p[r] + (rank >> 12);
             ent_id[e] = id;
             ent_pp[e] = p;
             ent_x[e] = xpack;
@@ -208,12 +223,12 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
             // descriptors, and the end of the slice before each (entries
             // overlapping a slice boundary belong to both slices; row_setup
             // ends every row's last slice)
-            const uint32_t rs = row_start[r];
+            const uint32_t rs = s_rs[r];
             const uint32_t rel = p - rs;
             const uint32_t k0 = (rel + kSlice - 1) / kSlice, k1 = (rel + w - 1) / kSlice;
             if (k0 <= k1) {
-                const uint32_t re = row_start[r + 1];
-                const uint32_t fs = first_slice[r], ns = first_slice[r + 1] - fs;
+                const uint32_t re = s_rs[r + 1];
+                const uint32_t fs = s_fs[r], ns = s_fs[r + 1] - fs;
                 for (uint32_t k = k0; k <= k1; ++k) {
                     const uint32_t a = rs + k * kSlice;
                     slice_desc[fs + k] = make_uint4(e, a, min(a + uint32_t(kSlice), re),
@@ -581,7 +596,7 @@ hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, i
     const uint32_t nblk = bin_blocks(n);
     if (nblk == 0) return hipSuccess;
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
-    entry_kernel<<<dim3(nblk), dim3(kBinThreads), 0, s>>>(
+    entry_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy + 1) * 16, s>>>(
         reinterpret_cast<const uint2*>(ws + L.srect), order, n, grid, nblk, u32(L.ecnt),
         u32(L.pcnt), u32(L.row_start), u32(L.first_slice), capacity, u32(L.ent_id),
         u32(L.ent_pp), u32(L.ent_x), reinterpret_cast<uint4*>(ws + L.slice_desc), u32(L.slice_e1));
