@@ -6,10 +6,11 @@
 //                     (one private histogram per wavefront, then summed) and
 //                     stores them digit-major, counts[digit][block];
 //   2. exclusive scan of counts -> first output slot of (digit, block);
-//   3. scatter      : the block walks its keys in input order, 256 at a time;
-//                     equal digits inside a wavefront are ranked with eight
-//                     ballots, wavefronts are ordered through LDS, so equal
-//                     keys keep their input order (stability).
+//   3. scatter      : the block sorts its tile by digit in LDS, walking its
+//                     keys in input order 256 at a time (equal digits inside a
+//                     wavefront ranked with eight ballots, wavefronts ordered
+//                     through LDS, so equal keys keep their input order), then
+//                     writes each digit's run to consecutive output slots.
 #include "common.hpp"
 
 namespace tgs {
@@ -40,23 +41,48 @@ digit_counts(const uint32_t* __restrict__ keys, uint64_t count, int shift,
     counts[uint64_t(tid) * nblocks + blockIdx.x] = s;
 }
 
+// Forward declaration: block-wide exclusive scan (defined with the scans).
+template <typename T, int NT>
+__device__ __forceinline__ T block_exclusive_scan(T x, T& total);
+
 __global__ void __launch_bounds__(kSortThreads)
 digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
               uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, uint64_t count,
               int shift, const uint32_t* __restrict__ offsets, uint32_t nblocks) {
     constexpr int W = kSortThreads / 64;
-    __shared__ uint32_t run[kRadixBuckets];       // next output slot per digit
+    __shared__ uint32_t s_key[kSortTile], s_val[kSortTile];   // the tile, ordered by digit
+    __shared__ uint32_t run[kRadixBuckets];       // next local slot per digit
+    __shared__ uint32_t lstart[kRadixBuckets];    // first local slot per digit
+    __shared__ uint32_t gbase[kRadixBuckets];     // first output slot per digit
     __shared__ uint32_t wcnt[W][kRadixBuckets];   // this round's count per wave and digit
     const int tid = threadIdx.x, wave = tid >> 6;
-    run[tid] = offsets[uint64_t(tid) * nblocks + blockIdx.x];
+    const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+    // the tile's keys, all loads in flight at once
+    uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
+        key[it] = idx < count ? keys_in[idx] : 0u;
+        val[it] = idx < count ? vals_in[idx] : 0u;
+    }
+    // this block's count of digit tid (difference of consecutive scanned
+    // counts) -> its first local slot; and its first output slot
+    const uint64_t i = uint64_t(tid) * nblocks + blockIdx.x;
+    const uint32_t off = offsets[i];
+    const uint32_t nxt = i + 1 < uint64_t(kRadixBuckets) * nblocks ? offsets[i + 1] : uint32_t(count);
+    uint32_t total;
+    const uint32_t ls = block_exclusive_scan<uint32_t, kSortThreads>(nxt - off, total);
+    lstart[tid] = ls;
+    run[tid] = ls;
+    gbase[tid] = off;
     for (int w = 0; w < W; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+    // stable local counting sort: 256 keys per round, equal digits inside a
+    // wavefront ranked with ballots, wavefronts ordered through LDS
     for (int it = 0; it < kSortItems; ++it) {
         const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
         const bool valid = idx < count;
-        const uint32_t k = valid ? keys_in[idx] : 0u;
-        const uint32_t v = valid ? vals_in[idx] : 0u;
+        const uint32_t k = key[it];
         const uint32_t d = (k >> shift) & (kRadixBuckets - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -72,8 +98,8 @@ digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__
         if (valid) {
             uint32_t pos = run[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            keys_out[pos] = k;
-            vals_out[pos] = v;
+            s_key[pos] = k;
+            s_val[pos] = val[it];
         }
         __syncthreads();
         uint32_t add = 0;
@@ -83,6 +109,16 @@ digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__
         }
         run[tid] += add;
         __syncthreads();
+    }
+    // out in local order: a digit's keys go to consecutive output slots, so
+    // neighbouring threads write neighbouring addresses
+    const uint32_t nvalid = uint32_t(min(uint64_t(kSortTile), count - base));
+    for (uint32_t j = tid; j < nvalid; j += kSortThreads) {
+        const uint32_t k = s_key[j];
+        const uint32_t d = (k >> shift) & (kRadixBuckets - 1);
+        const uint32_t pos = gbase[d] + (j - lstart[d]);
+        keys_out[pos] = k;
+        vals_out[pos] = s_val[j];
     }
 }
 
