@@ -281,8 +281,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     uint32_t start, end;
     tile_range(rv, tile, start, end);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
-    float X[S::NP], Y[S::NP], Tr[S::NP], p0[S::NP], p1[S::NP], p2[S::NP];
-    float g0[S::NP], g1[S::NP], g2[S::NP], im0[S::NP], im1[S::NP], im2[S::NP];
+    // pg = sum_c dL/dC_c * (colour accumulated so far)_c, gim = sum_c dL/dC_c C_c:
+    // the accumulated colour enters d image / d alpha only through these
+    float X[S::NP], Y[S::NP], Tr[S::NP], pg[S::NP], gim[S::NP];
+    float g0[S::NP], g1[S::NP], g2[S::NP];
     bool done[S::NP];
     bool alive = false;
 #pragma unroll
@@ -294,16 +296,15 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         X[k] = float(grid.stride * i + grid.off_x);
         Y[k] = float(grid.stride * j + grid.off_y);
         Tr[k] = 1.0f;
-        p0[k] = p1[k] = p2[k] = 0.0f;
-        g0[k] = g1[k] = g2[k] = im0[k] = im1[k] = im2[k] = 0.0f;
+        pg[k] = gim[k] = 0.0f;
+        g0[k] = g1[k] = g2[k] = 0.0f;
         if (in) {
             const uint64_t p = uint64_t(j) * grid.w_ds + i;
             g0[k] = rv.dL[p];
             g1[k] = rv.dL[pix + p];
             g2[k] = rv.dL[2 * pix + p];
-            im0[k] = rv.image[p];
-            im1[k] = rv.image[pix + p];
-            im2[k] = rv.image[2 * pix + p];
+            gim[k] = g0[k] * rv.image[p] + g1[k] * rv.image[pix + p] +
+                     g2[k] * rv.image[2 * pix + p];
         }
     }
     // factor of the component this lane owns after wave_sum9
@@ -352,14 +353,12 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             for (int k = 0; k < S::NP; ++k) {
                 const float T0 = Tr[k];
                 const float w = blend[k] ? alpha[k] * T0 : 0.0f;
-                p0[k] = fmaf(b.z, w, p0[k]);
-                p1[k] = fmaf(b.w, w, p1[k]);
-                p2[k] = fmaf(c.x, w, p2[k]);
-                // d image / d alpha = rgb T - (colour behind) / (1 - alpha)
+                const float gcol = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
+                pg[k] = fmaf(gcol, w, pg[k]);
+                // dL/d alpha = sum_c dL/dC_c (rgb_c T - (colour behind)_c / (1 - alpha)),
+                // colour behind = C - accumulated
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[k]);
-                const float dal = g0[k] * fmaf(p0[k] - im0[k], inv, b.z * T0) +
-                                  g1[k] * fmaf(p1[k] - im1[k], inv, b.w * T0) +
-                                  g2[k] * fmaf(p2[k] - im2[k], inv, c.x * T0);
+                const float dal = fmaf(pg[k] - gim[k], inv, gcol * T0);
                 // no gradient through the 0.99 clamp
                 const bool live = blend[k] && !(raw[k] > kAlphaMax);
                 const float dp = live ? alpha[k] * dal : 0.0f;
