@@ -281,9 +281,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     uint32_t start, end;
     tile_range(rv, tile, start, end);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
-    // pg = sum_c dL/dC_c * (colour accumulated so far)_c, gim = sum_c dL/dC_c C_c:
-    // the accumulated colour enters d image / d alpha only through these
-    float X[S::NP], Y[S::NP], Tr[S::NP], pg[S::NP], gim[S::NP];
+    // r_c = colour still to come behind the current entry (image minus the
+    // colour accumulated so far), kept per channel and updated in place
+    float X[S::NP], Y[S::NP], Tr[S::NP], r0[S::NP], r1[S::NP], r2[S::NP];
     float g0[S::NP], g1[S::NP], g2[S::NP];
     bool done[S::NP];
     bool alive = false;
@@ -296,15 +296,16 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         X[k] = float(grid.stride * i + grid.off_x);
         Y[k] = float(grid.stride * j + grid.off_y);
         Tr[k] = 1.0f;
-        pg[k] = gim[k] = 0.0f;
+        r0[k] = r1[k] = r2[k] = 0.0f;
         g0[k] = g1[k] = g2[k] = 0.0f;
         if (in) {
             const uint64_t p = uint64_t(j) * grid.w_ds + i;
             g0[k] = rv.dL[p];
             g1[k] = rv.dL[pix + p];
             g2[k] = rv.dL[2 * pix + p];
-            gim[k] = g0[k] * rv.image[p] + g1[k] * rv.image[pix + p] +
-                     g2[k] * rv.image[2 * pix + p];
+            r0[k] = rv.image[p];
+            r1[k] = rv.image[pix + p];
+            r2[k] = rv.image[2 * pix + p];
         }
     }
     // factor of the component this lane owns after wave_sum9
@@ -353,12 +354,14 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             for (int k = 0; k < S::NP; ++k) {
                 const float T0 = Tr[k];
                 const float w = blend[k] ? alpha[k] * T0 : 0.0f;
+                r0[k] = fmaf(-b.z, w, r0[k]);
+                r1[k] = fmaf(-b.w, w, r1[k]);
+                r2[k] = fmaf(-c.x, w, r2[k]);
+                // dL/d alpha = sum_c dL/dC_c (rgb_c T - (colour behind)_c / (1 - alpha))
                 const float gcol = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
-                pg[k] = fmaf(gcol, w, pg[k]);
-                // dL/d alpha = sum_c dL/dC_c (rgb_c T - (colour behind)_c / (1 - alpha)),
-                // colour behind = C - accumulated
+                const float grest = fmaf(g2[k], r2[k], fmaf(g1[k], r1[k], g0[k] * r0[k]));
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[k]);
-                const float dal = fmaf(pg[k] - gim[k], inv, gcol * T0);
+                const float dal = fmaf(-grest, inv, gcol * T0);
                 // no gradient through the 0.99 clamp
                 const bool live = blend[k] && !(raw[k] > kAlphaMax);
                 const float dp = live ? alpha[k] * dal : 0.0f;
