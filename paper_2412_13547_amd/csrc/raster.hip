@@ -335,7 +335,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             // decisions, exactly as in the forward
             float dx[S::NP], dy[S::NP], t[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
             bool blend[S::NP];
-            bool any = false;
+            uint64_t any = 0;                         // lanes with a blending pixel
             alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
@@ -343,11 +343,11 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                     splat_alpha(a, b, X[k], Y[k], dx[k], dy[k], t[k], G[k], raw[k], alpha[k]) && !done[k];
                 const bool stop = hit && Tr[k] - alpha[k] * Tr[k] < kTMin;
                 blend[k] = hit != stop;
-                any = any || blend[k];
+                any |= __ballot(blend[k]);
                 done[k] = done[k] || stop;
                 alive = alive || !done[k];
             }
-            if (__ballot(any) == 0) return;            // no pixel of the wavefront blends it
+            if (any == 0) return;                     // no pixel of the wavefront blends it
             const float4 c = s_c[e];                  // (b, qa2, qc2, -)
             float gv[kGrad2d];
 #pragma unroll
