@@ -122,7 +122,8 @@ digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__
     }
 }
 
-// ---- exclusive scan: reduce tiles, scan the tile sums, scan each tile -----
+// ---- exclusive scan: reduce tiles, then scan each tile after the sums of the
+// tiles before it ------------------------------------------------------------
 
 template <typename In, typename Out>
 __device__ __forceinline__ Out load_in(const In* in, const uint32_t* gather, uint64_t i) {
@@ -172,21 +173,6 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T& total) {
     return before + incl - x;
 }
 
-// Exclusive scan, in place, of the tile sums (single block).
-template <typename T>
-__global__ void __launch_bounds__(1024) scan_partials(T* __restrict__ p, uint64_t count) {
-    T carry = 0;
-    for (uint64_t base = 0; base < count; base += 1024) {
-        const uint64_t idx = base + threadIdx.x;
-        const T x = idx < count ? p[idx] : T(0);
-        T total;
-        const T ex = block_exclusive_scan<T, 1024>(x, total);
-        if (idx < count) p[idx] = carry + ex;
-        carry += total;
-    }
-    if (threadIdx.x == 0) p[count] = carry;
-}
-
 template <typename In, typename Out>
 __global__ void __launch_bounds__(kScanThreads)
 scan_down(const In* in, const uint32_t* __restrict__ gather, uint64_t count,
@@ -200,15 +186,19 @@ scan_down(const In* in, const uint32_t* __restrict__ gather, uint64_t count,
         v[it] = idx < count ? load_in<In, Out>(in, gather, idx) : Out(0);
         s += v[it];
     }
+    // the sums of the tiles before this one (a few hundred at most in use)
+    Out before = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads) before += partials[b];
+    Out carry;
+    (void)block_exclusive_scan<Out, kScanThreads>(before, carry);
     Out total;
-    Out run = partials[blockIdx.x] + block_exclusive_scan<Out, kScanThreads>(s, total);
+    Out run = carry + block_exclusive_scan<Out, kScanThreads>(s, total);
     for (int it = 0; it < kScanItems; ++it) {
         const uint64_t idx = base + it;
         if (idx < count) out[idx] = run;
         run += v[it];
     }
-    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
-        out[count] = partials[gridDim.x];
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = carry + total;
 }
 
 template <typename In, typename Out>
@@ -217,7 +207,6 @@ hipError_t exclusive_scan(const In* in, const uint32_t* gather, Out* out, uint64
     const uint64_t nb = (count + kScanTile - 1) / kScanTile;
     if (nb == 0) return hipSuccess;
     scan_reduce<In, Out><<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, gather, count, partials);
-    scan_partials<Out><<<1, 1024, 0, s>>>(partials, nb);
     scan_down<In, Out><<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, gather, count, partials,
                                                                          out, write_total);
     return hipGetLastError();
