@@ -296,7 +296,10 @@ tgs_status tgs_batch_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, in
 
 /* Stage (b) for every view (as tgs_bin_sort, without the readback): the
  * pair count stays on the device and a view whose pairs exceed its capacity
- * gets empty ranges.  Sets states[v].pair_count to TGS_PAIR_COUNT_PENDING. */
+ * gets empty ranges.  Sets states[v].pair_count to TGS_PAIR_COUNT_PENDING.
+ * The views are binned concurrently on streams the context owns, forked from
+ * and joined back into `stream` (under graph capture: parallel branches of
+ * the graph); calls of this function on one context must not overlap. */
 tgs_status tgs_batch_bin_sort(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
                               const tgs_camera* cams, const tgs_dilation* dils,
                               const tgs_options* opt, tgs_state* states, void* stream);

@@ -3,6 +3,7 @@
 // error path can be exercised on a machine without a GPU.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,14 +14,20 @@
 
 #include "common.hpp"
 
+namespace {
+constexpr size_t kPinnedBytes = 4 * (tgs::kMaxCols * 4 + 8);   // row starts of the tallest grid
+// Streams beside the caller's on which the batched binning runs views
+// concurrently (forked from and joined into the caller's stream).
+constexpr int kAuxStreams = 3;
+}
+
 struct tgs_context {
     int device;
     uint64_t* pinned;   // host-pinned readback of the tile-row starts
+    hipStream_t aux[kAuxStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kAuxStreams];
 };
-
-namespace {
-constexpr size_t kPinnedBytes = 4 * (tgs::kMaxCols * 4 + 8);   // row starts of the tallest grid
-}
 
 namespace {
 
@@ -369,13 +376,25 @@ tgs_status tgs_create(int device, tgs_context** out) {
         return fail(TGS_ERR_NO_DEVICE, "device %d not available (%d devices)", device, count);
     TGS_HIP(hipSetDevice(device));
     TGS_HIP(tgs::prepare_binning_kernels());
-    auto* ctx = new (std::nothrow) tgs_context{device, nullptr};
+    auto* ctx = new (std::nothrow) tgs_context{};
     if (!ctx) return fail(TGS_ERR_HIP, "out of host memory");
+    ctx->device = device;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kPinnedBytes,
                                  hipHostMallocDefault);
+    const char* what = "hipHostMalloc";
+    // default-priority streams, not synchronising with the null stream
+    for (int a = 0; a < kAuxStreams && e == hipSuccess; ++a) {
+        what = "hipStreamCreateWithFlags";
+        e = hipStreamCreateWithFlags(&ctx->aux[a], hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            what = "hipEventCreateWithFlags";
+            e = hipEventCreateWithFlags(&ctx->join[a], hipEventDisableTiming);
+        }
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
     if (e != hipSuccess) {
-        delete ctx;
-        return hip_fail(e, "hipHostMalloc");
+        tgs_destroy(ctx);
+        return hip_fail(e, what);
     }
     *out = ctx;
     return TGS_OK;
@@ -383,6 +402,11 @@ tgs_status tgs_create(int device, tgs_context** out) {
 
 void tgs_destroy(tgs_context* ctx) {
     if (!ctx) return;
+    for (int a = 0; a < kAuxStreams; ++a) {
+        if (ctx->aux[a]) (void)hipStreamDestroy(ctx->aux[a]);
+        if (ctx->join[a]) (void)hipEventDestroy(ctx->join[a]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
@@ -678,20 +702,56 @@ tgs_status tgs_batch_bin_sort(tgs_context* ctx, const tgs_gaussians* g, int32_t 
     TGS_CHECK(check_views(g->n, views, cams, dils, opt, states, grids, Ls));
     TGS_CHECK(use_device(ctx));
     auto strm = static_cast<hipStream_t>(stream);
-    for (int v = 0; v < views; ++v) {
+    // the views' binning chains are independent (each view has its own
+    // workspace): spread them over the caller's stream and the auxiliary
+    // streams, largest first onto the least loaded chain, forked from and
+    // joined back into the caller's stream (a captured graph gets parallel
+    // branches)
+    const int chains = views > 1 ? std::min(views, kAuxStreams + 1) : 1;
+    hipStream_t chain_stream[kAuxStreams + 1] = {strm};
+    for (int a = 0; a + 1 < chains; ++a) chain_stream[a + 1] = ctx->aux[a];
+    int chain_of[TGS_MAX_VIEWS];
+    {
+        uint64_t load[kAuxStreams + 1] = {};
+        int idx[TGS_MAX_VIEWS];
+        for (int v = 0; v < views; ++v) idx[v] = v;
+        std::sort(idx, idx + views, [&](int a, int b) {
+            return states[a].pair_capacity > states[b].pair_capacity;
+        });
+        for (int k = 0; k < views; ++k) {
+            int best = 0;
+            for (int c = 1; c < chains; ++c)
+                if (load[c] < load[best]) best = c;
+            chain_of[idx[k]] = best;
+            load[best] += states[idx[k]].pair_capacity + uint64_t(g->n);
+        }
+    }
+    if (chains > 1) {
+        TGS_HIP(hipEventRecord(ctx->fork, strm));
+        for (int c = 1; c < chains; ++c) TGS_HIP(hipStreamWaitEvent(chain_stream[c], ctx->fork, 0));
+    }
+    tgs_status status = TGS_OK;
+    for (int v = 0; v < views && status == TGS_OK; ++v) {
         tgs_state& st = states[v];
         auto* ws = static_cast<uint8_t*>(st.workspace);
         const uint32_t cap = uint32_t(st.pair_capacity);
         int dres = 0;
         const uint32_t* order = nullptr;
         const uint64_t max_slices = tgs::bin_max_slices(cap, grids[v].gy);
-        TGS_CHECK(enqueue_counts(ws, Ls[v], grids[v], g->n, max_slices, strm, &dres, &order));
-        TGS_CHECK(enqueue_emit(ws, Ls[v], grids[v], g->n, order, max_slices, cap, strm));
+        const hipStream_t vs = chain_stream[chain_of[v]];
+        status = enqueue_counts(ws, Ls[v], grids[v], g->n, max_slices, vs, &dres, &order);
+        if (status == TGS_OK)
+            status = enqueue_emit(ws, Ls[v], grids[v], g->n, order, max_slices, cap, vs);
         publish_offsets(&st, Ls[v], grids[v], dres);
         st.pair_count = TGS_PAIR_COUNT_PENDING;
         st.key_bits = uint32_t(key_bits_for(grids[v].num_tiles()));
     }
-    return TGS_OK;
+    // join every chain, also after an error, so no stream is left forked
+    for (int c = 1; c < chains; ++c) {
+        TGS_HIP(hipEventRecord(ctx->join[c - 1], chain_stream[c]));
+        TGS_HIP(hipStreamWaitEvent(strm, ctx->join[c - 1], 0));
+    }
+    return status;
 }
 
 tgs_status tgs_batch_raster_fwd(tgs_context* ctx, int64_t n, int32_t views, const tgs_camera* cams,
