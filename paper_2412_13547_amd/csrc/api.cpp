@@ -540,9 +540,10 @@ tgs_status tgs_l1_grad(tgs_context* ctx, const tgs_camera* cam, const tgs_dilati
     if (s != TGS_OK) return s;
     if (!image || !target || !dL_dimage) return fail(TGS_ERR_INVALID_ARG, "a buffer is NULL");
     if ((s = use_device(ctx)) != TGS_OK) return s;
-    const tgs::Grid grid = tgs::make_grid(*cam, *dil, 16);
-    TGS_HIP(tgs::launch_l1_grad(grid, image, target, dL_dimage, loss,
-                                static_cast<hipStream_t>(stream)));
+    tgs::L1Views lt{};
+    lt.count = 1;
+    lt.v[0] = tgs::L1View{tgs::make_grid(*cam, *dil, 16), image, target, dL_dimage, loss};
+    TGS_HIP(tgs::launch_l1_grad(lt, static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
 
@@ -807,11 +808,12 @@ tgs_status tgs_batch_l1_grad(tgs_context* ctx, int32_t views, const tgs_camera* 
     }
     TGS_CHECK(use_device(ctx));
     auto strm = static_cast<hipStream_t>(stream);
-    for (int v = 0; v < views; ++v) {
-        const tgs::Grid grid = tgs::make_grid(cams[v], dils[v], 16);
-        TGS_HIP(tgs::launch_l1_grad(grid, io[v].image, io[v].target, io[v].dL_dimage,
-                                    loss ? loss + v : nullptr, strm));
-    }
+    tgs::L1Views lt{};
+    lt.count = views;
+    for (int v = 0; v < views; ++v)
+        lt.v[v] = tgs::L1View{tgs::make_grid(cams[v], dils[v], 16), io[v].image, io[v].target,
+                              io[v].dL_dimage, loss ? loss + v : nullptr};
+    TGS_HIP(tgs::launch_l1_grad(lt, strm));
     return TGS_OK;
 }
 

@@ -176,8 +176,21 @@ hipError_t launch_raster_fwd(int tile, int ppt, int lds_batch, const RasterViews
                              hipStream_t s);
 hipError_t launch_raster_bwd(int tile, int ppt, int lds_batch, const RasterViews& views,
                              hipStream_t s);
-hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,
-                          float* dL_dimage, double* loss, hipStream_t s);
+// L1 loss and gradient of a table of views in one launch (loss may be null).
+struct L1View {
+    Grid grid;
+    const float* image;
+    const float* target;
+    float* dL;
+    double* loss;
+};
+struct L1Views {
+    int count;
+    uint32_t first_block[kMaxViews + 1];   // filled by launch_l1_grad
+    L1View v[kMaxViews];
+};
+static_assert(sizeof(L1Views) <= 3584, "L1 view table too large for kernel arguments");
+hipError_t launch_l1_grad(L1Views& views, hipStream_t s);
 
 // Fused Adam (optim.hip): a table of parameter groups, the step counter and
 // bias corrections in a small device buffer.

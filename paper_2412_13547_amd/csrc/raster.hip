@@ -408,32 +408,37 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     }
 }
 
-// L1 loss of Eq. 1-2 over the dilated image and its gradient.  Blocks walk
-// rows of the strided image (the rows of a pixel phase), so the image and
-// dL accesses are contiguous; one double atomic per block adds the block's
-// share of the loss (a bounded number of atomics on one address).
-constexpr unsigned kL1MaxBlocks = 2048;
+// L1 loss of Eq. 1-2 over the dilated image and its gradient, for a table
+// of views in one launch.  A view's blocks walk rows of its strided image
+// (the rows of a pixel phase), so the image and dL accesses are contiguous;
+// one double atomic per block adds the block's share of the view's loss (a
+// bounded number of atomics on one address).
+constexpr uint32_t kL1MaxBlocks = 2048;
 
-__global__ void __launch_bounds__(256)
-l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restrict__ target,
-               float* __restrict__ dL, double* __restrict__ loss) {
+__global__ void __launch_bounds__(256) l1_grad_kernel(L1Views vt) {
     __shared__ double wsum[4];
+    int v = 0;
+    while (v + 1 < vt.count && blockIdx.x >= vt.first_block[v + 1]) ++v;   // block-uniform
+    const L1View& lv = vt.v[v];
+    const Grid& grid = lv.grid;
+    const uint32_t lb = blockIdx.x - vt.first_block[v];
+    const uint32_t nb = vt.first_block[v + 1] - vt.first_block[v];
     const uint32_t w = uint32_t(grid.w_ds), h = uint32_t(grid.h_ds);
     const uint64_t pix = uint64_t(w) * h;
     const uint64_t full = uint64_t(grid.width) * grid.height;
     const float inv = 1.0f / float(3 * pix);
     double s = 0.0;
-    for (uint32_t j = blockIdx.x; j < h; j += gridDim.x) {
+    for (uint32_t j = lb; j < h; j += nb) {
         const uint64_t Y = uint64_t(grid.stride) * j + grid.off_y;
-        const float* trow = target + Y * grid.width + grid.off_x;
+        const float* trow = lv.target + Y * grid.width + grid.off_x;
         for (uint32_t i = threadIdx.x; i < w; i += blockDim.x) {
             const uint64_t p = uint64_t(j) * w + i;
             const uint64_t X = uint64_t(grid.stride) * i;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float diff = image[c * pix + p] - trow[c * full + X];
+                const float diff = lv.image[c * pix + p] - trow[c * full + X];
                 const float sg = diff > 0.0f ? 1.0f : (diff < 0.0f ? -1.0f : 0.0f);
-                dL[c * pix + p] = sg * inv;
+                lv.dL[c * pix + p] = sg * inv;
                 s += fabs(double(diff));
             }
         }
@@ -441,9 +446,16 @@ l1_grad_kernel(Grid grid, const float* __restrict__ image, const float* __restri
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0 && loss) {
-        atomicAdd(loss, (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / double(3 * pix));
+    if (threadIdx.x == 0 && lv.loss) {
+        atomicAdd(lv.loss, (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / double(3 * pix));
     }
+}
+
+// The views' losses to zero before the atomics (a fill kernel, so the step
+// stays capturable without memset nodes).
+__global__ void l1_zero_kernel(L1Views vt) {
+    const int v = int(threadIdx.x);
+    if (v < vt.count && vt.v[v].loss) *vt.v[v].loss = 0.0;
 }
 
 bool wants_counts(const RasterViews& vt) {
@@ -495,16 +507,18 @@ hipError_t launch_raster_bwd(int tile, int ppt, int batch, const RasterViews& vt
     return launch_raster(false, tile, ppt, batch, vt, s);
 }
 
-hipError_t launch_l1_grad(const Grid& grid, const float* image, const float* target,
-                          float* dL_dimage, double* loss, hipStream_t s) {
-    const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
-    if (loss) {
-        hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(loss), 0u, 2, s);
-        if (e != hipSuccess) return e;
+hipError_t launch_l1_grad(L1Views& vt, hipStream_t s) {
+    uint32_t blocks = 0;
+    for (int k = 0; k < vt.count; ++k) {
+        vt.first_block[k] = blocks;
+        const Grid& g = vt.v[k].grid;
+        const uint64_t pix = uint64_t(g.w_ds) * g.h_ds;
+        blocks += pix == 0 ? 0u : uint32_t(std::min<uint64_t>(uint64_t(g.h_ds), kL1MaxBlocks));
     }
-    if (pix == 0) return hipSuccess;
-    const unsigned blocks = unsigned(std::min<uint64_t>(uint64_t(grid.h_ds), kL1MaxBlocks));
-    l1_grad_kernel<<<dim3(blocks), dim3(256), 0, s>>>(grid, image, target, dL_dimage, loss);
+    vt.first_block[vt.count] = blocks;
+    if (vt.count == 0) return hipSuccess;
+    l1_zero_kernel<<<1, 64, 0, s>>>(vt);
+    if (blocks > 0) l1_grad_kernel<<<dim3(blocks), dim3(256), 0, s>>>(vt);
     return hipGetLastError();
 }
 
