@@ -42,7 +42,6 @@ constexpr int kEntryBatch = 2;                             // 64-entry batches l
 constexpr int kScatterWaves = 8;                           // wavefronts per scatter block
 constexpr int kHistThreads = 256;
 constexpr int kColBatch = 16;                              // slices loaded together in col_scan
-constexpr int kHistCols = kMaxCols / kHistThreads;
 
 __device__ __forceinline__ int wave_min(int x) {
     for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
@@ -275,47 +274,57 @@ __device__ __forceinline__ bool clip_entry(uint32_t pp, uint32_t xpack, uint32_t
 
 // hist[b][tx]: pairs of slice b in column tx, from the slice's entries: +1 at
 // the first column of each entry's part, -1 after its last, then a prefix.
+// One wavefront per slice (no block barriers), kHistThreads / 64 slices per
+// block.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __global__ void __launch_bounds__(kHistThreads)
 slice_hist_kernel(const uint32_t* __restrict__ ent_pp, const uint32_t* __restrict__ ent_x,
                   const uint32_t* __restrict__ first_slice, const uint32_t* __restrict__ row_start,
                   const uint4* __restrict__ slice_desc, const uint32_t* __restrict__ slice_e1,
-                  Grid grid, uint32_t capacity, uint32_t* __restrict__ hist) {
-    __shared__ int32_t d[kMaxCols + 1];
-    __shared__ uint32_t s_w[kHistThreads / 64];
+                  Grid grid, uint32_t slices, uint32_t capacity, uint32_t* __restrict__ hist) {
+    constexpr int W = kHistThreads / 64;
+    __shared__ int32_t d_all[W][kMaxCols + 1];
+    const int wv = int(threadIdx.x >> 6), lane = __lane_id();
+    const uint32_t b = blockIdx.x * W + uint32_t(wv);
     Slice s;
-    if (!find_slice(blockIdx.x, first_slice, row_start, slice_desc, slice_e1, grid.gy, capacity,
-                    s))
-        return;                                         // block-uniform
-    const int gx = grid.gx, tid = threadIdx.x;
-    for (int c = tid; c <= gx; c += kHistThreads) d[c] = 0;
-    __syncthreads();
-    for (uint32_t e = s.e0 + tid; e < s.e1; e += kHistThreads) {
+    if (b >= slices ||                                  // past the launched slices
+        !find_slice(b, first_slice, row_start, slice_desc, slice_e1, grid.gy, capacity, s))
+        return;                                         // wavefront-uniform
+    const int gx = grid.gx;
+    int32_t* d = d_all[wv];
+    for (int c = lane; c <= gx; c += 64) d[c] = 0;
+    wave_sync_lds();
+    for (uint32_t e = s.e0 + uint32_t(lane); e < s.e1; e += 64) {
         uint32_t c0, c1, p0;
         if (clip_entry(ent_pp[e], ent_x[e], s.start, s.end, c0, c1, p0)) {
             atomicAdd(&d[c0], 1);
             atomicSub(&d[c1], 1);
         }
     }
-    __syncthreads();
-    // prefix over the columns, kHistCols per thread
-    constexpr int CPT = kHistCols;
-    int32_t v[CPT];
+    wave_sync_lds();
+    // prefix over the columns: each lane a chunk of consecutive columns
+    const int cpl = (gx + 63) / 64;
     int32_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int c = CPT * tid + j;
-        v[j] = c < gx ? d[c] : 0;
-        mine += v[j];
+    for (int j = 0; j < cpl; ++j) {
+        const int c = lane * cpl + j;
+        if (c < gx) mine += d[c];
     }
     uint32_t all;
-    int32_t run = int32_t(block_exclusive_sum<kHistThreads>(uint32_t(mine), s_w, all));
-    const uint64_t base = uint64_t(blockIdx.x) * gx;
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int c = CPT * tid + j;
-        run += v[j];
-        if (c < gx) hist[base + c] = uint32_t(run);
+    int32_t run = int32_t(wave_exclusive_sum(uint32_t(mine), all));
+    for (int j = 0; j < cpl; ++j) {
+        const int c = lane * cpl + j;
+        if (c < gx) {
+            run += d[c];
+            d[c] = run;
+        }
     }
+    wave_sync_lds();
+    const uint64_t base = uint64_t(b) * gx;
+    for (int c = lane; c < gx; c += 64) hist[base + c] = uint32_t(d[c]);
 }
 
 // One block per tile row: turns hist[b][tx] into the first output slot of
@@ -619,8 +628,9 @@ hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint6
     const uint32_t* e1 = u32(L.slice_e1);
     uint32_t* hist = u32(L.col_hist);
     if (slices > 0) {
-        slice_hist_kernel<<<dim3(unsigned(slices)), dim3(kHistThreads), 0, s>>>(
-            u32(L.ent_pp), u32(L.ent_x), fs, rs, sd, e1, grid, capacity, hist);
+        const uint64_t hist_blocks = (slices + kHistThreads / 64 - 1) / (kHistThreads / 64);
+        slice_hist_kernel<<<dim3(unsigned(hist_blocks)), dim3(kHistThreads), 0, s>>>(
+            u32(L.ent_pp), u32(L.ent_x), fs, rs, sd, e1, grid, uint32_t(slices), capacity, hist);
     }
     col_scan_kernel<<<dim3(unsigned(grid.gy)), dim3(1024), 0, s>>>(hist, fs, rs, grid, capacity,
                                                                   u32(L.ranges));
