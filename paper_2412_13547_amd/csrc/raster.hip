@@ -45,17 +45,32 @@ __device__ __forceinline__ void stage_conic(const float4 r0, const float4 r1, fl
 // computed either way (branch-free callers select on the result).  Forward
 // and backward evaluate exactly these operations (explicit FMAs, no
 // contraction elsewhere), so they take bit-identical decisions.
-__device__ __forceinline__ bool splat_alpha(const float4 ga, const float4 gb, float X, float Y,
-                                            float& dx, float& dy, float& t, float& G,
-                                            float& raw, float& alpha) {
+// The two halves: the exponent, then the test on it.
+__device__ __forceinline__ float splat_exponent(const float4 ga, const float4 gb, float X,
+                                                float Y, float& dx, float& dy, float& t) {
     dx = ga.x - X;
     dy = ga.y - Y;
     t = ga.w * dy;
-    const float p2 = fmaf(dx, fmaf(ga.z, dx, t), (gb.x * dy) * dy);
+    return fmaf(dx, fmaf(ga.z, dx, t), (gb.x * dy) * dy);
+}
+
+__device__ __forceinline__ bool splat_test(const float4 gb, float p2, float& G, float& raw,
+                                           float& alpha) {
     G = __builtin_amdgcn_exp2f(p2);
     raw = gb.y * G;
     alpha = fminf(kAlphaMax, raw);
     return p2 <= 0.0f && raw >= kAlphaMin;
+}
+
+// Exponent below which o 2^p2 < 1/255 for certain: log2(1/255 / o) less a
+// margin (1/64 in log2, i.e. 1.1 % of alpha) far above the rounding of the
+// exponential, the product and this logarithm.  An entry whose exponent is
+// below it at every live pixel of a wavefront is skipped by the whole
+// wavefront: it would be skipped by each pixel anyway (o <= 0 gives NaN or
+// +inf here, and no exponent passes).
+constexpr float kSkipMargin = 1.0f / 64.0f;
+__device__ __forceinline__ float skip_threshold(float o) {
+    return log2f(kAlphaMin / o) - kSkipMargin;
 }
 
 // Launch shape (the work split): a T x T tile is covered by (T/PX) x (T/PY)
@@ -154,7 +169,7 @@ template <int T, int PPT, int BATCH, bool COUNTS>
 __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterViews vt) {
     using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH];
-    __shared__ float s_c[BATCH];
+    __shared__ float2 s_c[BATCH];                                // (blue, skip threshold)
     int v;
     int64_t tile;
     if (!locate(vt, blockIdx.x, v, tile)) return;                // block-uniform
@@ -188,19 +203,30 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
         for (int q = tid; q < cnt; q += S::NT) {
             const uint32_t id = rv.vals[base + q];
             const float4* r = rv.rec + 3 * uint64_t(id);
-            stage_conic(r[0], r[1], s_a[q], s_b[q]);
-            s_c[q] = r[2].x;
+            const float4 r1 = r[1];
+            stage_conic(r[0], r1, s_a[q], s_b[q]);
+            s_c[q] = make_float2(r[2].x, skip_threshold(r1.y));
         }
         __syncthreads();
-        // branch-free per entry: a skipped entry adds exactly 0 and leaves T
+        // branch-free per entry: a skipped entry adds exactly 0 and leaves T;
+        // an entry no live pixel of the wavefront can take is skipped whole
         auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
-            const float bb = s_c[e];
+            const float2 cc = s_c[e];
+            const float bb = cc.x;
+            float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP];
+            bool cand = false;
+#pragma unroll
+            for (int k = 0; k < S::NP; ++k) {
+                p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
+                cand = cand || (p2[k] >= cc.y && !done[k]);
+            }
+            if (__ballot(cand) == 0) return;          // T, colours and stops unchanged
             alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                float dx, dy, t, G, raw, alpha;
-                const bool hit = splat_alpha(a, b, X[k], Y[k], dx, dy, t, G, raw, alpha) && !done[k];
+                float G, raw, alpha;
+                const bool hit = splat_test(b, p2[k], G, raw, alpha) && !done[k];
                 const float w0 = alpha * Tr[k];
                 // T after this entry below the floor: the pixel stops here;
                 // otherwise it blends (one comparison: stop implies hit)
@@ -324,7 +350,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             stage_conic(r[0], r[1], ga, gb);
             s_a[q] = ga;
             s_b[q] = gb;
-            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, 0.0f);
+            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, skip_threshold(r[1].y));
             s_id[q] = id;
         }
         if constexpr (kBlockSum)
@@ -332,15 +358,22 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         __syncthreads();
         auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
-            // decisions, exactly as in the forward
-            float dx[S::NP], dy[S::NP], t[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
+            const float4 c = s_c[e];                  // (b, qa2, qc2, skip threshold)
+            // decisions, exactly as in the forward (same wavefront skip)
+            float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
             bool blend[S::NP];
+            bool cand = false;
+#pragma unroll
+            for (int k = 0; k < S::NP; ++k) {
+                p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
+                cand = cand || (p2[k] >= c.w && !done[k]);
+            }
+            if (__ballot(cand) == 0) return;
             uint64_t any = 0;                         // lanes with a blending pixel
             alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const bool hit =
-                    splat_alpha(a, b, X[k], Y[k], dx[k], dy[k], t[k], G[k], raw[k], alpha[k]) && !done[k];
+                const bool hit = splat_test(b, p2[k], G[k], raw[k], alpha[k]) && !done[k];
                 const bool stop = hit && Tr[k] - alpha[k] * Tr[k] < kTMin;
                 blend[k] = hit != stop;
                 any |= __ballot(blend[k]);
@@ -348,7 +381,6 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                 alive = alive || !done[k];
             }
             if (any == 0) return;                     // no pixel of the wavefront blends it
-            const float4 c = s_c[e];                  // (b, qa2, qc2, -)
             float gv[kGrad2d];
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
