@@ -40,17 +40,30 @@ sys.path.insert(0, ROOT)
 PEAK_HBM = 8.0e12                    # B/s, MI355X HBM3E
 PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 # The least FP32 arithmetic the method needs per list entry and pixel (lane
-# operations, an FMA counts 1; per-splat work such as scaling the conic is
-# not counted):
+# operations, an FMA counts 1; per-splat work such as scaling the conic or
+# the per-splat skip threshold is not counted):
 #   examined entry (forward up to the stop, backward up to the last blended
-#   entry): offset 2, quadratic form 5, exp 1, opacity product 1, clamp 1,
-#   the two skip tests 2, alpha T 1, T after the entry 1, stop test 1   -> 15
+#   entry): offset 2, quadratic form 5, test of the exponent against the
+#   splat's threshold 1                                                  -> 8
+#   hit (alpha >= 1/255: the entry blends, or stops the pixel): exp 1,
+#   opacity product 1, clamp 1, exact skip test 1, alpha T 1, T after the
+#   entry 1, stop test 1                                                 -> 7
 #   blended entry, forward: colour accumulation 3                        -> 3
 #   blended entry, backward: weight 1, running colour 3, d/drgb 3,
 #   1 - alpha and its reciprocal 2, d/dalpha through the colour behind 12,
 #   clamp test, d/dpower, d/do 3, d/d(u, v, A, B, C) 9, the sums of the
 #   nine values over pixels 9, T update 1                                -> 43
-OPS_EXAMINE, OPS_BLEND_FWD, OPS_BLEND_BWD = 15, 3, 43
+# Hits are counted as blends plus one per rendered pixel (its stop, an upper
+# bound) in the forward and as blends in the backward.
+OPS_EXAMINE, OPS_HIT, OPS_BLEND_FWD, OPS_BLEND_BWD = 8, 7, 3, 43
+
+
+def fwd_ops(evals, blended, pixels):
+    return OPS_EXAMINE * evals + OPS_HIT * (blended + pixels) + OPS_BLEND_FWD * blended
+
+
+def bwd_ops(evals, blended):
+    return OPS_EXAMINE * evals + (OPS_HIT + OPS_BLEND_BWD) * blended
 STAGES = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd", "preprocess_bwd")
 
 
@@ -267,6 +280,7 @@ def run_batched(args, api, torch, np):
     pc = b.pair_counts()
     s64 = lambda ts: int(sum(int(t.sum(dtype=torch.int64)) for t in ts))
     fwd_e, bwd_e, blended = s64(b.n_eval), s64(b.last_contrib), s64(b.n_blend)
+    batch_pixels = sum(int(vw.image_shape[1]) * int(vw.image_shape[2]) for vw in b.views)
     res.update(pairs=int(sum(pc)), fwd_evals=fwd_e, bwd_evals=bwd_e, blended=blended)
     del b
     torch.cuda.empty_cache()
@@ -340,9 +354,8 @@ def run_batched(args, api, torch, np):
     res["speedup_vs_per_view_calls"] = res["ms_per_view_calls"] / res["ms_per_step"]
     res["speedup_graph_vs_eager"] = res["ms_eager"] / res["ms_per_step"]
     st = res["stages_ms"]
-    res["roofline_raster_bwd"] = dict(**_alu(OPS_EXAMINE * bwd_e + OPS_BLEND_BWD * blended,
-                                             st["raster_bwd"]))
-    res["roofline_raster_fwd"] = dict(**_alu(OPS_EXAMINE * fwd_e + OPS_BLEND_FWD * blended,
+    res["roofline_raster_bwd"] = dict(**_alu(bwd_ops(bwd_e, blended), st["raster_bwd"]))
+    res["roofline_raster_fwd"] = dict(**_alu(fwd_ops(fwd_e, blended, batch_pixels),
                                              st["raster_fwd"]))
     return res
 
@@ -458,6 +471,7 @@ def main():
     fwd_evals = float(np.mean([c[0] for c in cnt]))
     bwd_evals = float(np.mean([c[1] for c in cnt]))
     blended = float(np.mean([c[2] for c in cnt]))
+    dil_pixels = int(dil.view.image_shape[1]) * int(dil.view.image_shape[2])
     pairs = float(np.mean([c[3] for c in cnt]))
     log(f"# dilated: {ms:.3f} ms/step, pairs {pairs:.0f}, stages {stage}")
 
@@ -478,11 +492,11 @@ def main():
     alu = _alu
     n = sc.n
     roof_bwd = dict(kernel="raster_bwd_kernel<16,1,256>",
-                    **alu(OPS_EXAMINE * bwd_evals + OPS_BLEND_BWD * blended, stage["raster_bwd"]),
+                    **alu(bwd_ops(bwd_evals, blended), stage["raster_bwd"]),
                     traffic=measured_traffic("paper_2412_13547_amd/csrc/raster.hip",
                                              "profiles/raster_bwd_dilated4k_traffic.txt"))
     roof_fwd = dict(kernel="raster_fwd_kernel<16,1,256,false>",
-                    **alu(OPS_EXAMINE * fwd_evals + OPS_BLEND_FWD * blended, stage["raster_fwd"]))
+                    **alu(fwd_ops(fwd_evals, blended, dil_pixels), stage["raster_fwd"]))
     # the least the stage must move: the pair list (4 B per pair) and, per
     # Gaussian, its rectangle inputs (u, v, radius: 12 B) and depth key and
     # index written and read by the depth sort (16 B)
