@@ -89,6 +89,67 @@ struct Shape {
     __device__ static int py(int tid) { return ((tid >> 6) / (TX / 8) * 8 + ((tid >> 3) & 7)) * PY; }
 };
 
+// The pixel rectangles of a tile's wavefronts, in full-resolution coordinates
+// of their pixel centres (pixels past the image edge included): wavefront w
+// covers x in [x0 + w_x step, x0 + w_x step + span], w_x = w mod (TX / 8),
+// and likewise in y.
+template <class S>
+struct WaveRects {
+    static constexpr int NW = S::NT / 64, WX = S::TX / 8;
+    float x0, y0, stepx, stepy, spanx, spany;
+    __device__ void init(const Grid& g, int tx, int ty, int T) {
+        auto u = [](float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); };
+        x0 = u(float(g.stride * tx * T + g.off_x));
+        y0 = u(float(g.stride * ty * T + g.off_y));
+        stepx = float(g.stride * 8 * S::PX);
+        stepy = float(g.stride * 8 * S::PY);
+        spanx = float(g.stride * (8 * S::PX - 1));
+        spany = float(g.stride * (8 * S::PY - 1));
+    }
+};
+
+// Bit w set when the splat's exponent may reach thr somewhere on wavefront
+// w's rectangle: the maximum of the (negative definite) quadratic form over
+// the rectangle -- 0 if it holds the centre, else the largest of the four
+// edge maxima -- plus a margin (1/32 in log2 and a relative bound on the
+// rounding of the form's terms) against thr.  A clear bit is a promise that
+// no pixel of the wavefront passes the per-pixel test, so the wavefront
+// skips the entry without evaluating it; a form that is not negative
+// definite sets every bit.
+template <class S>
+__device__ __forceinline__ uint32_t wave_mask(const float4 ga, float qc, float thr,
+                                              const WaveRects<S>& wr) {
+    constexpr int NW = WaveRects<S>::NW;
+    constexpr uint32_t kAll = NW >= 32 ? 0xFFFFFFFFu : (1u << NW) - 1u;
+    const float u = ga.x, v = ga.y, qa = ga.z, qb = ga.w;
+    if (!(qa < 0.0f && qc < 0.0f && 4.0f * qa * qc > qb * qb)) return kAll;
+    const float ka = -qb / (2.0f * qa);      // maximising dx on a line dy = e: ka e
+    const float kc = -qb / (2.0f * qc);      // maximising dy on a line dx = d: kc d
+    auto f = [&](float d, float e) { return fmaf(d, fmaf(qa, d, qb * e), (qc * e) * e); };
+    uint32_t mask = 0;
+#pragma unroll 1
+    for (int w = 0; w < NW; ++w) {
+        const float xa = wr.x0 + float(w % WaveRects<S>::WX) * wr.stepx;
+        const float ya = wr.y0 + float(w / WaveRects<S>::WX) * wr.stepy;
+        const float d0 = u - (xa + wr.spanx), d1 = u - xa;       // d0 <= d1
+        const float e0 = v - (ya + wr.spany), e1 = v - ya;
+        float m;
+        if (d0 <= 0.0f && d1 >= 0.0f && e0 <= 0.0f && e1 >= 0.0f) {
+            m = 0.0f;
+        } else {
+            m = f(d0, fminf(fmaxf(kc * d0, e0), e1));
+            m = fmaxf(m, f(d1, fminf(fmaxf(kc * d1, e0), e1)));
+            m = fmaxf(m, f(fminf(fmaxf(ka * e0, d0), d1), e0));
+            m = fmaxf(m, f(fminf(fmaxf(ka * e1, d0), d1), e1));
+            const float dm = fmaxf(-d0, d1), em = fmaxf(-e0, e1);
+            const float mag = fmaf(-qa * dm, dm, fmaf(fabsf(qb) * dm, em, (-qc * em) * em));
+            m += 1.0f / 32.0f + 4e-6f * mag;
+        }
+        if (m >= thr) mask |= 1u << w;
+    }
+    return mask;
+}
+
 // Which view and tile workgroup b works on: the views' workgroups are laid
 // out one view after the other, tiles row-major within a view.
 __device__ __forceinline__ bool locate(const RasterViews& vt, uint32_t b, int& v, int64_t& tile) {
@@ -170,6 +231,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH];
     __shared__ float2 s_c[BATCH];                                // (blue, skip threshold)
+    __shared__ uint32_t s_m[BATCH];                              // wavefronts that look at it
     int v;
     int64_t tile;
     if (!locate(vt, blockIdx.x, v, tile)) return;                // block-uniform
@@ -180,6 +242,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     const int i0 = tx * T + S::px(tid), j0 = ty * T + S::py(tid);
     uint32_t start, end;
     tile_range(rv, tile, start, end);
+    WaveRects<S> wr;
+    wr.init(grid, tx, ty, T);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
     uint32_t last[S::NP], neval[S::NP], nblend[S::NP];
     bool done[S::NP];
@@ -204,13 +269,19 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
             const uint32_t id = rv.vals[base + q];
             const float4* r = rv.rec + 3 * uint64_t(id);
             const float4 r1 = r[1];
-            stage_conic(r[0], r1, s_a[q], s_b[q]);
-            s_c[q] = make_float2(r[2].x, skip_threshold(r1.y));
+            float4 ga, gb;
+            stage_conic(r[0], r1, ga, gb);
+            const float thr = skip_threshold(r1.y);
+            s_a[q] = ga;
+            s_b[q] = gb;
+            s_c[q] = make_float2(r[2].x, thr);
+            s_m[q] = wave_mask<S>(ga, gb.x, thr, wr);
         }
         __syncthreads();
         // branch-free per entry: a skipped entry adds exactly 0 and leaves T;
         // an entry no live pixel of the wavefront can take is skipped whole
         auto entry = [&](int e) {
+            if (!((s_m[e] >> wave) & 1u)) return;     // no pixel of this wavefront reaches it
             const float4 a = s_a[e], b = s_b[e];
             const float2 cc = s_c[e];
             const float bb = cc.x;
@@ -292,6 +363,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
     __shared__ uint32_t s_id[BATCH];
+    __shared__ uint32_t s_m[BATCH];                              // wavefronts that look at it
     // multi-wavefront tiles add their wavefronts' sums in LDS and flush each
     // batch with one set of global atomics per entry
     constexpr bool kBlockSum = S::NT > 64;
@@ -306,6 +378,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     const int i0 = tx * T + S::px(tid), j0 = ty * T + S::py(tid);
     uint32_t start, end;
     tile_range(rv, tile, start, end);
+    WaveRects<S> wr;
+    wr.init(grid, tx, ty, T);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
     // r_c = colour still to come behind the current entry (image minus the
     // colour accumulated so far), kept per channel and updated in place
@@ -350,13 +425,16 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             stage_conic(r[0], r[1], ga, gb);
             s_a[q] = ga;
             s_b[q] = gb;
-            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, skip_threshold(r[1].y));
+            const float thr = skip_threshold(r[1].y);
+            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, thr);
+            s_m[q] = wave_mask<S>(ga, gb.x, thr, wr);
             s_id[q] = id;
         }
         if constexpr (kBlockSum)
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) s_g[q] = 0.0f;
         __syncthreads();
         auto entry = [&](int e) {
+            if (!((s_m[e] >> wave) & 1u)) return;     // no pixel of this wavefront reaches it
             const float4 a = s_a[e], b = s_b[e];
             const float4 c = s_c[e];                  // (b, qa2, qc2, skip threshold)
             // decisions, exactly as in the forward (same wavefront skip)
