@@ -54,7 +54,11 @@ PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 1
 #   clamp test, d/dpower, d/do 3, d/d(u, v, A, B, C) 9, the sums of the
 #   nine values over pixels 9, T update 1                                -> 43
 # Hits are counted as blends plus one per rendered pixel (its stop, an upper
-# bound) in the forward and as blends in the backward.
+# bound) in the forward and as blends in the backward.  This is the method's
+# per-pixel work: the kernels decide most examined entries for a whole
+# wavefront (8 x 8 pixels) at once with a bound on the exponent over its
+# pixels, so the rate below is the per-pixel method's equivalent, not the
+# instructions issued (those are in the SQ counter profiles).
 OPS_EXAMINE, OPS_HIT, OPS_BLEND_FWD, OPS_BLEND_BWD = 8, 7, 3, 43
 
 
