@@ -495,11 +495,11 @@ def main():
     # stage against HBM (bytes the implementation has to move)
     alu = _alu
     n = sc.n
-    roof_bwd = dict(kernel="raster_bwd_kernel<16,1,256>",
+    roof_bwd = dict(kernel="raster_bwd_kernel<16,2,128>",
                     **alu(bwd_ops(bwd_evals, blended), stage["raster_bwd"]),
                     traffic=measured_traffic("paper_2412_13547_amd/csrc/raster.hip",
                                              "profiles/raster_bwd_dilated4k_traffic.txt"))
-    roof_fwd = dict(kernel="raster_fwd_kernel<16,1,256,false>",
+    roof_fwd = dict(kernel="raster_fwd_kernel<16,2,128,false>",
                     **alu(fwd_ops(fwd_evals, blended, dil_pixels), stage["raster_fwd"]))
     # the least the stage must move: the pair list (4 B per pair) and, per
     # Gaussian, its rectangle inputs (u, v, radius: 12 B) and depth key and
