@@ -43,8 +43,11 @@ PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 1
 # operations, an FMA counts 1; per-splat work such as scaling the conic or
 # the per-splat skip threshold is not counted):
 #   examined entry (forward up to the stop, backward up to the last blended
-#   entry): offset 2, quadratic form 5, test of the exponent against the
-#   splat's threshold 1                                                  -> 8
+#   entry), decided for the pixel's 8 x 8 wavefront at once by a bound on the
+#   exponent over the block: 56 per entry and wavefront, 56/64 per pixel
+#   tested entry (one the bound does not exclude, evaluated pixel by pixel):
+#   offset 2, quadratic form 5, test of the exponent against the splat's
+#   threshold 1                                                          -> 8
 #   hit (alpha >= 1/255: the entry blends, or stops the pixel): exp 1,
 #   opacity product 1, clamp 1, exact skip test 1, alpha T 1, T after the
 #   entry 1, stop test 1                                                 -> 7
@@ -54,20 +57,19 @@ PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 1
 #   clamp test, d/dpower, d/do 3, d/d(u, v, A, B, C) 9, the sums of the
 #   nine values over pixels 9, T update 1                                -> 43
 # Hits are counted as blends plus one per rendered pixel (its stop, an upper
-# bound) in the forward and as blends in the backward.  This is the method's
-# per-pixel work: the kernels decide most examined entries for a whole
-# wavefront (8 x 8 pixels) at once with a bound on the exponent over its
-# pixels, so the rate below is the per-pixel method's equivalent, not the
-# instructions issued (those are in the SQ counter profiles).
-OPS_EXAMINE, OPS_HIT, OPS_BLEND_FWD, OPS_BLEND_BWD = 8, 7, 3, 43
+# bound) in the forward and as blends in the backward.  Tested entries are
+# counted by the counting forward (n_tested); the backward's are taken in the
+# same proportion of its examined entries.
+OPS_BOUND, OPS_EXAMINE, OPS_HIT, OPS_BLEND_FWD, OPS_BLEND_BWD = 56, 8, 7, 3, 43
 
 
-def fwd_ops(evals, blended, pixels):
-    return OPS_EXAMINE * evals + OPS_HIT * (blended + pixels) + OPS_BLEND_FWD * blended
+def fwd_ops(evals, tested, blended, pixels):
+    return (OPS_BOUND / 64.0 * evals + OPS_EXAMINE * tested + OPS_HIT * (blended + pixels)
+            + OPS_BLEND_FWD * blended)
 
 
-def bwd_ops(evals, blended):
-    return OPS_EXAMINE * evals + (OPS_HIT + OPS_BLEND_BWD) * blended
+def bwd_ops(evals, tested, blended):
+    return OPS_BOUND / 64.0 * evals + OPS_EXAMINE * tested + (OPS_HIT + OPS_BLEND_BWD) * blended
 STAGES = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd", "preprocess_bwd")
 
 
@@ -152,17 +154,23 @@ class Runner:
         rec(6)
 
     def counts(self, k):
-        """Per-step sums of n_eval, last_contrib and n_blend for phase k."""
+        """Per-step sums of n_eval, last_contrib and n_blend, the pair count and
+        the sum of n_tested for phase k (one counting forward of the view as a
+        one-view batch, which carries the n_tested output)."""
         t = self.torch
-        self._phase(k)
-        img, _ = self._bufs()
-        shape = self.view.image_shape
-        z = lambda: t.empty(shape[1:], dtype=t.int32, device="cuda")
-        last, neval, nblend = z(), z(), z()
-        self.view.forward(self.dev, img, last_contrib=last, n_eval=neval, n_blend=nblend)
+        from paper_2412_13547_amd import scenes
+        ox, oy = scenes.phase_offsets(k, self.stride)
+        b = self.api.Batch(self.ctx, self.dev.n, [(self.view.cam, self.stride, ox, oy)], tile=16,
+                           counts=True)
+        b.fit_capacity(self.dev)
+        b.forward(self.dev)
         t.cuda.synchronize()
-        s = lambda x: int(x.sum(dtype=t.int64))
-        return s(neval), s(last), s(nblend), int(self.view.state.pair_count)
+        s = lambda x: int(x[0].sum(dtype=t.int64))
+        res = (s(b.n_eval), s(b.last_contrib), s(b.n_blend), b.pair_counts()[0],
+               s(b.n_tested))
+        del b
+        t.cuda.empty_cache()
+        return res
 
     def timed(self, steps, warmup):
         t = self.torch
@@ -284,8 +292,10 @@ def run_batched(args, api, torch, np):
     pc = b.pair_counts()
     s64 = lambda ts: int(sum(int(t.sum(dtype=torch.int64)) for t in ts))
     fwd_e, bwd_e, blended = s64(b.n_eval), s64(b.last_contrib), s64(b.n_blend)
+    tested = s64(b.n_tested)
     batch_pixels = sum(int(vw.image_shape[1]) * int(vw.image_shape[2]) for vw in b.views)
-    res.update(pairs=int(sum(pc)), fwd_evals=fwd_e, bwd_evals=bwd_e, blended=blended)
+    res.update(pairs=int(sum(pc)), fwd_evals=fwd_e, bwd_evals=bwd_e, blended=blended,
+               tested=tested)
     del b
     torch.cuda.empty_cache()
     b = make(views)
@@ -358,8 +368,9 @@ def run_batched(args, api, torch, np):
     res["speedup_vs_per_view_calls"] = res["ms_per_view_calls"] / res["ms_per_step"]
     res["speedup_graph_vs_eager"] = res["ms_eager"] / res["ms_per_step"]
     st = res["stages_ms"]
-    res["roofline_raster_bwd"] = dict(**_alu(bwd_ops(bwd_e, blended), st["raster_bwd"]))
-    res["roofline_raster_fwd"] = dict(**_alu(fwd_ops(fwd_e, blended, batch_pixels),
+    res["roofline_raster_bwd"] = dict(**_alu(bwd_ops(bwd_e, tested * bwd_e / max(fwd_e, 1), blended),
+                                             st["raster_bwd"]))
+    res["roofline_raster_fwd"] = dict(**_alu(fwd_ops(fwd_e, tested, blended, batch_pixels),
                                              st["raster_fwd"]))
     return res
 
@@ -475,6 +486,7 @@ def main():
     fwd_evals = float(np.mean([c[0] for c in cnt]))
     bwd_evals = float(np.mean([c[1] for c in cnt]))
     blended = float(np.mean([c[2] for c in cnt]))
+    tested = float(np.mean([c[4] for c in cnt]))
     dil_pixels = int(dil.view.image_shape[1]) * int(dil.view.image_shape[2])
     pairs = float(np.mean([c[3] for c in cnt]))
     log(f"# dilated: {ms:.3f} ms/step, pairs {pairs:.0f}, stages {stage}")
@@ -496,11 +508,12 @@ def main():
     alu = _alu
     n = sc.n
     roof_bwd = dict(kernel="raster_bwd_kernel<16,2,128>",
-                    **alu(bwd_ops(bwd_evals, blended), stage["raster_bwd"]),
+                    **alu(bwd_ops(bwd_evals, tested * bwd_evals / max(fwd_evals, 1.0), blended),
+                          stage["raster_bwd"]),
                     traffic=measured_traffic("paper_2412_13547_amd/csrc/raster.hip",
                                              "profiles/raster_bwd_dilated4k_traffic.txt"))
     roof_fwd = dict(kernel="raster_fwd_kernel<16,2,128,false>",
-                    **alu(fwd_ops(fwd_evals, blended, dil_pixels), stage["raster_fwd"]))
+                    **alu(fwd_ops(fwd_evals, tested, blended, dil_pixels), stage["raster_fwd"]))
     # the least the stage must move: the pair list (4 B per pair) and, per
     # Gaussian, its rectangle inputs (u, v, radius: 12 B) and depth key and
     # index written and read by the depth sort (16 B)
@@ -524,6 +537,7 @@ def main():
                    "width": cam.width, "height": cam.height, "stride": stride, "tile": 16,
                    "phases": "cycle (0,0),(1,0),(0,1),(1,1)" if stride == 2 else "single"},
         "pairs": pairs, "fwd_evals": fwd_evals, "bwd_evals": bwd_evals, "blended": blended,
+        "tested": tested,
         "stages_ms": stage,
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms) if plain else None,

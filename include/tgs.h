@@ -170,6 +170,10 @@ typedef struct tgs_view_io {
     const float* target;     /* [3][H][W] full-resolution target (tgs_batch_l1_grad)         */
     float* dL_dimage;        /* [3][H_ds][W_ds]; written by tgs_batch_l1_grad, read by the
                                 backward                                                    */
+    uint32_t* n_tested;      /* optional [H_ds][W_ds]: of the entries the pixel examined, those
+                                its wavefront evaluated pixel by pixel (the others it skipped
+                                on a bound over its 8 x 8 pixel block); a measure of the
+                                rasterizer's work, not of the method's result              */
 } tgs_view_io;
 
 typedef struct tgs_context tgs_context;

@@ -83,7 +83,7 @@ class tgs_adam_group(C.Structure):
 class tgs_view_io(C.Structure):
     _fields_ = [("image", C.c_void_p), ("t_final", C.c_void_p), ("last_contrib", C.c_void_p),
                 ("n_eval", C.c_void_p), ("n_blend", C.c_void_p), ("target", C.c_void_p),
-                ("dL_dimage", C.c_void_p)]
+                ("dL_dimage", C.c_void_p), ("n_tested", C.c_void_p)]
 
 
 _P = C.POINTER
@@ -477,13 +477,14 @@ class Batch:
         self.dL = [torch.zeros(v.image_shape, dtype=f32, device="cuda") for v in self.views]
         self.targets = [None] * nv
         self.loss = torch.zeros(nv, dtype=torch.float64, device="cuda")
-        self.t_final = self.last_contrib = self.n_eval = self.n_blend = None
+        self.t_final = self.last_contrib = self.n_eval = self.n_blend = self.n_tested = None
         if counts:
             px = lambda v, dt: torch.zeros(v.image_shape[1:], dtype=dt, device="cuda")
             self.t_final = [px(v, f32) for v in self.views]
             self.last_contrib = [px(v, i32) for v in self.views]
             self.n_eval = [px(v, i32) for v in self.views]
             self.n_blend = [px(v, i32) for v in self.views]
+            self.n_tested = [px(v, i32) for v in self.views]
         for k in range(nv):
             io = self.io[k]
             io.image = _ptr(self.images[k])
@@ -493,6 +494,7 @@ class Batch:
                 io.last_contrib = _ptr(self.last_contrib[k])
                 io.n_eval = _ptr(self.n_eval[k])
                 io.n_blend = _ptr(self.n_blend[k])
+                io.n_tested = _ptr(self.n_tested[k])
 
     def set_targets(self, targets):
         for k, t in enumerate(targets):

@@ -773,6 +773,7 @@ tgs_status tgs_batch_raster_fwd(tgs_context* ctx, int64_t n, int32_t views, cons
         rv.last_contrib = io[v].last_contrib;
         rv.n_eval = io[v].n_eval;
         rv.n_blend = io[v].n_blend;
+        rv.n_tested = io[v].n_tested;
         add_raster_view(rt, rv);
     }
     TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), rt,

@@ -157,6 +157,7 @@ struct RasterView {
     uint32_t* last_contrib;   // forward, optional
     uint32_t* n_eval;         // forward, optional
     uint32_t* n_blend;        // forward, optional
+    uint32_t* n_tested;       // forward, optional: entries evaluated pixel by pixel
     const float* dL;          // backward in
     float* g2d;               // backward out (accumulated; zero it first)
 };

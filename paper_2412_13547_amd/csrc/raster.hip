@@ -225,7 +225,8 @@ __device__ __forceinline__ float wave_sum9(const float* v, int& comp) {
     return y;
 }
 
-// COUNTS adds the per-pixel counters last_contrib, n_eval and n_blend.
+// COUNTS adds the per-pixel counters last_contrib, n_eval, n_blend and
+// n_tested.
 template <int T, int PPT, int BATCH, bool COUNTS>
 __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterViews vt) {
     using S = Shape<T, PPT>;
@@ -246,7 +247,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     wr.init(grid, tx, ty, T);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
-    uint32_t last[S::NP], neval[S::NP], nblend[S::NP];
+    uint32_t last[S::NP], neval[S::NP], nblend[S::NP], ntest[S::NP];
     bool done[S::NP];
     bool alive = false;
 #pragma unroll
@@ -260,6 +261,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
         c0[k] = c1[k] = c2[k] = 0.0f;
         last[k] = 0;
         nblend[k] = 0;
+        ntest[k] = 0;
         neval[k] = end - start;
     }
     for (uint32_t base = start; base < end; base += BATCH) {
@@ -282,6 +284,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
         // an entry no live pixel of the wavefront can take is skipped whole
         auto entry = [&](int e) {
             if (!((s_m[e] >> wave) & 1u)) return;     // no pixel of this wavefront reaches it
+            if constexpr (COUNTS) {
+#pragma unroll
+                for (int k = 0; k < S::NP; ++k) ntest[k] += done[k] ? 0u : 1u;
+            }
             const float4 a = s_a[e], b = s_b[e];
             const float2 cc = s_c[e];
             const float bb = cc.x;
@@ -347,6 +353,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
             if (rv.last_contrib) rv.last_contrib[p] = last[k];
             if (rv.n_eval) rv.n_eval[p] = neval[k];
             if (rv.n_blend) rv.n_blend[p] = nblend[k];
+            if (rv.n_tested) rv.n_tested[p] = ntest[k];
         }
     }
 }
@@ -570,7 +577,8 @@ __global__ void l1_zero_kernel(L1Views vt) {
 
 bool wants_counts(const RasterViews& vt) {
     for (int k = 0; k < vt.count; ++k)
-        if (vt.v[k].last_contrib || vt.v[k].n_eval || vt.v[k].n_blend) return true;
+        if (vt.v[k].last_contrib || vt.v[k].n_eval || vt.v[k].n_blend || vt.v[k].n_tested)
+            return true;
     return false;
 }
 

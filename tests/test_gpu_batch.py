@@ -58,6 +58,7 @@ def _setup(tile=16, lds_batch=0, specs=SPECS, seed=7, n=400, deg=3):
                loss=b.loss.cpu(),
                t_final=[t.cpu() for t in b.t_final], last=[t.cpu() for t in b.last_contrib],
                n_eval=[t.cpu() for t in b.n_eval], n_blend=[t.cpu() for t in b.n_blend],
+               n_tested=[t.cpu() for t in b.n_tested],
                records=[v.records().cpu() for v in b.views],
                pair_vals=[v.pair_vals().cpu() for v in b.views],
                ranges=[v.ranges().cpu() for v in b.views],
@@ -83,6 +84,18 @@ def test_batch_forward_bitwise_equals_single_views():
         assert torch.equal(r["dL"][k], s["dL"]), k
         assert abs(float(r["loss"][k]) - float(s["loss"].item())) <= 1e-12 * float(r["loss"][k])
     say(f"[gpu] batch forward bit-exact on {len(r['singles'])} views, pairs {r['counts']}")
+
+
+def test_batch_tested_entries_lie_between_blends_and_examined():
+    """An entry is tested pixel by pixel unless the bound over the pixel's
+    wavefront excludes it, and every blended entry must have been tested."""
+    r = _setup()
+    for k in range(len(r["singles"])):
+        nt, ne, nb = r["n_tested"][k], r["n_eval"][k], r["n_blend"][k]
+        assert bool((nb <= nt).all()) and bool((nt <= ne).all()), k
+        assert int(nt.sum()) > 0, k
+    say(f"[gpu] tested/examined {[int(t.sum()) for t in r['n_tested']]} / "
+        f"{[int(t.sum()) for t in r['n_eval']]}")
 
 
 def test_batch_gradients_are_sums_of_single_views():
