@@ -408,10 +408,13 @@ col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_
 // slice's pairs in columns < c), the parts of a column one after the other:
 // a part's first slot in a column follows the earlier parts' pairs there,
 // counted from difference arrays (+1 at an entry's first column, -1 after
-// its last) that the wavefronts fill before the walk.  The walk reads each
-// covering entry into scalar registers (readlane over the ballot of the
-// entries that touch the group), so per entry and wavefront it costs one
-// LDS write.  At the end each wavefront copies a share of its group's runs
+// its last) that the wavefronts fill before the walk.  For the walk, each
+// batch of 64 entries held in registers is compacted (ballot + lane prefix)
+// into a wavefront-private LDS list of the entries that touch the group;
+// the wavefront then reads the list back entry by entry with uniform
+// addresses (an LDS broadcast), so per covering entry the walk is a few
+// vector instructions and one LDS write by the covered lanes, with no
+// scalar work.  At the end each wavefront copies a share of its group's runs
 // out; a run's consecutive local slots go to consecutive output slots.
 //
 // The count of (slice b, column c) is base[b + 1][c] - base[b][c] for the
@@ -420,6 +423,9 @@ col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_
 struct ScatterShape {
     int groups, parts;
 };
+
+constexpr int kWalkUnroll = 4;                             // list entries read per walk step
+constexpr int kListLen = 64 + kWalkUnroll;                 // a batch plus the padding
 
 __host__ __device__ inline ScatterShape scatter_shape(int gx) {
     const int groups = (gx + 63) / 64;
@@ -439,7 +445,8 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
     const ScatterShape sh = scatter_shape(gx);
     const int waves = sh.groups * sh.parts;
     uint2* s_pair = reinterpret_cast<uint2*>(smem);                // [kSlice] (Gaussian, output slot)
-    int32_t* s_diff = reinterpret_cast<int32_t*>(s_pair + kSlice); // [waves][65]
+    uint2* s_list = s_pair + kSlice;                               // [waves][kListLen] (Gaussian, lo | len << 16)
+    int32_t* s_diff = reinterpret_cast<int32_t*>(s_list + kListLen * waves); // [waves][65]
     uint32_t* s_gtot = reinterpret_cast<uint32_t*>(s_diff + 65 * waves);  // [groups]
     const int w = int(threadIdx.x >> 6), lane = __lane_id();
     const int g = w % sh.groups, p = w / sh.groups;
@@ -522,8 +529,10 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
         dst += c;
     }
     // the walk: the entries covering part of the group, in depth order,
-    // read into scalar registers (readlane over the ballot of the batch)
+    // compacted per batch into this wavefront's list and read back with
+    // uniform addresses; padding entries (len 0) cover no column
     uint2* pv = s_pair + slot;                                     // next slot of the column
+    uint2* list = s_list + kListLen * w;
     const bool reload = pe1 - pe0 > kBatch;
     for (uint32_t e = pe0; e < pe1; e += kBatch) {
         if (reload) load(e);
@@ -532,18 +541,27 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
             if (e + 64u * uint32_t(j) >= pe1) break;               // wave-uniform
             uint32_t lo, hi;
             cover(j, e, lo, hi);
-            const uint32_t packed = lo | ((hi - lo) << 8);
-            uint64_t m = __ballot(lo < hi);
-            while (m) {
-                const int k = __builtin_ctzll(m);
-                m &= m - 1;
-                const uint32_t pk = uint32_t(__builtin_amdgcn_readlane(int(packed), k));
-                const uint32_t gid = uint32_t(__builtin_amdgcn_readlane(int(id[j]), k));
-                if (uint32_t(lane) - (pk & 0xFFu) < (pk >> 8)) {
-                    *pv++ = make_uint2(gid, dst);
-                    ++dst;
+            const bool has = lo < hi;
+            const uint64_t m = __ballot(has);
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+            const uint32_t cnt = uint32_t(__builtin_popcountll(m));
+            if (has) list[pos] = make_uint2(id[j], lo | ((hi - lo) << 16));
+            if (lane < kWalkUnroll) list[cnt + uint32_t(lane)] = make_uint2(0u, 0u);
+            wave_sync_lds();
+            for (uint32_t k = 0; k < cnt; k += kWalkUnroll) {
+                uint2 v[kWalkUnroll];
+#pragma unroll
+                for (int u = 0; u < kWalkUnroll; ++u) v[u] = list[k + uint32_t(u)];
+#pragma unroll
+                for (int u = 0; u < kWalkUnroll; ++u) {
+                    if (uint32_t(lane) - (v[u].y & 0xFFFFu) < (v[u].y >> 16)) {
+                        *pv++ = make_uint2(v[u].x, dst);
+                        ++dst;
+                    }
                 }
             }
+            wave_sync_lds();                                       // list read before it is rewritten
         }
     }
     __syncthreads();
@@ -568,7 +586,7 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
 size_t scatter_lds_bytes(int gx) {
     const ScatterShape sh = scatter_shape(gx);
     const size_t waves = size_t(sh.groups) * sh.parts;
-    return size_t(kSlice) * 8 + waves * 65 * 4 + size_t(sh.groups) * 4;
+    return size_t(kSlice) * 8 + waves * kListLen * 8 + waves * 65 * 4 + size_t(sh.groups) * 4;
 }
 
 }  // namespace
