@@ -225,8 +225,34 @@ __device__ __forceinline__ float wave_sum9(const float* v, int& comp) {
     return y;
 }
 
+// Calls entry(e), in order, for the entries e < cnt of an LDS batch whose
+// wavefront mask has this wavefront's bit, while live() holds on some lane:
+// each 64 entries' bits become one ballot, and the wavefront visits the set
+// bits only, so an entry its rectangle cannot reach costs nothing.  Entries
+// after every pixel has stopped change nothing, so leaving early keeps the
+// result.
+template <class L, class F>
+__device__ __forceinline__ void for_wave_entries(const uint32_t* s_m, int cnt, int wave, L&& live,
+                                                 F&& entry) {
+    for (int c = 0; c < cnt; c += 64) {
+        const int q = c + __lane_id();
+        uint64_t m = __ballot(q < cnt && ((s_m[q] >> wave) & 1u));
+        while (m != 0 && __ballot(live()) != 0) {
+            const int e = c + int(__builtin_ctzll(m));
+            m &= m - 1;
+            entry(e);
+        }
+    }
+}
+
 // COUNTS adds the per-pixel counters last_contrib, n_eval, n_blend and
 // n_tested.
+//
+// A pixel's state is its transmittance with a sign: positive while it
+// still takes entries, negated (the magnitude kept) once it has stopped or
+// when it lies outside the image.  Live transmittance never drops below
+// the floor kTMin > 0, so the sign is never ambiguous, and no per-pixel
+// flag has to be carried from entry to entry.
 template <int T, int PPT, int BATCH, bool COUNTS>
 __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterViews vt) {
     using S = Shape<T, PPT>;
@@ -246,26 +272,28 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     WaveRects<S> wr;
     wr.init(grid, tx, ty, T);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    float X[S::NP], Y[S::NP], Tr[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
+    float X[S::NP], Y[S::NP], Ts[S::NP], c0[S::NP], c1[S::NP], c2[S::NP];
     uint32_t last[S::NP], neval[S::NP], nblend[S::NP], ntest[S::NP];
-    bool done[S::NP];
-    bool alive = false;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
         const int i = i0 + k % S::PX, j = j0 + k / S::PX;
-        done[k] = !(i < grid.w_ds && j < grid.h_ds);
-        alive |= !done[k];
         X[k] = float(grid.stride * i + grid.off_x);
         Y[k] = float(grid.stride * j + grid.off_y);
-        Tr[k] = 1.0f;
+        Ts[k] = i < grid.w_ds && j < grid.h_ds ? 1.0f : -1.0f;
         c0[k] = c1[k] = c2[k] = 0.0f;
         last[k] = 0;
         nblend[k] = 0;
         ntest[k] = 0;
         neval[k] = end - start;
     }
+    auto live = [&]() {
+        bool l = false;
+#pragma unroll
+        for (int k = 0; k < S::NP; ++k) l = l || Ts[k] > 0.0f;
+        return l;
+    };
     for (uint32_t base = start; base < end; base += BATCH) {
-        if (__syncthreads_count(alive) == 0) break;
+        if (__syncthreads_count(live()) == 0) break;
         const int cnt = min(BATCH, int(end - base));
         for (int q = tid; q < cnt; q += S::NT) {
             const uint32_t id = rv.vals[base + q];
@@ -280,64 +308,43 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
             s_m[q] = wave_mask<S>(ga, gb.x, thr, wr);
         }
         __syncthreads();
-        // branch-free per entry: a skipped entry adds exactly 0 and leaves T;
-        // an entry no live pixel of the wavefront can take is skipped whole
+        // branch-free per entry: a skipped entry adds exactly 0 and leaves T
+        // (entries no pixel of the wavefront can reach are not visited)
         auto entry = [&](int e) {
-            if (!((s_m[e] >> wave) & 1u)) return;     // no pixel of this wavefront reaches it
             if constexpr (COUNTS) {
 #pragma unroll
-                for (int k = 0; k < S::NP; ++k) ntest[k] += done[k] ? 0u : 1u;
+                for (int k = 0; k < S::NP; ++k) ntest[k] += Ts[k] > 0.0f ? 1u : 0u;
             }
             const float4 a = s_a[e], b = s_b[e];
             const float2 cc = s_c[e];
             const float bb = cc.x;
             float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP];
-            bool cand = false;
 #pragma unroll
-            for (int k = 0; k < S::NP; ++k) {
-                p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
-                cand = cand || (p2[k] >= cc.y && !done[k]);
-            }
-            if (__ballot(cand) == 0) return;          // T, colours and stops unchanged
-            alive = false;
+            for (int k = 0; k < S::NP; ++k) p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
                 float G, raw, alpha;
-                const bool hit = splat_test(b, p2[k], G, raw, alpha) && !done[k];
-                const float w0 = alpha * Tr[k];
+                const bool hit = splat_test(b, p2[k], G, raw, alpha) && Ts[k] > 0.0f;
+                const float w0 = alpha * Ts[k];
                 // T after this entry below the floor: the pixel stops here;
                 // otherwise it blends (one comparison: stop implies hit)
-                const bool stop = hit && Tr[k] - w0 < kTMin;
+                const bool stop = hit && Ts[k] - w0 < kTMin;
                 const bool blend = hit != stop;
                 const float w = blend ? w0 : 0.0f;
                 c0[k] = fmaf(b.z, w, c0[k]);
                 c1[k] = fmaf(b.w, w, c1[k]);
                 c2[k] = fmaf(bb, w, c2[k]);
-                Tr[k] = Tr[k] - w;
+                const float tn = Ts[k] - w;           // Ts itself when not blending
+                Ts[k] = stop ? -tn : tn;
                 if constexpr (COUNTS) {
                     const uint32_t pos = base - start + uint32_t(e) + 1;
                     last[k] = blend ? pos : last[k];
                     nblend[k] += blend ? 1u : 0u;
                     neval[k] = stop ? pos : neval[k];
                 }
-                done[k] = done[k] || stop;
-                alive = alive || !done[k];
             }
         };
-        // the wavefront leaves as soon as all its pixels have stopped, checked
-        // every fourth entry (entries after a stop change nothing)
-        int e = 0;
-        for (; e + 4 <= cnt; e += 4) {
-            if (__ballot(alive) == 0) break;
-            entry(e);
-            entry(e + 1);
-            entry(e + 2);
-            entry(e + 3);
-        }
-        for (; e < cnt; ++e) {
-            if (__ballot(alive) == 0) break;
-            entry(e);
-        }
+        for_wave_entries(s_m, cnt, wave, live, entry);
     }
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
 #pragma unroll
@@ -345,10 +352,11 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
         const int i = i0 + k % S::PX, j = j0 + k / S::PX;
         if (!(i < grid.w_ds && j < grid.h_ds)) continue;
         const uint64_t p = uint64_t(j) * grid.w_ds + i;
-        rv.image[p] = fmaf(Tr[k], rv.bg[0], c0[k]);
-        rv.image[pix + p] = fmaf(Tr[k], rv.bg[1], c1[k]);
-        rv.image[2 * pix + p] = fmaf(Tr[k], rv.bg[2], c2[k]);
-        if (rv.t_final) rv.t_final[p] = Tr[k];
+        const float Tr = fabsf(Ts[k]);
+        rv.image[p] = fmaf(Tr, rv.bg[0], c0[k]);
+        rv.image[pix + p] = fmaf(Tr, rv.bg[1], c1[k]);
+        rv.image[2 * pix + p] = fmaf(Tr, rv.bg[2], c2[k]);
+        if (rv.t_final) rv.t_final[p] = Tr;
         if constexpr (COUNTS) {
             if (rv.last_contrib) rv.last_contrib[p] = last[k];
             if (rv.n_eval) rv.n_eval[p] = neval[k];
@@ -390,20 +398,18 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
     // r_c = colour still to come behind the current entry (image minus the
-    // colour accumulated so far), kept per channel and updated in place
-    float X[S::NP], Y[S::NP], Tr[S::NP], r0[S::NP], r1[S::NP], r2[S::NP];
+    // colour accumulated so far), kept per channel and updated in place;
+    // Ts = transmittance, negated once the pixel has stopped (as in the
+    // forward)
+    float X[S::NP], Y[S::NP], Ts[S::NP], r0[S::NP], r1[S::NP], r2[S::NP];
     float g0[S::NP], g1[S::NP], g2[S::NP];
-    bool done[S::NP];
-    bool alive = false;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
         const int i = i0 + k % S::PX, j = j0 + k / S::PX;
         const bool in = i < grid.w_ds && j < grid.h_ds;
-        done[k] = !in;
-        alive |= in;
         X[k] = float(grid.stride * i + grid.off_x);
         Y[k] = float(grid.stride * j + grid.off_y);
-        Tr[k] = 1.0f;
+        Ts[k] = in ? 1.0f : -1.0f;
         r0[k] = r1[k] = r2[k] = 0.0f;
         g0[k] = g1[k] = g2[k] = 0.0f;
         if (in) {
@@ -422,8 +428,14 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     const float scale = own == 0 || own == 1 ? kLn2
                         : own == 2 || own == 4 ? -0.5f
                         : own == 3 ? -1.0f : 1.0f;
+    auto live = [&]() {
+        bool l = false;
+#pragma unroll
+        for (int k = 0; k < S::NP; ++k) l = l || Ts[k] > 0.0f;
+        return l;
+    };
     for (uint32_t base = start; base < end; base += BATCH) {
-        if (__syncthreads_count(alive) == 0) break;
+        if (__syncthreads_count(live()) == 0) break;
         const int cnt = min(BATCH, int(end - base));
         for (int q = tid; q < cnt; q += S::NT) {
             const uint32_t id = rv.vals[base + q];
@@ -441,35 +453,29 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) s_g[q] = 0.0f;
         __syncthreads();
         auto entry = [&](int e) {
-            if (!((s_m[e] >> wave) & 1u)) return;     // no pixel of this wavefront reaches it
             const float4 a = s_a[e], b = s_b[e];
             const float4 c = s_c[e];                  // (b, qa2, qc2, skip threshold)
             // decisions, exactly as in the forward (same wavefront skip)
             float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
             bool blend[S::NP];
-            bool cand = false;
 #pragma unroll
-            for (int k = 0; k < S::NP; ++k) {
-                p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
-                cand = cand || (p2[k] >= c.w && !done[k]);
-            }
-            if (__ballot(cand) == 0) return;
+            for (int k = 0; k < S::NP; ++k) p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
             uint64_t any = 0;                         // lanes with a blending pixel
-            alive = false;
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const bool hit = splat_test(b, p2[k], G[k], raw[k], alpha[k]) && !done[k];
-                const bool stop = hit && Tr[k] - alpha[k] * Tr[k] < kTMin;
+                const bool hit = splat_test(b, p2[k], G[k], raw[k], alpha[k]) && Ts[k] > 0.0f;
+                const bool stop = hit && Ts[k] - alpha[k] * Ts[k] < kTMin;
                 blend[k] = hit != stop;
                 any |= __ballot(blend[k]);
-                done[k] = done[k] || stop;
-                alive = alive || !done[k];
+                Ts[k] = stop ? -Ts[k] : Ts[k];
             }
             if (any == 0) return;                     // no pixel of the wavefront blends it
             float gv[kGrad2d];
+            // T0 is the pixel's transmittance where it blends; elsewhere every
+            // term it enters is selected away (w, dp and the G term are 0)
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const float T0 = Tr[k];
+                const float T0 = Ts[k];
                 const float w = blend[k] ? alpha[k] * T0 : 0.0f;
                 r0[k] = fmaf(-b.z, w, r0[k]);
                 r1[k] = fmaf(-b.w, w, r1[k]);
@@ -491,7 +497,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                     w * g0[k], w * g1[k], w * g2[k]};
 #pragma unroll
                 for (int q = 0; q < kGrad2d; ++q) gv[q] = k == 0 ? m[q] : gv[q] + m[q];
-                Tr[k] = T0 - w;
+                Ts[k] = T0 - w;
             }
             int comp;
             const float sum = wave_sum9(gv, comp);
@@ -500,20 +506,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                 else atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], sum * scale);
             }
         };
-        // the wavefront leaves once all its pixels have stopped, checked every
-        // fourth entry (entries after a stop change nothing)
-        int e = 0;
-        for (; e + 4 <= cnt; e += 4) {
-            if (__ballot(alive) == 0) break;
-            entry(e);
-            entry(e + 1);
-            entry(e + 2);
-            entry(e + 3);
-        }
-        for (; e < cnt; ++e) {
-            if (__ballot(alive) == 0) break;
-            entry(e);
-        }
+        for_wave_entries(s_m, cnt, wave, live, entry);
         if constexpr (kBlockSum) {
             __syncthreads();
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) {
