@@ -38,13 +38,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12                    # B/s, MI355X HBM3E
-PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# FP32 vector peak in lane operations with an FMA counted once: the published
+# 157.3 TFLOP/s of MI355X (256 CU, 2.4 GHz) over 2 flops per FMA.  The 16-lane
+# single-issue rate (256 x 4 x 16 x 2.4 GHz = 39.3 T/s) is no ceiling: the
+# batched rasterizers issue VALU instructions faster than that (hardware
+# counter SQ_INSTS_VALU over the kernel time).
+PEAK_VALU = 157.3e12 / 2.0
 # The least FP32 arithmetic the method needs per list entry and pixel (lane
 # operations, an FMA counts 1; per-splat work such as scaling the conic or
 # the per-splat skip threshold is not counted):
 #   examined entry (forward up to the stop, backward up to the last blended
-#   entry), decided for the pixel's 8 x 8 wavefront at once by a bound on the
-#   exponent over the block: 56 per entry and wavefront, 56/64 per pixel
+#   entry), decided for the pixel's wavefront (8 x 8 threads of 1-4 pixels)
+#   at once by a bound on the exponent over its pixel rectangle: 56 per
+#   entry and wavefront, 56 / (pixels of the wavefront) per pixel
 #   tested entry (one the bound does not exclude, evaluated pixel by pixel):
 #   offset 2, quadratic form 5, test of the exponent against the splat's
 #   threshold 1                                                          -> 8
@@ -63,13 +69,26 @@ PEAK_VALU = 256 * 4 * 16 * 2.4e9     # FP32 VALU lane-ops/s: 256 CU x 4 SIMD x 1
 OPS_BOUND, OPS_EXAMINE, OPS_HIT, OPS_BLEND_FWD, OPS_BLEND_BWD = 56, 8, 7, 3, 43
 
 
-def fwd_ops(evals, tested, blended, pixels):
-    return (OPS_BOUND / 64.0 * evals + OPS_EXAMINE * tested + OPS_HIT * (blended + pixels)
+def wave_pixels(tile=16):
+    """Pixels of one rasterizer wavefront at the default launch of `tile`."""
+    from paper_2412_13547_amd import api
+    return 64 * api.default_launch(tile)[1]
+
+
+def raster_labels(tile=16):
+    """Kernel names of the default rasterizer launch of `tile`."""
+    from paper_2412_13547_amd import api
+    lds, ppt = api.default_launch(tile)
+    return (f"raster_fwd_kernel<{tile},{ppt},{lds},false>", f"raster_bwd_kernel<{tile},{ppt},{lds}>")
+
+
+def fwd_ops(evals, tested, blended, pixels, wpix):
+    return (OPS_BOUND / wpix * evals + OPS_EXAMINE * tested + OPS_HIT * (blended + pixels)
             + OPS_BLEND_FWD * blended)
 
 
-def bwd_ops(evals, tested, blended):
-    return OPS_BOUND / 64.0 * evals + OPS_EXAMINE * tested + (OPS_HIT + OPS_BLEND_BWD) * blended
+def bwd_ops(evals, tested, blended, wpix):
+    return OPS_BOUND / wpix * evals + OPS_EXAMINE * tested + (OPS_HIT + OPS_BLEND_BWD) * blended
 STAGES = ("preprocess_fwd", "bin_sort", "raster_fwd", "l1_grad", "raster_bwd", "preprocess_bwd")
 
 
@@ -368,9 +387,11 @@ def run_batched(args, api, torch, np):
     res["speedup_vs_per_view_calls"] = res["ms_per_view_calls"] / res["ms_per_step"]
     res["speedup_graph_vs_eager"] = res["ms_eager"] / res["ms_per_step"]
     st = res["stages_ms"]
-    res["roofline_raster_bwd"] = dict(**_alu(bwd_ops(bwd_e, tested * bwd_e / max(fwd_e, 1), blended),
+    wpix = wave_pixels()
+    res["roofline_raster_bwd"] = dict(**_alu(bwd_ops(bwd_e, tested * bwd_e / max(fwd_e, 1), blended,
+                                                     wpix),
                                              st["raster_bwd"]))
-    res["roofline_raster_fwd"] = dict(**_alu(fwd_ops(fwd_e, tested, blended, batch_pixels),
+    res["roofline_raster_fwd"] = dict(**_alu(fwd_ops(fwd_e, tested, blended, batch_pixels, wpix),
                                              st["raster_fwd"]))
     return res
 
@@ -507,13 +528,15 @@ def main():
     # stage against HBM (bytes the implementation has to move)
     alu = _alu
     n = sc.n
-    roof_bwd = dict(kernel="raster_bwd_kernel<16,2,128>",
-                    **alu(bwd_ops(bwd_evals, tested * bwd_evals / max(fwd_evals, 1.0), blended),
+    label_fwd, label_bwd = raster_labels()
+    wpix = wave_pixels()
+    roof_bwd = dict(kernel=label_bwd,
+                    **alu(bwd_ops(bwd_evals, tested * bwd_evals / max(fwd_evals, 1.0), blended, wpix),
                           stage["raster_bwd"]),
                     traffic=measured_traffic("paper_2412_13547_amd/csrc/raster.hip",
                                              "profiles/raster_bwd_dilated4k_traffic.txt"))
-    roof_fwd = dict(kernel="raster_fwd_kernel<16,2,128,false>",
-                    **alu(fwd_ops(fwd_evals, tested, blended, dil_pixels), stage["raster_fwd"]))
+    roof_fwd = dict(kernel=label_fwd,
+                    **alu(fwd_ops(fwd_evals, tested, blended, dil_pixels, wpix), stage["raster_fwd"]))
     # the least the stage must move: the pair list (4 B per pair) and, per
     # Gaussian, its rectangle inputs (u, v, radius: 12 B) and depth key and
     # index written and read by the depth sort (16 B)

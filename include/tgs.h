@@ -196,6 +196,12 @@ void tgs_destroy(tgs_context* ctx);
 tgs_status tgs_query_sizes(int64_t n, const tgs_camera* cam, const tgs_dilation* dil,
                            const tgs_options* opt, uint64_t pair_capacity, tgs_sizes* out);
 
+/* Host only, no device needed.  The rasterizer launch a tile size gets when
+ * tgs_options leaves lds_batch and pixels_per_thread at 0: the LDS batch and
+ * pixels per thread written to *lds_batch and *pixels_per_thread.  Returns
+ * TGS_ERR_INVALID_ARG for a tile other than 8, 16 or 32 or a NULL output. */
+tgs_status tgs_default_launch(int32_t tile, int32_t* lds_batch, int32_t* pixels_per_thread);
+
 /* Stage (a), Sec. 3 and Sec. 4.1: per Gaussian, view transform, near cull,
  * Sigma = R S S^T R^T, EWA projection with the full-resolution focal length
  * plus a 0.3 px^2 low-pass, conic, radius, SH colour, and the number of

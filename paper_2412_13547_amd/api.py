@@ -19,7 +19,7 @@ TGS_OK, TGS_ERR_INVALID_ARG, TGS_ERR_CAPACITY, TGS_ERR_HIP, TGS_ERR_NO_DEVICE, T
 
 EXPORTED = (
     "tgs_status_str", "tgs_last_error", "tgs_version", "tgs_create", "tgs_destroy",
-    "tgs_query_sizes", "tgs_preprocess_fwd", "tgs_bin_sort", "tgs_raster_fwd", "tgs_forward",
+    "tgs_query_sizes", "tgs_default_launch", "tgs_preprocess_fwd", "tgs_bin_sort", "tgs_raster_fwd", "tgs_forward",
     "tgs_l1_grad", "tgs_raster_bwd", "tgs_preprocess_bwd", "tgs_backward",
     "tgs_batch_preprocess_fwd", "tgs_batch_bin_sort", "tgs_batch_raster_fwd",
     "tgs_batch_forward", "tgs_batch_l1_grad", "tgs_batch_raster_bwd", "tgs_batch_preprocess_bwd",
@@ -100,6 +100,7 @@ def _declare(lib):
         "tgs_destroy": (None, [vp]),
         "tgs_query_sizes": (C.c_int, [C.c_int64, _P(tgs_camera), _P(tgs_dilation), _P(tgs_options),
                                       C.c_uint64, _P(tgs_sizes)]),
+        "tgs_default_launch": (C.c_int, [C.c_int32, _P(C.c_int32), _P(C.c_int32)]),
         "tgs_preprocess_fwd": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
                                          _P(tgs_options), _P(tgs_state), vp]),
         "tgs_bin_sort": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
@@ -287,6 +288,14 @@ def query_sizes(n, cam, dil: tgs_dilation, opt: tgs_options, pair_capacity: int)
     check(lib().tgs_query_sizes(int(n), C.byref(camera_struct(cam) if not isinstance(cam, tgs_camera) else cam),
                                 C.byref(dil), C.byref(opt), int(pair_capacity), C.byref(out)))
     return out
+
+
+def default_launch(tile: int) -> tuple[int, int]:
+    """(lds_batch, pixels_per_thread) the rasterizers use for `tile` when the
+    options leave them at 0."""
+    lds, ppt = C.c_int32(), C.c_int32()
+    check(lib().tgs_default_launch(int(tile), C.byref(lds), C.byref(ppt)))
+    return int(lds.value), int(ppt.value)
 
 
 class View:

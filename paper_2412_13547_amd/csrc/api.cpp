@@ -323,10 +323,11 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     return L;
 }
 
-// Fastest settings measured at the 4K dilated scene (3M Gaussians, stride 2).
-int default_lds_batch(int tile) { return tile == 8 ? 64 : tile == 16 ? 128 : 256; }
+// Fastest settings measured by the launch autotuner on a batch of 12 views
+// (2M Gaussians) and at the 4K dilated scene (3M Gaussians, stride 2).
+int default_lds_batch(int tile) { return tile == 8 ? 128 : tile == 16 ? 64 : 256; }
 
-int default_pixels_per_thread(int tile) { return tile == 8 ? 1 : 2; }
+int default_pixels_per_thread(int tile) { return tile == 8 ? 1 : 4; }
 
 CamDev make_cam(const tgs_camera& c) {
     CamDev d{};
@@ -410,6 +411,14 @@ void tgs_destroy(tgs_context* ctx) {
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
+}
+
+tgs_status tgs_default_launch(int32_t tile, int32_t* lds_batch, int32_t* pixels_per_thread) {
+    if (!lds_batch || !pixels_per_thread) return fail(TGS_ERR_INVALID_ARG, "output is NULL");
+    if (tile != 8 && tile != 16 && tile != 32) return fail(TGS_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
+    *lds_batch = tgs::default_lds_batch(tile);
+    *pixels_per_thread = tgs::default_pixels_per_thread(tile);
+    return TGS_OK;
 }
 
 tgs_status tgs_query_sizes(int64_t n, const tgs_camera* cam, const tgs_dilation* dil,

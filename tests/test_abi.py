@@ -49,6 +49,17 @@ def test_query_sizes_host_only():
     assert (s3.w_ds, s3.h_ds, s3.grid_x, s3.grid_y) == (33, 12, 5, 2)
 
 
+def test_default_launch_host_only():
+    for tile in (8, 16, 32):
+        lds, ppt = api.default_launch(tile)
+        assert lds in (64, 128, 256) and ppt in (1, 2, 4)
+        assert tile != 8 or ppt == 1
+        assert tile != 32 or ppt in (2, 4)
+    lds, ppt = C.c_int32(), C.c_int32()
+    assert api.lib().tgs_default_launch(12, C.byref(lds), C.byref(ppt)) == api.TGS_ERR_INVALID_ARG
+    assert api.lib().tgs_default_launch(16, None, C.byref(ppt)) == api.TGS_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("field,value", [("stride", 0), ("off_x", 2), ("off_y", -1)])
 def test_bad_dilation_rejected(field, value):
     dil = api.dilation_struct(2, 0, 0)
