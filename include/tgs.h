@@ -144,13 +144,16 @@ typedef struct tgs_state {
     uint32_t reserved;
     uint64_t off_records;        /* out: tgs_record[n]                                    */
     uint64_t off_tiles_touched;  /* out: uint32[n], ds tiles each Gaussian overlaps       */
-    uint64_t off_depth_order;    /* out: uint32[n], Gaussian ids sorted by depth key      */
+    uint64_t off_depth_order;    /* out: uint32[n]; its first m entries are the ids of the
+                                         m Gaussians with tiles, sorted by depth key (equal
+                                         keys by id); the rest is unspecified            */
     uint64_t off_pair_vals;      /* out: uint32[pair_count], Gaussian id of each pair in
                                          (tile, depth, index) order                      */
     uint64_t off_ranges;         /* out: uint32[num_tiles][2], [start, end) per tile      */
     uint64_t off_grad2d;         /* out: float[n][9], dL/d(u,v,A,B,C,o,r,g,b) (backward)  */
     uint64_t off_pair_count;     /* out: uint32, the pair count on the device; above
                                          pair_capacity when a batched bin/sort overflowed */
+    uint64_t off_depth_count;    /* out: uint32, m of off_depth_order, on the device     */
 } tgs_state;
 
 /* st->pair_count after a batched bin/sort, until tgs_pair_counts reads the

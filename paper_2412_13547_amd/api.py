@@ -72,7 +72,8 @@ class tgs_state(C.Structure):
                 ("off_records", C.c_uint64), ("off_tiles_touched", C.c_uint64),
                 ("off_depth_order", C.c_uint64),
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
-                ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64)]
+                ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64),
+                ("off_depth_count", C.c_uint64)]
 
 
 class tgs_adam_group(C.Structure):
@@ -434,7 +435,9 @@ class View:
         return self._view(self.state.off_tiles_touched, self.n, self._torch.int32)
 
     def depth_order(self):
-        return self._view(self.state.off_depth_order, self.n, self._torch.int32)
+        """Ids of the Gaussians with tiles, sorted by depth key (equal keys by id)."""
+        m = int(self._view(self.state.off_depth_count, 1, self._torch.int32).item())
+        return self._view(self.state.off_depth_order, m, self._torch.int32)
 
     def pair_vals(self):
         return self._view(self.state.off_pair_vals, int(self.state.pair_count), self._torch.int32)

@@ -166,11 +166,13 @@ tgs_status check_binned(const tgs_state* st, const tgs::Layout& L, const tgs::Gr
     return TGS_OK;
 }
 
-void publish_offsets(tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid, int depth_buf) {
+void publish_offsets(tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
+                     const uint32_t* depth_order, const uint8_t* ws) {
     st->off_pair_count = L.row_start + 4 * uint64_t(grid.gy);
     st->off_records = L.records;
     st->off_tiles_touched = L.tiles_touched;
-    st->off_depth_order = L.depth_val[depth_buf];
+    st->off_depth_order = uint64_t(reinterpret_cast<const uint8_t*>(depth_order) - ws);
+    st->off_depth_count = L.sort_counts + 4 * tgs::radix_kept_offset(uint64_t(n));
     st->off_pair_vals = L.pair_vals;
     st->off_ranges = L.ranges;
     st->off_grad2d = L.grad2d;
@@ -229,21 +231,27 @@ int ppt_of(const tgs_options& opt) {
 }
 
 // Depth sort and the pair counts per (tile row, chunk), up to the row starts
-// and the device pair count.  Returns the depth-sort result buffer.
+// and the device pair count.  Returns the depth-sort result buffer and the
+// device count of the Gaussians it holds.
 tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
                           uint64_t max_slices, hipStream_t strm, int* dres,
-                          const uint32_t** order) {
+                          const uint32_t** order, const uint32_t** dcount) {
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
     auto* partials = reinterpret_cast<uint64_t*>(ws + L.scan_partials);
-    // Gaussians by depth key (stable; culled and off-screen ones last)
+    // the Gaussians with tiles sorted by depth key (stable, so equal keys
+    // keep index order); culled and off-grid ones (key 0xFFFFFFFF) are left
+    // out, their number stays on the device
     uint32_t* dkeys[2] = {u32(L.depth_key[0]), u32(L.depth_key[1])};
     uint32_t* dvals[2] = {u32(L.depth_val[0]), u32(L.depth_val[1])};
-    TGS_HIP(tgs::radix_sort(dkeys, dvals, uint64_t(n), 32, u32(L.sort_counts), partials, dres, strm));
+    TGS_HIP(tgs::radix_sort(dkeys, dvals, uint64_t(n), 32, u32(L.sort_counts), partials, dres, strm,
+                            true, 0xFFFFFFFFu));
+    const uint32_t* kept = u32(L.sort_counts) + tgs::radix_kept_offset(uint64_t(n));
     *order = dvals[*dres];
+    *dcount = kept;
     // entries and pairs per (tile row, block of the depth order); scans ->
     // every block's place in every row
     const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_blocks(n);
-    TGS_HIP(tgs::launch_counts(ws, L, *order, n, grid, strm));
+    TGS_HIP(tgs::launch_counts(ws, L, *order, n, kept, grid, strm));
     TGS_HIP(tgs::exclusive_scan_u32(u32(L.ecnt), u32(L.ecnt), nrow, partials, true, strm));
     TGS_HIP(tgs::exclusive_scan_u32(u32(L.pcnt), u32(L.pcnt), nrow, partials, true, strm));
     TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, max_slices, strm));
@@ -255,9 +263,9 @@ tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& gr
 // bounds the column-sort slices from above; the kernels skip all work when
 // the device pair count exceeds the capacity.
 tgs_status enqueue_emit(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& grid, int64_t n,
-                        const uint32_t* order, uint64_t slices, uint32_t capacity,
-                        hipStream_t strm) {
-    TGS_HIP(tgs::launch_entries(ws, L, order, n, grid, capacity, strm));
+                        const uint32_t* order, const uint32_t* dcount, uint64_t slices,
+                        uint32_t capacity, hipStream_t strm) {
+    TGS_HIP(tgs::launch_entries(ws, L, order, n, dcount, grid, capacity, strm));
     TGS_HIP(tgs::launch_col_sort(ws, L, grid, slices, capacity, strm));
     return TGS_OK;
 }
@@ -461,7 +469,8 @@ tgs_status tgs_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, const tg
     TGS_HIP(tgs::launch_preprocess_fwd(*g, t, static_cast<hipStream_t>(stream)));
     st->pair_count = 0;
     st->key_bits = 0;     // not binned yet
-    publish_offsets(st, L, grid, 0);
+    auto* ws = static_cast<uint8_t*>(st->workspace);
+    publish_offsets(st, L, grid, g->n, reinterpret_cast<const uint32_t*>(ws + L.depth_val[0]), ws);
     return TGS_OK;
 }
 
@@ -480,8 +489,9 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     auto strm = static_cast<hipStream_t>(stream);
     int dres = 0;
     const uint32_t* order = nullptr;
+    const uint32_t* dcount = nullptr;
     const uint64_t max_slices = tgs::bin_max_slices(st->pair_capacity, grid.gy);
-    if ((s = enqueue_counts(ws, L, grid, g->n, max_slices, strm, &dres, &order)) != TGS_OK)
+    if ((s = enqueue_counts(ws, L, grid, g->n, max_slices, strm, &dres, &order, &dcount)) != TGS_OK)
         return s;
     // row starts (and the pair count) back to the host: the column sort is
     // then launched with exactly as many slices as there are
@@ -494,11 +504,12 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     for (int ty = 0; ty < grid.gy; ++ty) slices += (uint64_t(rs[ty + 1] - rs[ty]) + tgs::kSlice - 1) / tgs::kSlice;
     st->pair_count = P;
     st->key_bits = 0;
-    publish_offsets(st, L, grid, dres);
+    publish_offsets(st, L, grid, g->n, order, ws);
     if (P > st->pair_capacity)
         return fail(TGS_ERR_CAPACITY, "%llu pairs needed, capacity %llu", (unsigned long long)P,
                     (unsigned long long)st->pair_capacity);
-    if ((s = enqueue_emit(ws, L, grid, g->n, order, slices, uint32_t(st->pair_capacity), strm)) != TGS_OK)
+    if ((s = enqueue_emit(ws, L, grid, g->n, order, dcount, slices, uint32_t(st->pair_capacity),
+                          strm)) != TGS_OK)
         return s;
     st->key_bits = uint32_t(key_bits_for(grid.num_tiles()));   // marks the state as binned
     return TGS_OK;
@@ -699,7 +710,9 @@ tgs_status tgs_batch_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, in
     for (int v = 0; v < views; ++v) {
         states[v].pair_count = 0;
         states[v].key_bits = 0;
-        publish_offsets(&states[v], Ls[v], grids[v], 0);
+        auto* ws = static_cast<uint8_t*>(states[v].workspace);
+        publish_offsets(&states[v], Ls[v], grids[v], g->n,
+                        reinterpret_cast<const uint32_t*>(ws + Ls[v].depth_val[0]), ws);
     }
     return TGS_OK;
 }
@@ -748,12 +761,13 @@ tgs_status tgs_batch_bin_sort(tgs_context* ctx, const tgs_gaussians* g, int32_t 
         const uint32_t cap = uint32_t(st.pair_capacity);
         int dres = 0;
         const uint32_t* order = nullptr;
+        const uint32_t* dcount = nullptr;
         const uint64_t max_slices = tgs::bin_max_slices(cap, grids[v].gy);
         const hipStream_t vs = chain_stream[chain_of[v]];
-        status = enqueue_counts(ws, Ls[v], grids[v], g->n, max_slices, vs, &dres, &order);
+        status = enqueue_counts(ws, Ls[v], grids[v], g->n, max_slices, vs, &dres, &order, &dcount);
         if (status == TGS_OK)
-            status = enqueue_emit(ws, Ls[v], grids[v], g->n, order, max_slices, cap, vs);
-        publish_offsets(&st, Ls[v], grids[v], dres);
+            status = enqueue_emit(ws, Ls[v], grids[v], g->n, order, dcount, max_slices, cap, vs);
+        if (status == TGS_OK) publish_offsets(&st, Ls[v], grids[v], g->n, order, ws);
         st.pair_count = TGS_PAIR_COUNT_PENDING;
         st.key_bits = uint32_t(key_bits_for(grids[v].num_tiles()));
     }

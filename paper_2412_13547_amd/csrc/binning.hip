@@ -34,6 +34,8 @@
 #include "common.hpp"
 #include "wave.hpp"
 
+#include <algorithm>
+
 namespace tgs {
 namespace {
 
@@ -84,16 +86,17 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t* s_
 // gives the row starts and every block's offset inside every row).
 __global__ void __launch_bounds__(kBinThreads)
 count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order, int64_t n,
-             Grid grid, uint32_t nblk, uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt,
-             uint2* __restrict__ srect) {
+             const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
+             uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt, uint2* __restrict__ srect) {
     extern __shared__ uint32_t lds[];
+    const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;    // Gaussians in the order
     const int gy = grid.gy;
     uint32_t* ce = lds;           // [gy]
     uint32_t* cp = lds + gy;      // [gy]
     for (int r = threadIdx.x; r < gy; r += kBinThreads) ce[r] = cp[r] = 0;
     __syncthreads();
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
-    const uint2 packed = gather_rect(rects, order, s, n);
+    const uint2 packed = gather_rect(rects, order, s, m);
     if (s < n) srect[s] = packed;
     const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
@@ -156,8 +159,8 @@ row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict_
 // descriptor and closes the slice before it.
 __global__ void __launch_bounds__(kBinThreads)
 entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order, int64_t n,
-             Grid grid, uint32_t nblk, const uint32_t* __restrict__ escan,
-             const uint32_t* __restrict__ pscan, const uint32_t* __restrict__ row_start,
+             const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
+             const uint32_t* __restrict__ escan, const uint32_t* __restrict__ pscan, const uint32_t* __restrict__ row_start,
              const uint32_t* __restrict__ first_slice, uint32_t capacity,
              uint32_t* __restrict__ ent_id, uint32_t* __restrict__ ent_pp,
              uint32_t* __restrict__ ent_x, uint4* __restrict__ slice_desc,
@@ -183,7 +186,8 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     }
     const int wv = threadIdx.x >> 6;
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
-    const uint32_t id = s < n ? order[s] : 0u;
+    const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;
+    const uint32_t id = s < m ? order[s] : 0u;
     const uint2 packed = s < n ? srect[s] : make_uint2(0u, 0u);
     const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
@@ -596,12 +600,12 @@ uint32_t bin_blocks(int64_t n) { return uint32_t((n + kBinThreads - 1) / kBinThr
 uint64_t bin_max_slices(uint64_t pairs, int gy) { return pairs / kSlice + uint64_t(gy) + 1; }
 
 hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                         const Grid& grid, hipStream_t s) {
+                         const uint32_t* dcount, const Grid& grid, hipStream_t s) {
     const uint32_t nblk = bin_blocks(n);
     if (nblk > 0) {
         auto* w = const_cast<uint8_t*>(ws);
         count_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy) * 8, s>>>(
-            reinterpret_cast<const uint2*>(ws + L.rects), order, n, grid, nblk,
+            reinterpret_cast<const uint2*>(ws + L.rects), order, n, dcount, grid, nblk,
             reinterpret_cast<uint32_t*>(w + L.ecnt), reinterpret_cast<uint32_t*>(w + L.pcnt),
             reinterpret_cast<uint2*>(w + L.srect));
     }
@@ -619,12 +623,13 @@ hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid&
 }
 
 hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                          const Grid& grid, uint32_t capacity, hipStream_t s) {
+                          const uint32_t* dcount, const Grid& grid, uint32_t capacity,
+                          hipStream_t s) {
     const uint32_t nblk = bin_blocks(n);
     if (nblk == 0) return hipSuccess;
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
     entry_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy + 1) * 16, s>>>(
-        reinterpret_cast<const uint2*>(ws + L.srect), order, n, grid, nblk, u32(L.ecnt),
+        reinterpret_cast<const uint2*>(ws + L.srect), order, n, dcount, grid, nblk, u32(L.ecnt),
         u32(L.pcnt), u32(L.row_start), u32(L.first_slice), capacity, u32(L.ent_id),
         u32(L.ent_pp), u32(L.ent_x), reinterpret_cast<uint4*>(ws + L.slice_desc), u32(L.slice_e1));
     return hipGetLastError();

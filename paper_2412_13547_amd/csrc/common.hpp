@@ -64,7 +64,8 @@ struct Layout {
     uint64_t col_hist;         // uint32[gx * max_slices], column histograms, then scanned
     uint64_t ranges;           // uint32[num_tiles][2]
     uint64_t grad2d;           // float[n][9]
-    uint64_t sort_counts;      // uint32, radix digit counts
+    uint64_t sort_counts;      // uint32, radix digit counts, then the number of Gaussians
+                               //   with tiles (at radix_kept_offset(n))
     uint64_t scan_partials;    // uint64, scan block sums
     uint64_t total;
 };
@@ -111,11 +112,16 @@ hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const PrepViews& views,
                                  uint8_t* visible, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs on bits [0, bits).
-// Returns the index (0 or 1) of the buffer pair holding the result.
+// Returns the index (0 or 1) of the buffer pair holding the result.  With
+// drop_on, the pairs whose key equals drop are left out; the number of pairs
+// kept is then counts[radix_kept_offset(count)] on the device (the result
+// holds that many).  counts needs radix_counts_elems(count) entries.
 int radix_sort_passes(int bits);
 hipError_t radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint64_t count, int bits,
-                      uint32_t* counts, uint64_t* partials, int* result, hipStream_t s);
+                      uint32_t* counts, uint64_t* partials, int* result, hipStream_t s,
+                      bool drop_on = false, uint32_t drop = 0u);
 uint64_t radix_counts_elems(uint64_t count);
+uint64_t radix_kept_offset(uint64_t count);
 
 // Exclusive scan of uint32 (in may equal out); with write_total, out[count]
 // receives the total (out then has count + 1 entries).
@@ -129,12 +135,15 @@ uint64_t scan_partials_elems(uint64_t count);
 // can be enqueued without reading the count back.
 uint32_t bin_blocks(int64_t n);
 uint64_t bin_max_slices(uint64_t pairs, int gy);
+// `order` holds the Gaussians with tiles in depth order; their number is
+// min(n, *dcount) when dcount is given (device), n otherwise.
 hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                         const Grid& grid, hipStream_t s);
+                         const uint32_t* dcount, const Grid& grid, hipStream_t s);
 hipError_t launch_row_setup(uint8_t* ws, const Layout& L, int64_t n, const Grid& grid,
                             uint64_t max_slices, hipStream_t s);
 hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, int64_t n,
-                          const Grid& grid, uint32_t capacity, hipStream_t s);
+                          const uint32_t* dcount, const Grid& grid, uint32_t capacity,
+                          hipStream_t s);
 // Stable counting sort of every row bucket by column, and the tile ranges;
 // `slices` bounds the number of column-sort slices from above.
 hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,

@@ -5,12 +5,18 @@
 //   1. digit_counts : each block counts the digits of its 4096 keys in LDS
 //                     (one private histogram per wavefront, then summed) and
 //                     stores them digit-major, counts[digit][block];
-//   2. exclusive scan of counts -> first output slot of (digit, block);
+//   2. exclusive scan of counts -> first output slot of (digit, block), and
+//      the total after the last entry;
 //   3. scatter      : the block sorts its tile by digit in LDS, walking its
-//                     keys in input order 256 at a time (equal digits inside a
-//                     wavefront ranked with eight ballots, wavefronts ordered
-//                     through LDS, so equal keys keep their input order), then
-//                     writes each digit's run to consecutive output slots.
+//                     keys in input order 1024 at a time (equal digits inside
+//                     a wavefront ranked with eight ballots, wavefronts
+//                     ordered by a prefix over them per digit, so equal keys
+//                     keep their input order), then writes each digit's run
+//                     to consecutive output slots.
+// The first pass may drop every pair whose key equals a given value (it is
+// neither counted nor written); the scanned total is then the number of
+// pairs kept, and the later passes read it on the device (their grids are
+// sized for the input count; tiles past the kept count are empty).
 #include "common.hpp"
 
 namespace tgs {
@@ -22,18 +28,37 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (uint64_t(1) << lane_id()) - 1;
 }
 
+// How a pass treats its input: the number of keys (the host bound, or the
+// device count when given) and the dropped key, if any.
+struct PassInput {
+    uint64_t bound;
+    const uint32_t* dcount;
+    bool drop_on;
+    uint32_t drop;
+    __device__ uint64_t count() const { return dcount ? min(bound, uint64_t(*dcount)) : bound; }
+    __device__ bool kept(uint32_t k) const { return !drop_on || k != drop; }
+};
+
 __global__ void __launch_bounds__(kSortThreads)
-digit_counts(const uint32_t* __restrict__ keys, uint64_t count, int shift,
+digit_counts(const uint32_t* __restrict__ keys, PassInput in, int shift,
              uint32_t* __restrict__ counts, uint32_t nblocks) {
     __shared__ uint32_t hist[kSortThreads / 64][kRadixBuckets];
+    const uint64_t count = in.count();
     const int tid = threadIdx.x, wave = tid >> 6;
+    if (uint64_t(blockIdx.x) * kSortTile >= count) {             // empty tile, block-uniform
+        counts[uint64_t(tid) * nblocks + blockIdx.x] = 0u;
+        return;
+    }
     for (int w = 0; w < kSortThreads / 64; ++w) hist[w][tid] = 0;
     __syncthreads();
     const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
 #pragma unroll 4
     for (int it = 0; it < kSortItems; ++it) {
         const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
-        if (idx < count) atomicAdd(&hist[wave][(keys[idx] >> shift) & (kRadixBuckets - 1)], 1u);
+        if (idx < count) {
+            const uint32_t k = keys[idx];
+            if (in.kept(k)) atomicAdd(&hist[wave][(k >> shift) & (kRadixBuckets - 1)], 1u);
+        }
     }
     __syncthreads();
     uint32_t s = 0;
@@ -45,44 +70,55 @@ digit_counts(const uint32_t* __restrict__ keys, uint64_t count, int shift,
 template <typename T, int NT>
 __device__ __forceinline__ T block_exclusive_scan(T x, T& total);
 
-__global__ void __launch_bounds__(kSortThreads)
+constexpr int kScatterThreads = 1024;
+constexpr int kScatterRounds = kSortTile / kScatterThreads;
+
+__global__ void __launch_bounds__(kScatterThreads)
 digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-              uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, uint64_t count,
+              uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, PassInput in,
               int shift, const uint32_t* __restrict__ offsets, uint32_t nblocks) {
-    constexpr int W = kSortThreads / 64;
+    constexpr int W = kScatterThreads / 64;
     __shared__ uint32_t s_key[kSortTile], s_val[kSortTile];   // the tile, ordered by digit
     __shared__ uint32_t run[kRadixBuckets];       // next local slot per digit
     __shared__ uint32_t lstart[kRadixBuckets];    // first local slot per digit
     __shared__ uint32_t gbase[kRadixBuckets];     // first output slot per digit
-    __shared__ uint32_t wcnt[W][kRadixBuckets];   // this round's count per wave and digit
-    const int tid = threadIdx.x, wave = tid >> 6;
+    // per round: (round + 1) << 16 | count of the digit in the wavefront,
+    // written by the digit's first lane; then the wavefront's first local slot
+    __shared__ uint32_t wcnt[W][kRadixBuckets];
+    const uint64_t count = in.count();
     const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+    if (base >= count) return;                                   // empty tile, block-uniform
+    const int tid = threadIdx.x, wave = tid >> 6;
     // the tile's keys, all loads in flight at once
-    uint32_t key[kSortItems], val[kSortItems];
+    uint32_t key[kScatterRounds], val[kScatterRounds];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
+    for (int it = 0; it < kScatterRounds; ++it) {
+        const uint64_t idx = base + uint64_t(it) * kScatterThreads + tid;
         key[it] = idx < count ? keys_in[idx] : 0u;
         val[it] = idx < count ? vals_in[idx] : 0u;
     }
     // this block's count of digit tid (difference of consecutive scanned
-    // counts) -> its first local slot; and its first output slot
-    const uint64_t i = uint64_t(tid) * nblocks + blockIdx.x;
-    const uint32_t off = offsets[i];
-    const uint32_t nxt = i + 1 < uint64_t(kRadixBuckets) * nblocks ? offsets[i + 1] : uint32_t(count);
+    // counts; the scan ends with the total) -> its first local slot; and its
+    // first output slot
+    uint32_t off = 0, nxt = 0;
+    if (tid < kRadixBuckets) {
+        const uint64_t i = uint64_t(tid) * nblocks + blockIdx.x;
+        off = offsets[i];
+        nxt = offsets[i + 1];
+    }
     uint32_t total;
-    const uint32_t ls = block_exclusive_scan<uint32_t, kSortThreads>(nxt - off, total);
-    lstart[tid] = ls;
-    run[tid] = ls;
-    gbase[tid] = off;
-    for (int w = 0; w < W; ++w) wcnt[w][tid] = 0;
+    const uint32_t ls = block_exclusive_scan<uint32_t, kScatterThreads>(nxt - off, total);
+    if (tid < kRadixBuckets) {
+        lstart[tid] = ls;
+        run[tid] = ls;
+        gbase[tid] = off;
+    }
+    for (int j = tid; j < W * kRadixBuckets; j += kScatterThreads) (&wcnt[0][0])[j] = 0u;
     __syncthreads();
-    // stable local counting sort: 256 keys per round, equal digits inside a
-    // wavefront ranked with ballots, wavefronts ordered through LDS
-    for (int it = 0; it < kSortItems; ++it) {
-        const uint64_t idx = base + uint64_t(it) * kSortThreads + tid;
-        const bool valid = idx < count;
+    for (int it = 0; it < kScatterRounds; ++it) {
+        const uint64_t idx = base + uint64_t(it) * kScatterThreads + tid;
         const uint32_t k = key[it];
+        const bool valid = idx < count && in.kept(k);
         const uint32_t d = (k >> shift) & (kRadixBuckets - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -92,28 +128,30 @@ digit_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = __popcll(peers & lanemask_lt());
-        const bool leader = valid && (peers & lanemask_lt()) == 0;
-        if (leader) wcnt[wave][d] = __popcll(peers);
+        const uint32_t tag = uint32_t(it + 1) << 16;
+        if (valid && rank == 0) wcnt[wave][d] = tag | uint32_t(__popcll(peers));
+        __syncthreads();
+        // per digit: the first local slot of every wavefront this round
+        if (tid < kRadixBuckets) {
+            uint32_t acc = run[tid];
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = wcnt[w][tid];
+                wcnt[w][tid] = acc;                   // < 4096: never carries a tag
+                acc += (v >> 16) == uint32_t(it + 1) ? (v & 0xFFFFu) : 0u;
+            }
+            run[tid] = acc;
+        }
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            const uint32_t pos = wcnt[wave][d] + rank;
             s_key[pos] = k;
             s_val[pos] = val[it];
         }
         __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < W; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        run[tid] += add;
-        __syncthreads();
     }
     // out in local order: a digit's keys go to consecutive output slots, so
     // neighbouring threads write neighbouring addresses
-    const uint32_t nvalid = uint32_t(min(uint64_t(kSortTile), count - base));
-    for (uint32_t j = tid; j < nvalid; j += kSortThreads) {
+    for (uint32_t j = tid; j < total; j += kScatterThreads) {
         const uint32_t k = s_key[j];
         const uint32_t d = (k >> shift) & (kRadixBuckets - 1);
         const uint32_t pos = gbase[d] + (j - lstart[d]);
@@ -238,7 +276,7 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) 
 uint64_t scan_partials_elems(uint64_t count) { return (count + kScanTile - 1) / kScanTile + 1; }
 
 uint64_t radix_counts_elems(uint64_t count) {
-    return uint64_t(kRadixBuckets) * ((count + kSortTile - 1) / kSortTile);
+    return uint64_t(kRadixBuckets) * ((count + kSortTile - 1) / kSortTile) + 1;
 }
 
 int radix_sort_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
@@ -251,25 +289,38 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
 }
 
 hipError_t radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint64_t count, int bits,
-                      uint32_t* counts, uint64_t* partials, int* result, hipStream_t s) {
+                      uint32_t* counts, uint64_t* partials, int* result, hipStream_t s,
+                      bool drop_on, uint32_t drop) {
     int cur = 0;
     const uint64_t nb = (count + kSortTile - 1) / kSortTile;
     const int passes = radix_sort_passes(bits);
-    for (int p = 0; p < passes && count > 0; ++p) {
+    // the scanned total (kept pairs) sits after the nb * buckets counts
+    const uint32_t* kept = counts + nb * kRadixBuckets;
+    if (count == 0) {
+        *result = 0;
+        return fill_u32(counts, 0u, 1, s);
+    }
+    for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
-        digit_counts<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(keys[cur], count, shift,
-                                                                        counts, uint32_t(nb));
-        // digit counts fit in uint32; their scan is done in uint64 partials
+        PassInput in{count, nullptr, drop_on && p == 0, drop};
+        if (drop_on && p > 0) in.dcount = kept;
+        digit_counts<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(keys[cur], in, shift, counts,
+                                                                        uint32_t(nb));
+        // digit counts fit in uint32; the scan writes the total after them
         hipError_t e = exclusive_scan<uint32_t, uint32_t>(
-            counts, nullptr, counts, nb * kRadixBuckets,
-            reinterpret_cast<uint32_t*>(partials), false, s);
+            counts, nullptr, counts, nb * kRadixBuckets, reinterpret_cast<uint32_t*>(partials),
+            true, s);
         if (e != hipSuccess) return e;
-        digit_scatter<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(
-            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], count, shift, counts, uint32_t(nb));
+        digit_scatter<<<dim3(unsigned(nb)), dim3(kScatterThreads), 0, s>>>(
+            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], in, shift, counts, uint32_t(nb));
         cur = 1 - cur;
     }
     *result = cur;
     return hipGetLastError();
+}
+
+uint64_t radix_kept_offset(uint64_t count) {
+    return uint64_t(kRadixBuckets) * ((count + kSortTile - 1) / kSortTile);
 }
 
 }  // namespace tgs

@@ -106,6 +106,52 @@ def test_binning_sort_ranges_bit_exact(name):
     say(f"[gpu] {name}: {g['pair_count']} pairs bit-exact")
 
 
+def _expected_depth_order(b):
+    """Ids of the Gaussians with tiles, by depth bits, equal bits by id."""
+    ids = torch.nonzero(b["tiles_touched"] > 0).flatten().numpy()
+    zb = b["zbits"].numpy()[ids]
+    return ids[np.lexsort((ids, zb))]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_depth_order_is_the_sorted_gaussians_with_tiles(name):
+    sc, cam, _, g = _case(name)
+    rec = records_to_oracle(g["records"])
+    b = obn.bin_gaussians(rec["u"], rec["v"], rec["z"], rec["radius"], rec["culled"], g["grid"])
+    got = g["_view"].depth_order().cpu().to(torch.int64).numpy()
+    want = _expected_depth_order(b)
+    assert got.shape == want.shape and np.array_equal(got, want)
+    say(f"[gpu] {name}: depth order of {got.size} of {sc.n} Gaussians bit-exact")
+
+
+def test_depth_order_ties_and_culled():
+    """Exact depth ties (duplicated Gaussians) keep id order; Gaussians
+    behind the camera and off-screen ones are left out of the order."""
+    sc, cam = scenes.small_scene(7, 400, 128, 96, sh_degree=1)
+    sc = sc.copy()
+    sc.means[:, 200:300] = sc.means[:, 0:100]           # 100 exact depth ties
+    sc.scales[:, 200:300] = sc.scales[:, 0:100]
+    sc.quats[:, 200:300] = sc.quats[:, 0:100]
+    r = cam.w2c[:, :3].astype(np.float64)
+    t = cam.w2c[:, 3].astype(np.float64)
+    behind = r.T @ (np.array([[0.0], [0.0], [-1.0]]) - t[:, None])
+    sc.means[:, 300:340] = behind.astype(np.float32)     # behind the camera: culled
+    sc.means[:, 340:360] = (r.T @ (np.array([[50.0], [0.0], [3.0]]) - t[:, None])).astype(np.float32)
+    g = run_gpu(sc, cam, 2, 1, 0, 16, target=scenes.target_image(128, 96, 7))
+    rec = records_to_oracle(g["records"])
+    b = obn.bin_gaussians(rec["u"], rec["v"], rec["z"], rec["radius"], rec["culled"], g["grid"])
+    got = g["_view"].depth_order().cpu().to(torch.int64).numpy()
+    want = _expected_depth_order(b)
+    assert np.array_equal(got, want)
+    assert not np.isin(np.arange(300, 360), got).any()
+    zb = b["zbits"].numpy()
+    tied = [k for k in range(100) if zb[k] == zb[200 + k] and k in set(got.tolist())]
+    assert len(tied) > 10
+    pos = {int(v): i for i, v in enumerate(got)}
+    assert all(pos[k] < pos[200 + k] for k in tied)
+    say(f"[gpu] depth order with {len(tied)} exact ties and 60 culled or off-screen: bit-exact")
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_raster_forward_matches_oracle(name):
     sc, cam, _, g = _case(name)
