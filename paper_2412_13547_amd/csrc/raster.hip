@@ -367,10 +367,11 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
 }
 
 // Per blended entry the lane's contribution to the nine sums, as moments
-// that the wave reduces first; the constant factors of each component
-// (ln 2 for u and v, -1/2, -1, -1/2 for A, B, C) are applied once per wave
-// to the reduced sums:
-//   dL/du = ln2 sum dp (qa2 dx + qb dy),  dL/dv = ln2 sum dp (qc2 dy + qb dx),
+// that the wave reduces first; the splat's constants and the constant
+// factors of each component (ln 2 for u and v, -1/2, -1, -1/2 for A, B, C)
+// are applied once per wave to the reduced sums:
+//   dL/du = ln2 (qa2 Sx + qb Sy),  dL/dv = ln2 (qc2 Sy + qb Sx),
+//   Sx = sum dp dx,  Sy = sum dp dy,
 //   dL/dA = -1/2 sum dp dx^2,  dL/dB = -sum dp dx dy,  dL/dC = -1/2 sum dp dy^2,
 // with dp = dL/dpower, qa2 = 2 qa, qc2 = 2 qc.
 template <int T, int PPT, int BATCH>
@@ -490,8 +491,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                 const float dp = live ? alpha[k] * dal : 0.0f;
                 const float pdx = dp * dx[k], pdy = dp * dy[k];
                 const float m[kGrad2d] = {
-                    fmaf(c.y, dx[k], t[k]) * dp,            // (qa2 dx + qb dy) dp
-                    fmaf(c.z, dy[k], a.w * dx[k]) * dp,     // (qc2 dy + qb dx) dp
+                    pdx, pdy,                               // dp dx, dp dy
                     pdx * dx[k], pdx * dy[k], pdy * dy[k],
                     live ? G[k] * dal : 0.0f,
                     w * g0[k], w * g1[k], w * g2[k]};
@@ -500,7 +500,12 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                 Ts[k] = T0 - w;
             }
             int comp;
-            const float sum = wave_sum9(gv, comp);
+            float sum = wave_sum9(gv, comp);
+            // lanes 0 and 8 hold Sx and Sy: exchange them (rotation by 8
+            // within a row of 16 lanes) to form the u and v components
+            const float other = dpp_f<kDppRowRor8>(sum);
+            if (comp == 0) sum = fmaf(c.y, sum, a.w * other);
+            if (comp == 1) sum = fmaf(c.z, sum, a.w * other);
             if (comp >= 0 && sum != 0.0f) {
                 if constexpr (kBlockSum) atomicAdd(&s_g[e * kGrad2d + comp], sum * scale);
                 else atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], sum * scale);

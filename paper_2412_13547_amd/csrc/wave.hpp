@@ -11,6 +11,7 @@ namespace tgs {
 
 // DPP control codes (GCN / CDNA encoding)
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowRor8 = 0x128;   // rotate by 8 within each row of 16 lanes
 constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
 constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
 constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
