@@ -180,7 +180,7 @@ class Runner:
         from paper_2412_13547_amd import scenes
         ox, oy = scenes.phase_offsets(k, self.stride)
         b = self.api.Batch(self.ctx, self.dev.n, [(self.view.cam, self.stride, ox, oy)], tile=16,
-                           counts=True)
+                           counts=True, pair_capacity=int(self.view.state.pair_capacity))
         b.fit_capacity(self.dev)
         b.forward(self.dev)
         t.cuda.synchronize()
