@@ -31,10 +31,11 @@ def say(*a):
 
 
 def run_gpu(scene, cam, stride=1, off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0), target=None,
-            dL_dimage=None, backward=True):
+            dL_dimage=None, backward=True, lds_batch=0, pixels_per_thread=0):
     """Forward (+ loss + backward) on cuda:0; every result copied to the host."""
     dev = api.DeviceScene.from_scene(scene)
-    view = api.View(ctx(), scene.n, cam, stride, off_x, off_y, tile, bg)
+    view = api.View(ctx(), scene.n, cam, stride, off_x, off_y, tile, bg, lds_batch=lds_batch,
+                    pixels_per_thread=pixels_per_thread)
     shape = view.image_shape
     image = torch.empty(shape, dtype=torch.float32, device="cuda")
     tfin = torch.empty(shape[1:], dtype=torch.float32, device="cuda")

@@ -152,6 +152,33 @@ def test_depth_order_ties_and_culled():
     say(f"[gpu] depth order with {len(tied)} exact ties and 60 culled or off-screen: bit-exact")
 
 
+SPLITS = {8: (1,), 16: (1, 2, 4), 32: (2, 4)}
+
+
+@pytest.mark.parametrize("name", ["tiny128-d1-T16", "sh2-101x77-d3-o21-T8-bg",
+                                  "sh1-150x130-d4-o32-T32", "sh0-333x200-d2-o11-T16"])
+def test_work_split_and_lds_batch_leave_results_unchanged(name):
+    """Every (pixels per thread, LDS batch) of the tile size renders the same
+    image, transmittance and counters bit for bit as the checked default
+    (the wavefront skips depend on the split: each must be exact), and the
+    same gradients up to the order of the float atomics."""
+    sc, cam, tgt, ref = _case(name)
+    _, d, ox, oy, T, bg = CASES[name]
+    for ppt in SPLITS[T]:
+        for lds in (64, 128, 256):
+            say(f"[gpu] {name}: P={ppt} B={lds}")
+            g = run_gpu(sc, cam, d, ox, oy, T, bg, target=tgt, lds_batch=lds, pixels_per_thread=ppt)
+            for k in ("image", "t_final", "last_contrib", "n_eval", "n_blend"):
+                assert torch.equal(g[k], ref[k]), (ppt, lds, k)
+            assert torch.equal(g["pair_vals"], ref["pair_vals"])
+            a, b = g["grad2d"].to(F64), ref["grad2d"].to(F64)
+            assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, (ppt, lds)
+            for k in ("means", "opacities", "sh"):
+                a, b = g["grads"][k].to(F64), ref["grads"][k].to(F64)
+                assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, (ppt, lds, k)
+    say(f"[gpu] {name}: every split and LDS batch bit-exact in the forward")
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_raster_forward_matches_oracle(name):
     sc, cam, _, g = _case(name)
