@@ -546,15 +546,34 @@ __global__ void __launch_bounds__(256) l1_grad_kernel(L1Views vt) {
     for (uint32_t j = lb; j < h; j += nb) {
         const uint64_t Y = uint64_t(grid.stride) * j + grid.off_y;
         const float* trow = lv.target + Y * grid.width + grid.off_x;
-        for (uint32_t i = threadIdx.x; i < w; i += blockDim.x) {
-            const uint64_t p = uint64_t(j) * w + i;
-            const uint64_t X = uint64_t(grid.stride) * i;
+        // four pixels per thread and pass, every load issued before the
+        // first use
+        constexpr int kU = 4;
+        for (uint32_t i0 = threadIdx.x; i0 < w; i0 += kU * blockDim.x) {
+            float im[kU][3], tg[kU][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float diff = lv.image[c * pix + p] - trow[c * full + X];
-                const float sg = diff > 0.0f ? 1.0f : (diff < 0.0f ? -1.0f : 0.0f);
-                lv.dL[c * pix + p] = sg * inv;
-                s += fabs(double(diff));
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t i = i0 + uint32_t(u) * blockDim.x;
+                const uint64_t p = uint64_t(j) * w + i;
+                const uint64_t X = uint64_t(grid.stride) * i;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    im[u][c] = i < w ? lv.image[c * pix + p] : 0.0f;
+                    tg[u][c] = i < w ? trow[c * full + X] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t i = i0 + uint32_t(u) * blockDim.x;
+                if (i >= w) continue;
+                const uint64_t p = uint64_t(j) * w + i;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float diff = im[u][c] - tg[u][c];
+                    const float sg = diff > 0.0f ? 1.0f : (diff < 0.0f ? -1.0f : 0.0f);
+                    lv.dL[c * pix + p] = sg * inv;
+                    s += fabs(double(diff));
+                }
             }
         }
     }
