@@ -184,7 +184,7 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
         s_rs[r] = row_start[r];
         s_fs[r] = first_slice[r];
     }
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
     const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;
     const uint32_t id = s < m ? order[s] : 0u;
@@ -214,7 +214,8 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
         if (__lane_id() == 0) sw[wv] = wt;
         __syncthreads();
         uint32_t before = 0;
-        for (int k = 0; k < wv; ++k) before += sw[k];
+#pragma unroll
+        for (int k = 0; k < kBinThreads / 64 - 1; ++k) before += k < wv ? sw[k] : 0u;
         if (in) {
             const uint32_t rank = before + ex;
             const uint32_t e = s_e[r] + (rank & 0xFFFu);
