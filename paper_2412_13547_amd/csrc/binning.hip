@@ -453,7 +453,7 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
     uint2* s_list = s_pair + kSlice;                               // [waves][kListLen] (Gaussian, lo | len << 16)
     int32_t* s_diff = reinterpret_cast<int32_t*>(s_list + kListLen * waves); // [waves][65]
     uint32_t* s_gtot = reinterpret_cast<uint32_t*>(s_diff + 65 * waves);  // [groups]
-    const int w = int(threadIdx.x >> 6), lane = __lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = __lane_id();
     const int g = w % sh.groups, p = w / sh.groups;
     const uint32_t b = blockIdx.x;
     const uint32_t cbeg = 64u * uint32_t(g), col = cbeg + uint32_t(lane);
