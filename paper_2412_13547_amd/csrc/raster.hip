@@ -257,7 +257,8 @@ template <int T, int PPT, int BATCH, bool COUNTS>
 __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterViews vt) {
     using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH];
-    __shared__ float2 s_c[BATCH];                                // (blue, skip threshold)
+    // blue, at the stride of s_a and s_b so one address serves all three
+    __shared__ float4 s_c[BATCH];
     __shared__ uint32_t s_m[BATCH];                              // wavefronts that look at it
     int v;
     int64_t tile;
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
             const float thr = skip_threshold(r1.y);
             s_a[q] = ga;
             s_b[q] = gb;
-            s_c[q] = make_float2(r[2].x, thr);
+            s_c[q] = make_float4(r[2].x, 0.0f, 0.0f, 0.0f);
             s_m[q] = wave_mask<S>(ga, gb.x, thr, wr);
         }
         __syncthreads();
@@ -316,8 +317,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
                 for (int k = 0; k < S::NP; ++k) ntest[k] += Ts[k] > 0.0f ? 1u : 0u;
             }
             const float4 a = s_a[e], b = s_b[e];
-            const float2 cc = s_c[e];
-            const float bb = cc.x;
+            const float bb = s_c[e].x;
             float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP];
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
@@ -446,7 +446,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             s_a[q] = ga;
             s_b[q] = gb;
             const float thr = skip_threshold(r[1].y);
-            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, thr);
+            s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, 0.0f);
             s_m[q] = wave_mask<S>(ga, gb.x, thr, wr);
             s_id[q] = id;
         }
@@ -455,7 +455,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         __syncthreads();
         auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
-            const float4 c = s_c[e];                  // (b, qa2, qc2, skip threshold)
+            const float4 c = s_c[e];                  // (b, qa2, qc2, unused)
             // decisions, exactly as in the forward (same wavefront skip)
             float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
             bool blend[S::NP];
