@@ -435,9 +435,10 @@ class View:
         return self._view(self.state.off_tiles_touched, self.n, self._torch.int32)
 
     def depth_order(self):
-        """Ids of the Gaussians with tiles, sorted by depth key (equal keys by id)."""
+        """Ids of the Gaussians with tiles, sorted by depth key (equal keys by id);
+        valid after a bin/sort of this state."""
         m = int(self._view(self.state.off_depth_count, 1, self._torch.int32).item())
-        return self._view(self.state.off_depth_order, m, self._torch.int32)
+        return self._view(self.state.off_depth_order, min(max(m, 0), self.n), self._torch.int32)
 
     def pair_vals(self):
         return self._view(self.state.off_pair_vals, int(self.state.pair_count), self._torch.int32)
