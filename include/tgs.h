@@ -153,7 +153,8 @@ typedef struct tgs_state {
     uint64_t off_grad2d;         /* out: float[n][9], dL/d(u,v,A,B,C,o,r,g,b) (backward)  */
     uint64_t off_pair_count;     /* out: uint32, the pair count on the device; above
                                          pair_capacity when a batched bin/sort overflowed */
-    uint64_t off_depth_count;    /* out: uint32, m of off_depth_order, on the device     */
+    uint64_t off_depth_count;    /* out: uint32 on the device, m of off_depth_order;
+                                         valid once a bin/sort of this state has run     */
 } tgs_state;
 
 /* st->pair_count after a batched bin/sort, until tgs_pair_counts reads the
