@@ -89,25 +89,48 @@ count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order
              const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
              uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt, uint2* __restrict__ srect) {
     extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_w[kBinThreads / 64];
     const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;    // Gaussians in the order
     const int gy = grid.gy;
-    uint32_t* ce = lds;           // [gy]
-    uint32_t* cp = lds + gy;      // [gy]
-    for (int r = threadIdx.x; r < gy; r += kBinThreads) ce[r] = cp[r] = 0;
+    // difference arrays over the rows (+1 / +w at a Gaussian's first row,
+    // -1 / -w after its last; modulo 2^32), then one prefix over the rows
+    uint32_t* ce = lds;               // [gy + 1]
+    uint32_t* cp = lds + (gy + 1);    // [gy + 1]
+    for (int r = threadIdx.x; r <= gy; r += kBinThreads) ce[r] = cp[r] = 0;
     __syncthreads();
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
     const uint2 packed = gather_rect(rects, order, s, m);
     if (s < n) srect[s] = packed;
     const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
-    for (int r = rc.ylo; r < rc.yhi; ++r) {
-        atomicAdd(&ce[r], 1u);
-        atomicAdd(&cp[r], w);
+    if (rc.ylo < rc.yhi) {
+        atomicAdd(&ce[rc.ylo], 1u);
+        atomicAdd(&cp[rc.ylo], w);
+        atomicSub(&ce[rc.yhi], 1u);
+        atomicSub(&cp[rc.yhi], w);
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < gy; r += kBinThreads) {
-        ecnt[uint64_t(r) * nblk + blockIdx.x] = ce[r];
-        pcnt[uint64_t(r) * nblk + blockIdx.x] = cp[r];
+    // thread t owns the consecutive rows [t * cpl, t * cpl + cpl)
+    const int cpl = (gy + kBinThreads - 1) / kBinThreads;
+    const int r0 = int(threadIdx.x) * cpl;
+    uint32_t se = 0, sp = 0;
+    for (int j = 0; j < cpl; ++j) {
+        if (r0 + j < gy) {
+            se += ce[r0 + j];
+            sp += cp[r0 + j];
+        }
+    }
+    uint32_t tot;
+    uint32_t re = block_exclusive_sum<kBinThreads>(se, s_w, tot);
+    uint32_t rp = block_exclusive_sum<kBinThreads>(sp, s_w, tot);
+    for (int j = 0; j < cpl; ++j) {
+        const int r = r0 + j;
+        if (r < gy) {
+            re += ce[r];
+            rp += cp[r];
+            ecnt[uint64_t(r) * nblk + blockIdx.x] = re;
+            pcnt[uint64_t(r) * nblk + blockIdx.x] = rp;
+        }
     }
 }
 
@@ -605,7 +628,7 @@ hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* ord
     const uint32_t nblk = bin_blocks(n);
     if (nblk > 0) {
         auto* w = const_cast<uint8_t*>(ws);
-        count_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy) * 8, s>>>(
+        count_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy + 1) * 8, s>>>(
             reinterpret_cast<const uint2*>(ws + L.rects), order, n, dcount, grid, nblk,
             reinterpret_cast<uint32_t*>(w + L.ecnt), reinterpret_cast<uint32_t*>(w + L.pcnt),
             reinterpret_cast<uint2*>(w + L.srect));
