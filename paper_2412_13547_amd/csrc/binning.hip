@@ -45,6 +45,13 @@ constexpr int kScatterWaves = 8;                           // wavefronts per sca
 constexpr int kHistThreads = 256;
 constexpr int kColBatch = 16;                              // slices loaded together in col_scan
 
+// Orders this wavefront's LDS accesses: what its lanes wrote is visible to
+// all its lanes after this.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ int wave_min(int x) {
     for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
     return x;
@@ -175,29 +182,35 @@ row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict_
 }
 
 // Every block writes its entries row by row: ent_id (Gaussian), ent_pp
-// (first pair of the entry), ent_x (xlo | xhi << 16).  One block scan per row
-// ranks the block's entries and pairs at once (packed: pairs << 12 | 1; a
-// block holds 256 entries and at most 256 * 1024 pairs of a row).  The entry
-// that holds the first pair of a column-sort slice writes the slice's
-// descriptor and closes the slice before it.
+// (first pair of the entry), ent_x (xlo | xhi << 16).  A Gaussian's rank in
+// a row among the block's Gaussians counts entries and pairs at once
+// (packed: pairs << 12 | 1; a block holds 256 entries and at most
+// 256 * 1024 pairs of a row): per wavefront and row the packed totals come
+// from difference arrays over the rows and a prefix, a prefix over the
+// wavefronts gives each wavefront's first rank in every row, and then each
+// wavefront walks its own rows with no barrier, ranking its lanes with one
+// wavefront scan per row.  The entry that holds the first pair of a
+// column-sort slice writes the slice's descriptor and closes the slice
+// before it.
 __global__ void __launch_bounds__(kBinThreads)
 entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order, int64_t n,
              const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
-             const uint32_t* __restrict__ escan, const uint32_t* __restrict__ pscan, const uint32_t* __restrict__ row_start,
-             const uint32_t* __restrict__ first_slice, uint32_t capacity,
-             uint32_t* __restrict__ ent_id, uint32_t* __restrict__ ent_pp,
+             const uint32_t* __restrict__ escan, const uint32_t* __restrict__ pscan,
+             const uint32_t* __restrict__ row_start, const uint32_t* __restrict__ first_slice,
+             uint32_t capacity, uint32_t* __restrict__ ent_id, uint32_t* __restrict__ ent_pp,
              uint32_t* __restrict__ ent_x, uint4* __restrict__ slice_desc,
              uint32_t* __restrict__ slice_e1) {
-    __shared__ uint32_t s_w[2][kBinThreads / 64];
-    __shared__ int s_lim[2][kBinThreads / 64];
+    constexpr int W = kBinThreads / 64;
     // per row: this block's first entry and pair, the row's first pair and
-    // first slice (loaded once, so the row loop never waits on memory)
+    // first slice (loaded once, so the row loop never waits on memory); per
+    // wavefront and row: the packed count, then the wavefront's first rank
     extern __shared__ uint32_t s_row[];
     const int gy = grid.gy;
     uint32_t* s_e = s_row;
     uint32_t* s_p = s_row + (gy + 1);
     uint32_t* s_rs = s_row + 2 * (gy + 1);
     uint32_t* s_fs = s_row + 3 * (gy + 1);
+    uint32_t* s_wr = s_row + 4 * (gy + 1);                  // [W][gy + 1]
     if (row_start[gy] > capacity) return;               // overflow: block-uniform
     for (int r = threadIdx.x; r <= gy; r += kBinThreads) {
         if (r < gy) {
@@ -207,7 +220,9 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
         s_rs[r] = row_start[r];
         s_fs[r] = first_slice[r];
     }
+    for (int i = threadIdx.x; i < W * (gy + 1); i += kBinThreads) s_wr[i] = 0;
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int lane = __lane_id();
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
     const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;
     const uint32_t id = s < m ? order[s] : 0u;
@@ -215,32 +230,52 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
     const uint32_t xpack = packed.x;
-    // rows the block touches
-    const int lo = wave_min(rc.yhi > rc.ylo ? rc.ylo : gy), hi = wave_max(rc.yhi);
-    if (__lane_id() == 0) {
-        s_lim[0][wv] = lo;
-        s_lim[1][wv] = hi;
+    const uint32_t unit = (w << 12) | 1u;
+    __syncthreads();
+    // difference arrays of this wavefront's packed counts over the rows
+    // (modulo 2^32; a wavefront's count of a row stays below 4096)
+    uint32_t* wr = s_wr + wv * (gy + 1);
+    if (rc.ylo < rc.yhi) {
+        atomicAdd(&wr[rc.ylo], unit);
+        atomicSub(&wr[rc.yhi], unit);
+    }
+    wave_sync_lds();
+    // prefix over the rows: lane l owns the rows [l * cpl, l * cpl + cpl)
+    const int cpl = (gy + 63) / 64;
+    uint32_t sum = 0;
+    for (int j = 0; j < cpl; ++j) {
+        const int r = lane * cpl + j;
+        if (r < gy) sum += wr[r];
+    }
+    uint32_t all;
+    uint32_t run = wave_exclusive_sum(sum, all);
+    for (int j = 0; j < cpl; ++j) {
+        const int r = lane * cpl + j;
+        if (r < gy) {
+            run += wr[r];
+            wr[r] = run;
+        }
     }
     __syncthreads();
-    int r0 = gy, r1 = 0;
-    for (int k = 0; k < kBinThreads / 64; ++k) {
-        r0 = min(r0, s_lim[0][k]);
-        r1 = max(r1, s_lim[1][k]);
+    // per row: the wavefronts' first ranks (exclusive prefix over them)
+    for (int r = threadIdx.x; r < gy; r += kBinThreads) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const uint32_t v = s_wr[k * (gy + 1) + r];
+            s_wr[k * (gy + 1) + r] = b;
+            b += v;
+        }
     }
+    __syncthreads();
+    // this wavefront's rows
+    const int r0 = wave_min(rc.yhi > rc.ylo ? rc.ylo : gy), r1 = wave_max(rc.yhi);
     for (int r = r0; r < r1; ++r) {
         const bool in = r >= rc.ylo && r < rc.yhi;
-        // block exclusive scan of (w << 12 | 1); the wave totals alternate
-        // between two buffers so one barrier per row suffices
-        uint32_t wt;
-        const uint32_t ex = wave_exclusive_sum(in ? (w << 12) | 1u : 0u, wt);
-        uint32_t* sw = s_w[r & 1];
-        if (__lane_id() == 0) sw[wv] = wt;
-        __syncthreads();
-        uint32_t before = 0;
-#pragma unroll
-        for (int k = 0; k < kBinThreads / 64 - 1; ++k) before += k < wv ? sw[k] : 0u;
+        const uint32_t x = in ? unit : 0u;
+        const uint32_t ex = wave_inclusive_sum(x) - x;
         if (in) {
-            const uint32_t rank = before + ex;
+            const uint32_t rank = wr[r] + ex;
             const uint32_t e = s_e[r] + (rank & 0xFFFu);
             const uint32_t p = s_p[r] + (rank >> 12);
             ent_id[e] = id;
@@ -304,11 +339,6 @@ __device__ __forceinline__ bool clip_entry(uint32_t pp, uint32_t xpack, uint32_t
 // the first column of each entry's part, -1 after its last, then a prefix.
 // One wavefront per slice (no block barriers), kHistThreads / 64 slices per
 // block.
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 __global__ void __launch_bounds__(kHistThreads)
 slice_hist_kernel(const uint32_t* __restrict__ ent_pp, const uint32_t* __restrict__ ent_x,
                   const uint32_t* __restrict__ first_slice, const uint32_t* __restrict__ row_start,
@@ -652,7 +682,8 @@ hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, i
     const uint32_t nblk = bin_blocks(n);
     if (nblk == 0) return hipSuccess;
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
-    entry_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy + 1) * 16, s>>>(
+    const size_t lds = size_t(grid.gy + 1) * 4 * (4 + kBinThreads / 64);
+    entry_kernel<<<dim3(nblk), dim3(kBinThreads), lds, s>>>(
         reinterpret_cast<const uint2*>(ws + L.srect), order, n, dcount, grid, nblk, u32(L.ecnt),
         u32(L.pcnt), u32(L.row_start), u32(L.first_slice), capacity, u32(L.ent_id),
         u32(L.ent_pp), u32(L.ent_x), reinterpret_cast<uint4*>(ws + L.slice_desc), u32(L.slice_e1));
