@@ -50,7 +50,7 @@ typedef enum tgs_status {
     TGS_ERR_CAPACITY = 2,    /* the workspace holds fewer pairs than required  */
     TGS_ERR_HIP = 3,         /* a HIP runtime call failed                      */
     TGS_ERR_NO_DEVICE = 4,   /* no HIP device with the requested ordinal       */
-    TGS_ERR_UNSUPPORTED = 5  /* a valid request this build does not implement  */
+    TGS_ERR_UNSUPPORTED = 5  /* a valid request the library does not implement */
 } tgs_status;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward). */
