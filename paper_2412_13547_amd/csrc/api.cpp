@@ -252,8 +252,8 @@ tgs_status enqueue_counts(uint8_t* ws, const tgs::Layout& L, const tgs::Grid& gr
     // every block's place in every row
     const uint64_t nrow = uint64_t(grid.gy) * tgs::bin_blocks(n);
     TGS_HIP(tgs::launch_counts(ws, L, *order, n, kept, grid, strm));
-    TGS_HIP(tgs::exclusive_scan_u32(u32(L.ecnt), u32(L.ecnt), nrow, partials, true, strm));
-    TGS_HIP(tgs::exclusive_scan_u32(u32(L.pcnt), u32(L.pcnt), nrow, partials, true, strm));
+    TGS_HIP(tgs::exclusive_scan_u32_pair(u32(L.ecnt), u32(L.ecnt), u32(L.pcnt), u32(L.pcnt), nrow,
+                                         partials, true, strm));
     TGS_HIP(tgs::launch_row_setup(ws, L, n, grid, max_slices, strm));
     return TGS_OK;
 }

@@ -127,6 +127,11 @@ uint64_t radix_kept_offset(uint64_t count);
 // receives the total (out then has count + 1 entries).
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
                               uint64_t* partials, bool write_total, hipStream_t s);
+// The same for two arrays of one length in the same launches (partials needs
+// room for both arrays' tile sums).
+hipError_t exclusive_scan_u32_pair(const uint32_t* in0, uint32_t* out0, const uint32_t* in1,
+                                   uint32_t* out1, uint64_t count, uint64_t* partials,
+                                   bool write_total, hipStream_t s);
 uint64_t scan_partials_elems(uint64_t count);
 
 // binning (binning.hip).  The pair count lives on the device (row_start[gy]);

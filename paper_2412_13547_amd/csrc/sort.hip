@@ -170,9 +170,13 @@ __device__ __forceinline__ Out load_in(const In* in, const uint32_t* gather, uin
 
 template <typename In, typename Out>
 __global__ void __launch_bounds__(kScanThreads)
-scan_reduce(const In* __restrict__ in, const uint32_t* __restrict__ gather, uint64_t count,
-            Out* __restrict__ partials) {
+scan_reduce(const In* __restrict__ in0, const In* __restrict__ in1,
+            const uint32_t* __restrict__ gather, uint64_t count, Out* __restrict__ partials,
+            uint64_t pstride) {
+    // grid row y scans array y (in0 or in1), its tile sums at partials + y * pstride
     __shared__ Out wsum[kScanThreads / 64];
+    const In* in = blockIdx.y ? in1 : in0;
+    partials += blockIdx.y * pstride;
     const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
     Out s = 0;
     for (int it = 0; it < kScanItems; ++it) {
@@ -213,8 +217,12 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T& total) {
 
 template <typename In, typename Out>
 __global__ void __launch_bounds__(kScanThreads)
-scan_down(const In* in, const uint32_t* __restrict__ gather, uint64_t count,
-          const Out* __restrict__ partials, Out* out, bool write_total) {
+scan_down(const In* in0, const In* in1, const uint32_t* __restrict__ gather, uint64_t count,
+          const Out* __restrict__ partials, uint64_t pstride, Out* out0, Out* out1,
+          bool write_total) {
+    const In* in = blockIdx.y ? in1 : in0;
+    Out* out = blockIdx.y ? out1 : out0;
+    partials += blockIdx.y * pstride;
     // blocked arrangement: thread t owns items [t*16, t*16 + 16) of the tile
     const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
     Out v[kScanItems];
@@ -239,14 +247,23 @@ scan_down(const In* in, const uint32_t* __restrict__ gather, uint64_t count,
     if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = carry + total;
 }
 
+// One or two arrays of the same length (in1/out1 null: one); the second
+// array's tile sums follow the first's in partials.
 template <typename In, typename Out>
 hipError_t exclusive_scan(const In* in, const uint32_t* gather, Out* out, uint64_t count,
-                          Out* partials, bool write_total, hipStream_t s) {
+                          Out* partials, bool write_total, hipStream_t s,
+                          const In* in1 = nullptr, Out* out1 = nullptr) {
     const uint64_t nb = (count + kScanTile - 1) / kScanTile;
     if (nb == 0) return hipSuccess;
-    scan_reduce<In, Out><<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, gather, count, partials);
-    scan_down<In, Out><<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, gather, count, partials,
-                                                                         out, write_total);
+    const unsigned rows = in1 ? 2u : 1u;
+    if (!in1) {
+        in1 = in;
+        out1 = out;
+    }
+    scan_reduce<In, Out><<<dim3(unsigned(nb), rows), dim3(kScanThreads), 0, s>>>(
+        in, in1, gather, count, partials, nb);
+    scan_down<In, Out><<<dim3(unsigned(nb), rows), dim3(kScanThreads), 0, s>>>(
+        in, in1, gather, count, partials, nb, out, out1, write_total);
     return hipGetLastError();
 }
 
@@ -280,6 +297,19 @@ uint64_t radix_counts_elems(uint64_t count) {
 }
 
 int radix_sort_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
+
+hipError_t exclusive_scan_u32_pair(const uint32_t* in0, uint32_t* out0, const uint32_t* in1,
+                                   uint32_t* out1, uint64_t count, uint64_t* partials,
+                                   bool write_total, hipStream_t s) {
+    if (count == 0) {
+        if (!write_total) return hipSuccess;
+        hipError_t e = fill_u32(out0, 0u, 1, s);
+        return e != hipSuccess ? e : fill_u32(out1, 0u, 1, s);
+    }
+    return exclusive_scan<uint32_t, uint32_t>(in0, nullptr, out0, count,
+                                              reinterpret_cast<uint32_t*>(partials), write_total, s,
+                                              in1, out1);
+}
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,
                               uint64_t* partials, bool write_total, hipStream_t s) {
