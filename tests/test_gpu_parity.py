@@ -41,6 +41,10 @@ CASES = {
     "sh1-150x130-d4-o32-T32": (lambda: _small(3, 250, 150, 130, 1), 4, 3, 2, 32, (0.0, 0.0, 0.0)),
     "sh3-96x64-d1-T8": (lambda: _small(4, 300, 96, 64, 3), 1, 0, 0, 8, (0.0, 0.5, 0.0)),
     "sh0-333x200-d2-o11-T16": (lambda: _small(5, 600, 333, 200, 0), 2, 1, 1, 16, (0.0, 0.0, 0.0)),
+    # wide grids: 263 tile columns (5 column groups of the scatter, one part
+    # each) and the 1024-column maximum (16 groups, 1024 threads)
+    "sh1-2100x40-d1-T8": (lambda: _small(6, 400, 2100, 40, 1), 1, 0, 0, 8, (0.0, 0.0, 0.0)),
+    "sh0-8192x24-d1-T8": (lambda: _small(7, 500, 8192, 24, 0), 1, 0, 0, 8, (0.0, 0.0, 0.0)),
 }
 _CACHE = {}
 
