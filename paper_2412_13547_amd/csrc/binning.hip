@@ -647,6 +647,10 @@ size_t scatter_lds_bytes(int gx) {
     return size_t(kSlice) * 8 + waves * kListLen * 8 + waves * 65 * 4 + size_t(sh.groups) * 4;
 }
 
+// Dynamic LDS of the entry kernel for gy tile rows: four row tables and
+// one row table per wavefront.
+size_t entry_lds_bytes(int gy) { return size_t(gy + 1) * 4 * (4 + kBinThreads / 64); }
+
 }  // namespace
 
 uint32_t bin_blocks(int64_t n) { return uint32_t((n + kBinThreads - 1) / kBinThreads); }
@@ -682,8 +686,7 @@ hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, i
     const uint32_t nblk = bin_blocks(n);
     if (nblk == 0) return hipSuccess;
     auto u32 = [&](uint64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
-    const size_t lds = size_t(grid.gy + 1) * 4 * (4 + kBinThreads / 64);
-    entry_kernel<<<dim3(nblk), dim3(kBinThreads), lds, s>>>(
+    entry_kernel<<<dim3(nblk), dim3(kBinThreads), entry_lds_bytes(grid.gy), s>>>(
         reinterpret_cast<const uint2*>(ws + L.srect), order, n, dcount, grid, nblk, u32(L.ecnt),
         u32(L.pcnt), u32(L.row_start), u32(L.first_slice), capacity, u32(L.ent_id),
         u32(L.ent_pp), u32(L.ent_x), reinterpret_cast<uint4*>(ws + L.slice_desc), u32(L.slice_e1));
@@ -693,8 +696,13 @@ hipError_t launch_entries(uint8_t* ws, const Layout& L, const uint32_t* order, i
 hipError_t prepare_binning_kernels() {
     size_t most = 0;
     for (int gx = 1; gx <= kMaxCols; gx += 64) most = std::max(most, scatter_lds_bytes(gx));
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&slice_scatter_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(most));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&slice_scatter_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(most));
+    if (e != hipSuccess) return e;
+    // the row tables of the tallest grid the API accepts (4 kMaxCols rows)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&entry_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(entry_lds_bytes(4 * kMaxCols)));
 }
 
 hipError_t launch_col_sort(uint8_t* ws, const Layout& L, const Grid& grid, uint64_t slices,

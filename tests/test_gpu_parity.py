@@ -45,6 +45,9 @@ CASES = {
     # each) and the 1024-column maximum (16 groups, 1024 threads)
     "sh1-2100x40-d1-T8": (lambda: _small(6, 400, 2100, 40, 1), 1, 0, 0, 8, (0.0, 0.0, 0.0)),
     "sh0-8192x24-d1-T8": (lambda: _small(7, 500, 8192, 24, 0), 1, 0, 0, 8, (0.0, 0.0, 0.0)),
+    # tall grids: 263 tile rows, and the 4096-row maximum
+    "sh1-40x2100-d1-T8": (lambda: _small(8, 400, 40, 2100, 1), 1, 0, 0, 8, (0.0, 0.0, 0.0)),
+    "sh0-16x32768-d1-T8": (lambda: _small(9, 300, 16, 32768, 0), 1, 0, 0, 8, (0.0, 0.0, 0.0)),
 }
 _CACHE = {}
 
