@@ -212,6 +212,8 @@ tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const
     v.vals = reinterpret_cast<const uint32_t*>(ws + L.pair_vals);
     v.pair_count = reinterpret_cast<const uint32_t*>(ws + L.row_start) + grid.gy;
     v.g2d = reinterpret_cast<float*>(ws + L.grad2d);
+    v.work = reinterpret_cast<uint32_t*>(ws + L.tile_work);
+    v.order = reinterpret_cast<uint32_t*>(ws + L.tile_order);
     return v;
 }
 
@@ -321,6 +323,8 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.pair_vals = take(cap * 4);
     L.col_hist = take(hist * 4);
     L.ranges = take(uint64_t(grid.num_tiles()) * 8);
+    L.tile_work = take(uint64_t(grid.num_tiles()) * 4);
+    L.tile_order = take(uint64_t(grid.num_tiles()) * 4);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
     uint64_t most = radix_counts_elems(un);

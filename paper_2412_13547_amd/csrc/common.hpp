@@ -63,6 +63,8 @@ struct Layout {
     uint64_t pair_vals;        // uint32[capacity], Gaussian of each pair, final order
     uint64_t col_hist;         // uint32[gx * max_slices], column histograms, then scanned
     uint64_t ranges;           // uint32[num_tiles][2]
+    uint64_t tile_work;        // uint32[num_tiles], entries the forward walked per tile
+    uint64_t tile_order;       // uint32[num_tiles], the backward's tile per workgroup
     uint64_t grad2d;           // float[n][9]
     uint64_t sort_counts;      // uint32, radix digit counts, then the number of Gaussians
                                //   with tiles (at radix_kept_offset(n))
@@ -174,6 +176,9 @@ struct RasterView {
     uint32_t* n_tested;       // forward, optional: entries evaluated pixel by pixel
     const float* dL;          // backward in
     float* g2d;               // backward out (accumulated; zero it first)
+    uint32_t* work;           // forward out, optional: entries walked per tile
+    uint32_t* order;          // backward, optional: the tile of each workgroup, a
+                              //   permutation of the tiles written before the walk
 };
 struct RasterViews {
     int count;
