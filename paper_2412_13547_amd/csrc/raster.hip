@@ -606,17 +606,15 @@ bool wants_counts(const RasterViews& vt) {
 }
 
 // The backward's schedule.  A view's tiles carry very different work (the
-// entries walked before every pixel stops), and a single view's tiles are
-// all resident at once, so the dispatcher's static placement, not the
-// total, sets the time: in row-major order the SIMD with the heaviest mix
-// ends 40-60 % after the mean.  Each view's tiles are therefore ordered by
-// the entries the forward walked in them, heaviest first, in rounds of
-// `round` workgroups (the wavefront slots the dispatcher fills one per
-// SIMD), every other round reversed: each SIMD then receives one tile of
-// each weight band.  A counting sort over 256 weight buckets (exact below
-// 32, then eight per power of two) in one block per view.  Any weights
-// give a permutation of the tiles: they decide the order only, never what
-// is rendered.
+// entries walked before every pixel stops: up to 3x the mean at the 4K
+// scene), and in row-major order the heavy tiles of the image centre end
+// up unevenly on the SIMDs: the last ones finish 40-50 % after the mean.
+// The dispatcher starts workgroups in index order as slots free up, so the
+// tiles of each view are handed out heaviest first, by the entries the
+// forward walked in them (longest-processing-time-first list scheduling).
+// A counting sort over 256 weight buckets (exact below 32, then eight per
+// power of two), one block per view.  Any weights give a permutation of
+// the tiles: they decide the order only, never what is rendered.
 constexpr int kOrderBuckets = 256;
 
 __device__ __forceinline__ uint32_t weight_bucket(uint32_t w) {
@@ -625,7 +623,7 @@ __device__ __forceinline__ uint32_t weight_bucket(uint32_t w) {
     return 32u + (e - 5u) * 8u + ((w >> (e - 3u)) & 7u);         // < 248
 }
 
-__global__ void __launch_bounds__(1024) tile_order_kernel(RasterViews vt, uint32_t round) {
+__global__ void __launch_bounds__(1024) tile_order_kernel(RasterViews vt) {
     __shared__ uint32_t s_cur[kOrderBuckets];
     const RasterView& rv = vt.v[blockIdx.x];
     if (!rv.order || !rv.work) return;                           // block-uniform
@@ -654,9 +652,7 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(RasterViews vt, uint32
     __syncthreads();
     for (uint32_t t = tid; t < nt; t += blockDim.x) {
         const uint32_t pos = atomicAdd(&s_cur[weight_bucket(rv.work[t])], 1u);
-        if (pos >= nt) continue;                                 // weights changed under us
-        const uint32_t first = pos - pos % round, len = min(round, nt - first);
-        rv.order[(pos / round) & 1u ? first + (len - 1u) - (pos - first) : pos] = t;
+        if (pos < nt) rv.order[pos] = t;                         // (weights changed under us)
     }
 }
 
@@ -664,16 +660,13 @@ template <int T, int PPT, int B>
 void launch_both(bool fwd, const RasterViews& vt, hipStream_t s) {
     const dim3 grid(vt.first_block[vt.count]), block(Shape<T, PPT>::NT);
     if (!fwd) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 1;
-        const uint32_t round = std::max(1u, uint32_t(4 * cus) / uint32_t(Shape<T, PPT>::NT / 64));
-        tile_order_kernel<<<dim3(unsigned(vt.count)), dim3(1024), 0, s>>>(vt, round);
+        tile_order_kernel<<<dim3(unsigned(vt.count)), dim3(1024), 0, s>>>(vt);
+        raster_bwd_kernel<T, PPT, B><<<grid, block, 0, s>>>(vt);
+    } else if (wants_counts(vt)) {
+        raster_fwd_kernel<T, PPT, B, true><<<grid, block, 0, s>>>(vt);
+    } else {
+        raster_fwd_kernel<T, PPT, B, false><<<grid, block, 0, s>>>(vt);
     }
-    if (!fwd) raster_bwd_kernel<T, PPT, B><<<grid, block, 0, s>>>(vt);
-    else if (wants_counts(vt)) raster_fwd_kernel<T, PPT, B, true><<<grid, block, 0, s>>>(vt);
-    else raster_fwd_kernel<T, PPT, B, false><<<grid, block, 0, s>>>(vt);
 }
 
 template <int T, int PPT>
