@@ -73,7 +73,7 @@ class tgs_state(C.Structure):
                 ("off_depth_order", C.c_uint64),
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
                 ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64),
-                ("off_depth_count", C.c_uint64)]
+                ("off_depth_count", C.c_uint64), ("off_tile_work", C.c_uint64)]
 
 
 class tgs_adam_group(C.Structure):
@@ -449,6 +449,11 @@ class View:
 
     def grad2d(self):
         return self._view(self.state.off_grad2d, self.n * 9, self._torch.float32).view(self.n, 9)
+
+    def tile_work(self):
+        """Entries the last forward walked per tile (the backward's tile order
+        weights; any values give the same results)."""
+        return self._view(self.state.off_tile_work, int(self.sizes.num_tiles), self._torch.int32)
 
 
 def _grads_struct(grads: DeviceScene) -> tgs_grads:

@@ -176,6 +176,7 @@ void publish_offsets(tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid,
     st->off_pair_vals = L.pair_vals;
     st->off_ranges = L.ranges;
     st->off_grad2d = L.grad2d;
+    st->off_tile_work = L.tile_work;
 }
 
 tgs_status use_device(tgs_context* ctx) {

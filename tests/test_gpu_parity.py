@@ -162,6 +162,42 @@ def test_depth_order_ties_and_culled():
 SPLITS = {8: (1,), 16: (1, 2, 4), 32: (2, 4)}
 
 
+@pytest.mark.parametrize("name", ["sh2-101x77-d3-o21-T8-bg", "sh1-150x130-d4-o32-T32",
+                                  "sh0-333x200-d2-o11-T16", "sh1-40x2100-d1-T8",
+                                  "sh0-16x32768-d1-T8"])
+def test_backward_tile_order_leaves_gradients_unchanged(name):
+    """The forward records per tile the entries it walked (never more than the
+    tile's pairs, none in an empty tile); the backward takes the tiles
+    heaviest first by them.  With those weights replaced by arbitrary values
+    (the order a stale or foreign workspace would give) the backward returns
+    the same gradients up to the order of the float atomics."""
+    sc, cam, tgt, ref = _case(name)
+    view, dev, image = ref["_view"], ref["_dev"], ref["_image"]
+    work = view.tile_work().cpu().to(torch.int64) & 0xFFFFFFFF
+    r = ref["ranges"].to(torch.int64)
+    span = r[:, 1] - r[:, 0]
+    assert bool((work <= span).all()), "a tile walked more entries than it holds"
+    assert bool((work[span == 0] == 0).all())
+    assert bool((work > 0).any())
+    say(f"[gpu] {name}: {int((work > 0).sum())} of {work.numel()} tiles walked, at most {int(work.max())}")
+    gen = torch.Generator().manual_seed(7)
+    for trial in range(2):
+        w = torch.randint(-2**31, 2**31 - 1, (work.numel(),), generator=gen, dtype=torch.int64)
+        if trial == 1:
+            w[::3] = -1                                          # 0xFFFFFFFF: the top bucket
+        view.tile_work().copy_(w.to(torch.int32).cuda())
+        dL = ref["dL"].cuda()
+        grads = view.backward(dev, image, dL)
+        torch.cuda.synchronize()
+        a, b = view.grad2d().cpu().to(F64), ref["grad2d"].to(F64)
+        assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, trial
+        for k in ("means", "scales", "quats", "opacities", "sh"):
+            a, b = getattr(grads, k).cpu().to(F64), ref["grads"][k].to(F64)
+            assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, (trial, k)
+    view.tile_work().copy_(work.to(torch.int32).cuda())
+    say(f"[gpu] {name}: gradients unchanged under arbitrary tile weights")
+
+
 @pytest.mark.parametrize("name", ["tiny128-d1-T16", "sh2-101x77-d3-o21-T8-bg",
                                   "sh1-150x130-d4-o32-T32", "sh0-333x200-d2-o11-T16"])
 def test_work_split_and_lds_batch_leave_results_unchanged(name):
