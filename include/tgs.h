@@ -156,10 +156,11 @@ typedef struct tgs_state {
     uint64_t off_depth_count;    /* out: uint32 on the device, m of off_depth_order;
                                          valid once a bin/sort of this state has run     */
     uint64_t off_tile_work;      /* out: uint32[num_tiles], the entries the last forward
-                                         walked in each tile (at most the tile's pairs);
-                                         the backward takes the tiles heaviest first by
-                                         them.  Any values give the same results: they
-                                         only order the work                             */
+                                         walked in each tile (at most the tile's pairs).
+                                         The backward takes the tiles heaviest first by
+                                         them, and so does the next forward on this
+                                         workspace before it overwrites them.  Any values
+                                         give the same results: they only order the work */
 } tgs_state;
 
 /* st->pair_count after a batched bin/sort, until tgs_pair_counts reads the

@@ -265,6 +265,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     if (!locate(vt, blockIdx.x, v, tile)) return;                // block-uniform
     const RasterView& rv = vt.v[v];
     const Grid& grid = rv.grid;
+    if (rv.order)                                                // heaviest tiles first
+        tile = __builtin_amdgcn_readfirstlane(
+            int(min(rv.order[tile], uint32_t(grid.num_tiles() - 1))));
     const int tid = threadIdx.x;
     const int tx = int(tile % grid.gx), ty = int(tile / grid.gx);
     const int i0 = tx * T + S::px(tid), j0 = ty * T + S::py(tid);
@@ -605,16 +608,19 @@ bool wants_counts(const RasterViews& vt) {
     return false;
 }
 
-// The backward's schedule.  A view's tiles carry very different work (the
-// entries walked before every pixel stops: up to 3x the mean at the 4K
-// scene), and in row-major order the heavy tiles of the image centre end
-// up unevenly on the SIMDs: the last ones finish 40-50 % after the mean.
-// The dispatcher starts workgroups in index order as slots free up, so the
-// tiles of each view are handed out heaviest first, by the entries the
-// forward walked in them (longest-processing-time-first list scheduling).
-// A counting sort over 256 weight buckets (exact below 32, then eight per
-// power of two), one block per view.  Any weights give a permutation of
-// the tiles: they decide the order only, never what is rendered.
+// The rasterizers' schedule.  A view's tiles carry very different work
+// (the entries walked before every pixel stops: up to 3x the mean at the
+// 4K scene), and in row-major order the heavy tiles of the image centre
+// end up unevenly on the SIMDs: the last ones finish 40-50 % after the
+// mean.  The dispatcher starts workgroups in index order as slots free up,
+// so the tiles of each view are handed out heaviest first by the entries a
+// forward walked in them (longest-processing-time-first list scheduling):
+// the backward by those of its own forward, the forward by those the
+// previous forward on the same workspace left (the same view at another
+// phase, or the same camera at its previous visit).  A counting sort over
+// 256 weight buckets (exact below 32, then eight per power of two), one
+// block per view.  Any weights give a permutation of the tiles: they
+// decide the order only, never what is rendered.
 constexpr int kOrderBuckets = 256;
 
 __device__ __forceinline__ uint32_t weight_bucket(uint32_t w) {
@@ -663,8 +669,10 @@ void launch_both(bool fwd, const RasterViews& vt, hipStream_t s) {
         tile_order_kernel<<<dim3(unsigned(vt.count)), dim3(1024), 0, s>>>(vt);
         raster_bwd_kernel<T, PPT, B><<<grid, block, 0, s>>>(vt);
     } else if (wants_counts(vt)) {
+        tile_order_kernel<<<dim3(unsigned(vt.count)), dim3(1024), 0, s>>>(vt);
         raster_fwd_kernel<T, PPT, B, true><<<grid, block, 0, s>>>(vt);
     } else {
+        tile_order_kernel<<<dim3(unsigned(vt.count)), dim3(1024), 0, s>>>(vt);
         raster_fwd_kernel<T, PPT, B, false><<<grid, block, 0, s>>>(vt);
     }
 }

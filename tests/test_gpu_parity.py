@@ -167,10 +167,11 @@ SPLITS = {8: (1,), 16: (1, 2, 4), 32: (2, 4)}
                                   "sh0-16x32768-d1-T8"])
 def test_backward_tile_order_leaves_gradients_unchanged(name):
     """The forward records per tile the entries it walked (never more than the
-    tile's pairs, none in an empty tile); the backward takes the tiles
-    heaviest first by them.  With those weights replaced by arbitrary values
-    (the order a stale or foreign workspace would give) the backward returns
-    the same gradients up to the order of the float atomics."""
+    tile's pairs, none in an empty tile); the backward, and the next forward,
+    take the tiles heaviest first by them.  With those weights replaced by
+    arbitrary values (the order a stale or foreign workspace would give) the
+    backward returns the same gradients up to the order of the float atomics,
+    and the forward the same image and the same weights, bit for bit."""
     sc, cam, tgt, ref = _case(name)
     view, dev, image = ref["_view"], ref["_dev"], ref["_image"]
     work = view.tile_work().cpu().to(torch.int64) & 0xFFFFFFFF
@@ -194,8 +195,15 @@ def test_backward_tile_order_leaves_gradients_unchanged(name):
         for k in ("means", "scales", "quats", "opacities", "sh"):
             a, b = getattr(grads, k).cpu().to(F64), ref["grads"][k].to(F64)
             assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, (trial, k)
+        # the forward takes its order from the weights left in the workspace
+        view.tile_work().copy_(w.to(torch.int32).cuda())
+        img = torch.empty_like(image)
+        view.raster_fwd(img)
+        torch.cuda.synchronize()
+        assert torch.equal(img.cpu(), ref["image"]), trial
+        assert torch.equal((view.tile_work().cpu().to(torch.int64) & 0xFFFFFFFF), work), trial
     view.tile_work().copy_(work.to(torch.int32).cuda())
-    say(f"[gpu] {name}: gradients unchanged under arbitrary tile weights")
+    say(f"[gpu] {name}: image and gradients unchanged under arbitrary tile weights")
 
 
 @pytest.mark.parametrize("name", ["tiny128-d1-T16", "sh2-101x77-d3-o21-T8-bg",
