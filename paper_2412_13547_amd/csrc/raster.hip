@@ -6,7 +6,8 @@
 // position d i + o, so no thread is spent on an unrendered pixel).  One launch
 // covers the tiles of up to kMaxViews views (a view table passed by value):
 // workgroups are laid out view after view, so a batch of views of uneven size
-// is balanced by the hardware dispatcher like one big image.  16x16 and 8x8
+// is balanced by the hardware dispatcher like one big image, and within a
+// view they take the tiles heaviest first (the schedule below).  16x16 and 8x8
 // tiles give one pixel per thread, 32x32 tiles a 2x2 block per thread.  The
 // tile's list is staged through LDS B splat records at a time; every pixel
 // walks it front to back (Sec. 3 Eq. 2).
@@ -150,8 +151,9 @@ __device__ __forceinline__ uint32_t wave_mask(const float4 ga, float qc, float t
     return mask;
 }
 
-// Which view and tile workgroup b works on: the views' workgroups are laid
-// out one view after the other, tiles row-major within a view.
+// Which view workgroup b works on, and its index within the view: the
+// views' workgroups are laid out one view after the other (the index is the
+// tile itself unless the view carries a tile order).
 __device__ __forceinline__ bool locate(const RasterViews& vt, uint32_t b, int& v, int64_t& tile) {
     if (b >= vt.first_block[vt.count]) return false;
     v = 0;
