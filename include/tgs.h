@@ -23,11 +23,11 @@
  *    H_ds = ceil((H - o_y) / d) pixels; downsampled pixel (i, j) is rendered
  *    at full-resolution pixel (d i + o_x, d j + o_y), whose centre is at those
  *    integer coordinates.
- *  - Device work is enqueued on the given stream; calls return before it
- *    finishes, except tgs_forward / tgs_bin_sort, which read the pair count
- *    back to the host once (see tgs_bin_sort), and tgs_pair_counts.  The
- *    batched calls (tgs_batch_*) never synchronise, so a whole fitting step
- *    of several views can be captured in one HIP graph.
+ *  - Device work is enqueued on the given stream and calls return before it
+ *    finishes; no call synchronises except tgs_pair_counts and, when the
+ *    caller opts in with TGS_SYNC_CHECK in tgs_options.flags, tgs_bin_sort /
+ *    tgs_forward (see tgs_bin_sort).  Without that flag a whole fitting step,
+ *    single-view or batched, can be captured in one HIP graph.
  *  - Arguments are validated on the host before any HIP call; a failing call
  *    has enqueued nothing.  No C++ exception crosses this interface.
  *    tgs_last_error() returns a thread-local description of the last failure.
@@ -58,7 +58,8 @@ typedef struct tgs_camera {
     int32_t width, height;   /* full-resolution image size in pixels (> 0)     */
     float fx, fy, cx, cy;    /* focal lengths and principal point, full-res px */
     float world_to_cam[12];  /* row-major 3x4 [R | t]: x_cam = R x_world + t    */
-    float near_z;            /* Gaussians with camera depth <= near_z are culled */
+    float near_z;            /* Gaussians with camera depth <= near_z are culled;
+                                positive and finite (else TGS_ERR_INVALID_ARG) */
 } tgs_camera;
 
 /* Dilation pattern of Sec. 4.1: stride d >= 1, 0 <= off_x, off_y < d.
@@ -91,8 +92,18 @@ typedef struct tgs_options {
                                 2, 4), or 0 for the default of the tile size.
                                 Speed only; results do not depend on it.        */
     float bg[3];             /* background colour added with the final T         */
-    uint32_t flags;          /* must be 0                                        */
+    uint32_t flags;          /* 0 or TGS_SYNC_CHECK; other bits are invalid      */
 } tgs_options;
+
+/* tgs_options.flags: tgs_bin_sort (and tgs_forward) read the pair count back
+ * (one stream synchronisation) and report TGS_ERR_CAPACITY at once.  Without
+ * it the count stays on the device (see tgs_bin_sort). */
+#define TGS_SYNC_CHECK 1u
+
+/* Pair capacity limit of one view: the device pair count is a saturating
+ * uint32, so 2^32 - 1 or more pairs in one view cannot be represented; such a
+ * view is reported as TGS_ERR_UNSUPPORTED (it renders the background). */
+#define TGS_MAX_PAIR_CAPACITY 4294967294ull
 
 /* Gradients, same layout as the parameters; every array is overwritten. */
 typedef struct tgs_grads {
@@ -226,9 +237,19 @@ tgs_status tgs_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, const tg
  * rasterizer"): one pair per (Gaussian, overlapped tile), sorted by the key
  * (tile id, float32 depth bits), equal keys in ascending Gaussian index, and
  * the [start, end) range of every tile.  Requires tgs_preprocess_fwd on the
- * same state.  Reads the pair count back to the host (one stream
- * synchronisation); if it exceeds pair_capacity nothing more is enqueued,
- * st->pair_count holds the required count and TGS_ERR_CAPACITY is returned. */
+ * same state.
+ * Default (opt->flags without TGS_SYNC_CHECK): asynchronous.  The pair count
+ * stays on the device (st->off_pair_count) and st->pair_count is set to
+ * TGS_PAIR_COUNT_PENDING; when the count exceeds pair_capacity no pair is
+ * written, every tile range is empty (the raster stages render the
+ * background and backpropagate zero), and tgs_pair_counts later reports
+ * TGS_ERR_CAPACITY with the required count.
+ * With TGS_SYNC_CHECK: the count is read back to the host (one stream
+ * synchronisation) into st->pair_count; if it exceeds pair_capacity nothing
+ * more is enqueued and TGS_ERR_CAPACITY is returned.
+ * Either way 2^32 - 1 or more pairs give TGS_ERR_UNSUPPORTED (at once, or
+ * from tgs_pair_counts); pair_capacity above TGS_MAX_PAIR_CAPACITY is
+ * TGS_ERR_UNSUPPORTED. */
 tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
                         const tgs_dilation* dil, const tgs_options* opt, tgs_state* st,
                         void* stream);
@@ -371,8 +392,11 @@ tgs_status tgs_batch_backward(tgs_context* ctx, const tgs_gaussians* g, int32_t 
                               float* col_stat, uint8_t* visible, void* stream);
 
 /* Reads the device pair count of every state back (one stream
- * synchronisation) into states[v].pair_count.  Returns TGS_ERR_CAPACITY if
- * any count exceeds its pair_capacity (that view rendered nothing). */
+ * synchronisation) into states[v].pair_count, after a batched or an
+ * asynchronous single-view bin/sort.  Returns TGS_ERR_CAPACITY if any count
+ * exceeds its pair_capacity (that view rendered nothing), and
+ * TGS_ERR_UNSUPPORTED if a view reached 2^32 - 1 pairs (its count reads
+ * 4294967295). */
 tgs_status tgs_pair_counts(tgs_context* ctx, int32_t views, tgs_state* states, void* stream);
 
 /* ---- Fused Adam step (the optimiser of the fitting loop that follows

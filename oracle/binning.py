@@ -15,8 +15,11 @@ Readings:
   * r_ds = r / d is kept real (no rounding); r itself is an integer.
   * Downsampled size: W_ds = ceil((W - o_x) / d), H_ds = ceil((H - o_y) / d);
     tile grid G_x = ceil(W_ds / T), G_y = ceil(H_ds / T).
-  * Occupied tiles: every tile holding a downsampled pixel centre inside the
-    box [u_ds - r_ds, u_ds + r_ds] x [v_ds - r_ds, v_ds + r_ds]:
+  * Occupied tiles: every tile whose span of downsampled coordinates,
+    [t T, (t + 1) T) per axis, intersects the box
+    [u_ds - r_ds, u_ds + r_ds] x [v_ds - r_ds, v_ds + r_ds] (interval
+    intersection; a tile may qualify without holding a pixel centre inside
+    the box, e.g. u_ds - r_ds = 15.5 with T = 16 includes tile 0):
         x_lo = clamp(floor((u_ds - r_ds) / T), 0, G_x)
         x_hi = clamp(floor((u_ds + r_ds) / T) + 1, 0, G_x)      (exclusive)
     evaluated in IEEE double, in exactly this order of operations.

@@ -31,6 +31,8 @@ MAX_ADAM_GROUPS = 8
 
 MAX_VIEWS = 16
 PAIR_COUNT_PENDING = (1 << 64) - 1
+SYNC_CHECK = 1                      # tgs_options.flags: synchronous capacity check
+MAX_PAIR_CAPACITY = (1 << 32) - 2
 
 
 class tgs_camera(C.Structure):
@@ -197,14 +199,15 @@ def dilation_struct(stride=1, off_x=0, off_y=0) -> tgs_dilation:
     return tgs_dilation(int(stride), int(off_x), int(off_y))
 
 
-def options_struct(tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0, pixels_per_thread=0) -> tgs_options:
+def options_struct(tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0, pixels_per_thread=0,
+                   flags=0) -> tgs_options:
     o = tgs_options()
     o.tile = int(tile)
     o.lds_batch = int(lds_batch)
     o.pixels_per_thread = int(pixels_per_thread)
     for k in range(3):
         o.bg[k] = float(bg[k])
-    o.flags = 0
+    o.flags = int(flags)
     return o
 
 
@@ -302,13 +305,18 @@ def default_launch(tile: int) -> tuple[int, int]:
 class View:
     """One camera + dilation pattern with its workspace (device memory owned by torch).
 
-    ``pair_capacity`` grows on demand (a forward that needs more pairs than
-    the workspace holds is re-run once with a larger workspace).
+    With ``sync_check`` (the default here) the binning reads the pair count
+    back and ``pair_capacity`` grows on demand: a forward that needs more
+    pairs than the workspace holds is re-run once with a larger workspace.
+    Without it every call stays asynchronous (the library's default; the
+    step can be captured in a graph): size the workspace first with
+    ``fit_capacity``, and read the count with ``pair_count()``.
     """
 
     def __init__(self, ctx: Context, n: int, cam, stride=1, off_x=0, off_y=0, tile=16,
                  bg=(0.0, 0.0, 0.0), pair_capacity: int | None = None, lds_batch: int = 0,
-                 state: tgs_state | None = None, pixels_per_thread: int = 0):
+                 state: tgs_state | None = None, pixels_per_thread: int = 0,
+                 sync_check: bool = True):
         import torch
         self.ctx = ctx
         self.n = int(n)
@@ -316,6 +324,8 @@ class View:
         self.cam_s = camera_struct(cam)
         self.dil = dilation_struct(stride, off_x, off_y)
         self.opt = options_struct(tile, bg, lds_batch, pixels_per_thread)
+        self.opt_sync = options_struct(tile, bg, lds_batch, pixels_per_thread, SYNC_CHECK)
+        self.sync_check = bool(sync_check)
         self.state = state if state is not None else tgs_state()
         self.workspace = None
         self.sizes = query_sizes(self.n, self.cam_s, self.dil, self.opt, 0)
@@ -350,18 +360,48 @@ class View:
                                        C.byref(self.dil), C.byref(self.opt), C.byref(self.state),
                                        _stream(stream)))
 
-    def bin_sort(self, scene: DeviceScene, stream=None, grow: bool = True):
+    def bin_sort(self, scene: DeviceScene, stream=None, grow: bool = True, sync: bool | None = None):
+        """Pairs, sort and ranges.  sync (default: the view's sync_check) reads
+        the count back and, with grow, enlarges the workspace and repeats."""
         g = scene.struct()
+        sync = self.sync_check if sync is None else bool(sync)
+        opt = self.opt_sync if sync else self.opt
         st = lib().tgs_bin_sort(self.ctx.handle, C.byref(g), C.byref(self.cam_s), C.byref(self.dil),
-                                C.byref(self.opt), C.byref(self.state), _stream(stream))
-        if st == TGS_ERR_CAPACITY and grow:
+                                C.byref(opt), C.byref(self.state), _stream(stream))
+        if sync and st == TGS_ERR_CAPACITY and grow:
             need = int(self.state.pair_count)
             self.reserve(int(need * 1.25) + 1024)
             self.preprocess_fwd(scene, stream)
             st = lib().tgs_bin_sort(self.ctx.handle, C.byref(g), C.byref(self.cam_s),
-                                    C.byref(self.dil), C.byref(self.opt), C.byref(self.state),
+                                    C.byref(self.dil), C.byref(opt), C.byref(self.state),
                                     _stream(stream))
         check(st)
+
+    def pair_count(self, stream=None) -> int:
+        """The pair count of the last bin/sort; reads the device count back
+        (synchronises) when it is pending.  Raises TgsError when the pairs did
+        not fit the workspace (the count is then in state.pair_count)."""
+        if int(self.state.pair_count) == PAIR_COUNT_PENDING:
+            check(lib().tgs_pair_counts(self.ctx.handle, 1, C.byref(self.state), _stream(stream)))
+        elif int(self.state.pair_count) > int(self.state.pair_capacity):
+            raise TgsError(TGS_ERR_CAPACITY, "pairs exceed the workspace capacity")
+        return int(self.state.pair_count)
+
+    def fit_capacity(self, scene: DeviceScene, slack: float = 1.1, tries: int = 4) -> int:
+        """Run asynchronous forwards until the pairs fit the workspace; returns
+        the count.  The workspace may be re-allocated, so capture graphs only
+        after this."""
+        for _ in range(tries):
+            self.preprocess_fwd(scene)
+            self.bin_sort(scene, sync=False)
+            lib().tgs_pair_counts(self.ctx.handle, 1, C.byref(self.state), _stream(None))
+            need = int(self.state.pair_count)
+            if need >= (1 << 32) - 1:
+                raise TgsError(TGS_ERR_UNSUPPORTED, "2^32 - 1 or more pairs in one view")
+            if need <= int(self.state.pair_capacity):
+                return need
+            self.reserve(min(int(need * slack) + 4096, MAX_PAIR_CAPACITY))
+        raise TgsError(TGS_ERR_CAPACITY, "pair capacity did not converge")
 
     def raster_fwd(self, image, t_final=None, last_contrib=None, n_eval=None, n_blend=None,
                    stream=None):
@@ -441,7 +481,7 @@ class View:
         return self._view(self.state.off_depth_order, min(max(m, 0), self.n), self._torch.int32)
 
     def pair_vals(self):
-        return self._view(self.state.off_pair_vals, int(self.state.pair_count), self._torch.int32)
+        return self._view(self.state.off_pair_vals, self.pair_count(), self._torch.int32)
 
     def ranges(self):
         nt = int(self.sizes.num_tiles)

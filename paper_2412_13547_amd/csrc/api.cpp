@@ -19,6 +19,11 @@ constexpr size_t kPinnedBytes = 4 * (tgs::kMaxCols * 4 + 8);   // row starts of 
 // Streams beside the caller's on which the batched binning runs views
 // concurrently (forked from and joined into the caller's stream).
 constexpr int kAuxStreams = 3;
+// The device pair count is a saturating uint32 (UINT32_MAX means "2^32 - 1
+// pairs or more"); a capacity below it tells an overflow from a fit.
+constexpr uint64_t kSaturated = UINT32_MAX;
+constexpr uint64_t kMaxPairCapacity = TGS_MAX_PAIR_CAPACITY;
+static_assert(kMaxPairCapacity == kSaturated - 1, "capacity limit below the saturated count");
 }
 
 struct tgs_context {
@@ -61,8 +66,12 @@ tgs_status check_camera(const tgs_camera* cam) {
         return fail(TGS_ERR_INVALID_ARG, "camera size %dx%d must be positive", cam->width, cam->height);
     if (!(cam->fx > 0) || !(cam->fy > 0) || !is_finite(cam->fx) || !is_finite(cam->fy))
         return fail(TGS_ERR_INVALID_ARG, "focal lengths must be positive and finite");
-    if (!is_finite(cam->cx) || !is_finite(cam->cy) || !is_finite(cam->near_z))
-        return fail(TGS_ERR_INVALID_ARG, "principal point and near_z must be finite");
+    if (!is_finite(cam->cx) || !is_finite(cam->cy))
+        return fail(TGS_ERR_INVALID_ARG, "principal point must be finite");
+    // depth keys are float bits (their integer order is the depth order only
+    // for positive depths) and the projection divides by the depth
+    if (!(cam->near_z > 0.0f) || !is_finite(cam->near_z))
+        return fail(TGS_ERR_INVALID_ARG, "near_z must be positive and finite");
     for (int k = 0; k < 12; ++k)
         if (!is_finite(cam->world_to_cam[k])) return fail(TGS_ERR_INVALID_ARG, "world_to_cam is not finite");
     return TGS_OK;
@@ -94,7 +103,9 @@ tgs_status check_options(const tgs_options* opt) {
         return fail(TGS_ERR_INVALID_ARG,
                     "pixels_per_thread %d not available for tile %d (8: 1; 16: 1, 2, 4; 32: 2, 4)",
                     ppt, opt->tile);
-    if (opt->flags != 0) return fail(TGS_ERR_INVALID_ARG, "option flags must be 0");
+    if ((opt->flags & ~uint32_t(TGS_SYNC_CHECK)) != 0)
+        return fail(TGS_ERR_INVALID_ARG, "option flags 0x%x: only TGS_SYNC_CHECK is defined",
+                    opt->flags);
     for (int c = 0; c < 3; ++c)
         if (!is_finite(opt->bg[c])) return fail(TGS_ERR_INVALID_ARG, "background is not finite");
     return TGS_OK;
@@ -134,6 +145,8 @@ tgs_status check_state(const tgs_state* st, int64_t n, const tgs::Grid& grid, tg
     if (!st->workspace) return fail(TGS_ERR_INVALID_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(st->workspace) % 256 != 0)
         return fail(TGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (st->pair_capacity > kMaxPairCapacity)
+        return fail(TGS_ERR_UNSUPPORTED, "pair capacity above 2^32 - 2");
     *L = tgs::make_layout(n, st->pair_capacity, grid);
     if (st->workspace_bytes < L->total)
         return fail(TGS_ERR_INVALID_ARG, "workspace of %llu bytes < %llu required",
@@ -441,8 +454,8 @@ tgs_status tgs_query_sizes(int64_t n, const tgs_camera* cam, const tgs_dilation*
     tgs_status s = check_common(cam, dil, opt);
     if (s != TGS_OK) return s;
     if (!opt) return fail(TGS_ERR_INVALID_ARG, "options is NULL");
-    if (pair_capacity > uint64_t(UINT32_MAX))
-        return fail(TGS_ERR_UNSUPPORTED, "pair capacity above 2^32 - 1");
+    if (pair_capacity > kMaxPairCapacity)
+        return fail(TGS_ERR_UNSUPPORTED, "pair capacity above 2^32 - 2");
     const tgs::Grid g = tgs::make_grid(*cam, *dil, opt->tile);
     if ((s = check_grid(g)) != TGS_OK) return s;
     const tgs::Layout L = tgs::make_layout(n, pair_capacity, g);
@@ -498,21 +511,35 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
     const uint64_t max_slices = tgs::bin_max_slices(st->pair_capacity, grid.gy);
     if ((s = enqueue_counts(ws, L, grid, g->n, max_slices, strm, &dres, &order, &dcount)) != TGS_OK)
         return s;
-    // row starts (and the pair count) back to the host: the column sort is
-    // then launched with exactly as many slices as there are
-    TGS_HIP(hipMemcpyAsync(ctx->pinned, ws + L.row_start, (uint64_t(grid.gy) + 1) * 4,
-                           hipMemcpyDeviceToHost, strm));
-    TGS_HIP(hipStreamSynchronize(strm));
-    const uint32_t* rs = reinterpret_cast<const uint32_t*>(ctx->pinned);
-    const uint64_t P = rs[grid.gy];
-    uint64_t slices = 0;
-    for (int ty = 0; ty < grid.gy; ++ty) slices += (uint64_t(rs[ty + 1] - rs[ty]) + tgs::kSlice - 1) / tgs::kSlice;
-    st->pair_count = P;
+    uint64_t slices = max_slices;
     st->key_bits = 0;
-    publish_offsets(st, L, grid, g->n, order, ws);
-    if (P > st->pair_capacity)
-        return fail(TGS_ERR_CAPACITY, "%llu pairs needed, capacity %llu", (unsigned long long)P,
-                    (unsigned long long)st->pair_capacity);
+    if (opt->flags & TGS_SYNC_CHECK) {
+        // row starts (and the pair count) back to the host: a capacity
+        // error can be reported now, and the column sort is launched with
+        // exactly as many slices as there are
+        TGS_HIP(hipMemcpyAsync(ctx->pinned, ws + L.row_start, (uint64_t(grid.gy) + 1) * 4,
+                               hipMemcpyDeviceToHost, strm));
+        TGS_HIP(hipStreamSynchronize(strm));
+        const uint32_t* rs = reinterpret_cast<const uint32_t*>(ctx->pinned);
+        const uint64_t P = rs[grid.gy];
+        st->pair_count = P;
+        publish_offsets(st, L, grid, g->n, order, ws);
+        if (P >= kSaturated)
+            return fail(TGS_ERR_UNSUPPORTED, "2^32 - 1 or more pairs in one view");
+        if (P > st->pair_capacity)
+            return fail(TGS_ERR_CAPACITY, "%llu pairs needed, capacity %llu",
+                        (unsigned long long)P, (unsigned long long)st->pair_capacity);
+        slices = 0;
+        for (int ty = 0; ty < grid.gy; ++ty)
+            slices += (uint64_t(rs[ty + 1] - rs[ty]) + tgs::kSlice - 1) / tgs::kSlice;
+    } else {
+        // asynchronous: the count stays on the device; the emission and the
+        // column sort are launched for the capacity's bound of slices and do
+        // nothing when the count exceeds the capacity (the view then renders
+        // the background); tgs_pair_counts reads the count later
+        st->pair_count = TGS_PAIR_COUNT_PENDING;
+        publish_offsets(st, L, grid, g->n, order, ws);
+    }
     if ((s = enqueue_emit(ws, L, grid, g->n, order, dcount, slices, uint32_t(st->pair_capacity),
                           strm)) != TGS_OK)
         return s;
@@ -651,8 +678,8 @@ tgs_status check_views(int64_t n, int32_t views, const tgs_camera* cams, const t
         grids[v] = tgs::make_grid(cams[v], dils[v], opt->tile);
         if ((s = check_state(&states[v], n, grids[v], &Ls[v])) != TGS_OK)
             return fail(s, "view %d: %s", v, g_error.c_str());
-        if (states[v].pair_capacity > uint64_t(UINT32_MAX))
-            return fail(TGS_ERR_UNSUPPORTED, "view %d: pair capacity above 2^32 - 1", v);
+        if (states[v].pair_capacity > kMaxPairCapacity)
+            return fail(TGS_ERR_UNSUPPORTED, "view %d: pair capacity above 2^32 - 2", v);
     }
     // workspaces must be disjoint: the views are processed concurrently
     for (int a = 0; a < views; ++a) {
@@ -923,11 +950,14 @@ tgs_status tgs_pair_counts(tgs_context* ctx, int32_t views, tgs_state* states, v
         TGS_HIP(hipMemcpyAsync(pin + v, static_cast<uint8_t*>(states[v].workspace) + states[v].off_pair_count,
                                4, hipMemcpyDeviceToHost, strm));
     TGS_HIP(hipStreamSynchronize(strm));
-    int over = -1;
+    int over = -1, huge = -1;
     for (int v = 0; v < views; ++v) {
         states[v].pair_count = pin[v];
         if (pin[v] > states[v].pair_capacity && over < 0) over = v;
+        if (pin[v] >= kSaturated && huge < 0) huge = v;
     }
+    if (huge >= 0)
+        return fail(TGS_ERR_UNSUPPORTED, "view %d: 2^32 - 1 or more pairs in one view", huge);
     if (over >= 0)
         return fail(TGS_ERR_CAPACITY, "view %d: %llu pairs needed, capacity %llu", over,
                     (unsigned long long)states[over].pair_count,

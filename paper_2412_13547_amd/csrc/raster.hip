@@ -534,8 +534,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     }
 }
 
-// L1 loss of Eq. 1-2 over the dilated image and its gradient, for a table
-// of views in one launch.  A view's blocks walk rows of its strided image
+// L1 photometric loss of the rendered pixels against the full-resolution
+// pixels they are rendered at (Sec. 4.1, Fig. 2: supervision from the
+// corresponding high-resolution pixels; Sec. 4.2 names the L1 loss) and its
+// gradient, for a table of views in one launch.  A view's blocks walk rows of its strided image
 // (the rows of a pixel phase), so the image and dL accesses are contiguous;
 // one double atomic per block adds the block's share of the view's loss (a
 // bounded number of atomics on one address).

@@ -67,7 +67,7 @@ digit_counts(const uint32_t* __restrict__ keys, PassInput in, int shift,
 }
 
 // Forward declaration: block-wide exclusive scan (defined with the scans).
-template <typename T, int NT>
+template <typename T, int NT, bool SAT = false>
 __device__ __forceinline__ T block_exclusive_scan(T x, T& total);
 
 constexpr int kScatterThreads = 1024;
@@ -168,7 +168,20 @@ __device__ __forceinline__ Out load_in(const In* in, const uint32_t* gather, uin
     return Out(gather ? in[gather[i]] : in[i]);
 }
 
-template <typename In, typename Out>
+// a + b, or, with SAT, min(a + b, max of Out): saturating addition of
+// non-negative values is associative, so a scan built from it equals the
+// exact prefix sums wherever those fit and the maximum everywhere after.
+template <bool SAT, typename T>
+__device__ __forceinline__ T add(T a, T b) {
+    if constexpr (SAT) {
+        const T s = a + b;
+        return s < a ? T(~T(0)) : s;
+    } else {
+        return a + b;
+    }
+}
+
+template <typename In, typename Out, bool SAT>
 __global__ void __launch_bounds__(kScanThreads)
 scan_reduce(const In* __restrict__ in0, const In* __restrict__ in1,
             const uint32_t* __restrict__ gather, uint64_t count, Out* __restrict__ partials,
@@ -181,41 +194,49 @@ scan_reduce(const In* __restrict__ in0, const In* __restrict__ in1,
     Out s = 0;
     for (int it = 0; it < kScanItems; ++it) {
         const uint64_t idx = base + uint64_t(it) * kScanThreads + threadIdx.x;
-        if (idx < count) s += load_in<In, Out>(in, gather, idx);
+        if (idx < count) s = add<SAT>(s, load_in<In, Out>(in, gather, idx));
     }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    for (int o = 32; o > 0; o >>= 1) s = add<SAT>(s, Out(__shfl_xor(s, o)));
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         Out t = 0;
-        for (int w = 0; w < kScanThreads / 64; ++w) t += wsum[w];
+        for (int w = 0; w < kScanThreads / 64; ++w) t = add<SAT>(t, wsum[w]);
         partials[blockIdx.x] = t;
     }
 }
 
 // Block-wide exclusive scan of one value per thread; returns the block total.
-template <typename T, int NT>
+template <typename T, int NT, bool SAT>
 __device__ __forceinline__ T block_exclusive_scan(T x, T& total) {
     __shared__ T wsum[NT / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T incl = x;
     for (int o = 1; o < 64; o <<= 1) {
         const T y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+        if (lane >= o) incl = add<SAT>(incl, y);
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     T before = 0;
     total = 0;
     for (int w = 0; w < NT / 64; ++w) {
-        if (w < wave) before += wsum[w];
-        total += wsum[w];
+        if (w < wave) before = add<SAT>(before, wsum[w]);
+        total = add<SAT>(total, wsum[w]);
     }
     __syncthreads();
-    return before + incl - x;
+    if constexpr (SAT) {
+        // the lane before's inclusive value (a saturated sum cannot be undone
+        // by subtracting x)
+        T excl = __shfl_up(incl, 1);
+        if (lane == 0) excl = 0;
+        return add<SAT>(before, excl);
+    } else {
+        return before + incl - x;
+    }
 }
 
-template <typename In, typename Out>
+template <typename In, typename Out, bool SAT>
 __global__ void __launch_bounds__(kScanThreads)
 scan_down(const In* in0, const In* in1, const uint32_t* __restrict__ gather, uint64_t count,
           const Out* __restrict__ partials, uint64_t pstride, Out* out0, Out* out1,
@@ -230,26 +251,29 @@ scan_down(const In* in0, const In* in1, const uint32_t* __restrict__ gather, uin
     for (int it = 0; it < kScanItems; ++it) {
         const uint64_t idx = base + it;
         v[it] = idx < count ? load_in<In, Out>(in, gather, idx) : Out(0);
-        s += v[it];
+        s = add<SAT>(s, v[it]);
     }
     // the sums of the tiles before this one (a few hundred at most in use)
     Out before = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads) before += partials[b];
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads)
+        before = add<SAT>(before, partials[b]);
     Out carry;
-    (void)block_exclusive_scan<Out, kScanThreads>(before, carry);
+    (void)block_exclusive_scan<Out, kScanThreads, SAT>(before, carry);
     Out total;
-    Out run = carry + block_exclusive_scan<Out, kScanThreads>(s, total);
+    Out run = add<SAT>(carry, block_exclusive_scan<Out, kScanThreads, SAT>(s, total));
     for (int it = 0; it < kScanItems; ++it) {
         const uint64_t idx = base + it;
         if (idx < count) out[idx] = run;
-        run += v[it];
+        run = add<SAT>(run, v[it]);
     }
-    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = carry + total;
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        out[count] = add<SAT>(carry, total);
 }
 
 // One or two arrays of the same length (in1/out1 null: one); the second
-// array's tile sums follow the first's in partials.
-template <typename In, typename Out>
+// array's tile sums follow the first's in partials.  With SAT the sums
+// saturate at the largest Out (see add).
+template <typename In, typename Out, bool SAT = false>
 hipError_t exclusive_scan(const In* in, const uint32_t* gather, Out* out, uint64_t count,
                           Out* partials, bool write_total, hipStream_t s,
                           const In* in1 = nullptr, Out* out1 = nullptr) {
@@ -260,9 +284,9 @@ hipError_t exclusive_scan(const In* in, const uint32_t* gather, Out* out, uint64
         in1 = in;
         out1 = out;
     }
-    scan_reduce<In, Out><<<dim3(unsigned(nb), rows), dim3(kScanThreads), 0, s>>>(
+    scan_reduce<In, Out, SAT><<<dim3(unsigned(nb), rows), dim3(kScanThreads), 0, s>>>(
         in, in1, gather, count, partials, nb);
-    scan_down<In, Out><<<dim3(unsigned(nb), rows), dim3(kScanThreads), 0, s>>>(
+    scan_down<In, Out, SAT><<<dim3(unsigned(nb), rows), dim3(kScanThreads), 0, s>>>(
         in, in1, gather, count, partials, nb, out, out1, write_total);
     return hipGetLastError();
 }
@@ -306,9 +330,9 @@ hipError_t exclusive_scan_u32_pair(const uint32_t* in0, uint32_t* out0, const ui
         hipError_t e = fill_u32(out0, 0u, 1, s);
         return e != hipSuccess ? e : fill_u32(out1, 0u, 1, s);
     }
-    return exclusive_scan<uint32_t, uint32_t>(in0, nullptr, out0, count,
-                                              reinterpret_cast<uint32_t*>(partials), write_total, s,
-                                              in1, out1);
+    return exclusive_scan<uint32_t, uint32_t, true>(in0, nullptr, out0, count,
+                                                    reinterpret_cast<uint32_t*>(partials),
+                                                    write_total, s, in1, out1);
 }
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t count,

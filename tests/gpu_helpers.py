@@ -89,12 +89,14 @@ def records_to_oracle(rec32: torch.Tensor) -> dict:
                 fovx=(flags & 16) != 0, fovy=(flags & 32) != 0)
 
 
-def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name=""):
-    """Gradient tolerance: per tensor ||d|| / ||g|| <= rel, and per element
-    |d| <= rel (|g| + rms(g)).  The element floor is tied to the typical
-    magnitude of the tensor: components that are a small difference of large
-    terms (e.g. the quaternion gradient after removing its radial part) carry
-    float32 rounding of the size of those terms, not of their own size."""
+def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name="", floor=None):
+    """The gradient bar: per tensor ||d|| / ||g|| <= rel, and per element
+    |d| <= rel (|g| + rel max|g|).
+
+    ``floor`` (optional, per element, same shape as ``want``) widens the
+    element bound by a rounding allowance derived from the magnitude of the
+    terms that cancel in that element; the callers that pass one state its
+    derivation.  The worst ratio of |d| to the bound is printed either way."""
     got = got.to(F64).flatten()
     want = want.to(F64).flatten()
     d = (got - want).abs()
@@ -103,9 +105,14 @@ def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name=""):
         assert (float(got.abs().max()) if got.numel() else 0.0) == 0.0, name
         return 0.0
     nrel = float(torch.linalg.norm(got - want) / torch.linalg.norm(want))
-    rms = float(torch.sqrt((want ** 2).mean()))
-    bad = d > rel * (want.abs() + rms)
+    bound = rel * (want.abs() + rel * gmax)
+    if floor is not None:
+        bound = bound + torch.as_tensor(floor, dtype=F64).flatten()
+    ratio = d / bound
+    worst = float(ratio.max())
+    say(f"[grad] {name}: norm-rel {nrel:.2e}, worst element {worst:.3f} of its bound")
     assert nrel <= rel, f"{name}: norm-relative error {nrel:.3e}"
+    bad = ratio > 1.0
     assert not bool(bad.any()), (f"{name}: {int(bad.sum())} elements out of bound, worst "
-                                 f"{float((d / (want.abs() + rms)).max()):.3e}")
+                                 f"{worst:.3e} of the bound")
     return nrel

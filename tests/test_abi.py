@@ -81,13 +81,20 @@ def test_bad_tile_rejected(tile):
 
 def test_bad_camera_rejected():
     out = api.tgs_sizes()
+    # near_z <= 0 would let Gaussians at depth <= 0 through: their float-bit
+    # depth keys would sort after every positive depth, and depth 0 divides
     for mutate in (lambda c: setattr(c, "width", 0), lambda c: setattr(c, "fx", -1.0),
-                   lambda c: setattr(c, "fy", float("nan"))):
+                   lambda c: setattr(c, "fy", float("nan")), lambda c: setattr(c, "near_z", 0.0),
+                   lambda c: setattr(c, "near_z", -0.2), lambda c: setattr(c, "near_z", float("inf"))):
         cam = _cam()
         mutate(cam)
         st = api.lib().tgs_query_sizes(10, C.byref(cam), C.byref(api.dilation_struct()),
                                        C.byref(api.options_struct()), 0, C.byref(out))
         assert st == api.TGS_ERR_INVALID_ARG
+    cam = _cam()
+    cam.near_z = 1e-3
+    assert api.lib().tgs_query_sizes(10, C.byref(cam), C.byref(api.dilation_struct()),
+                                     C.byref(api.options_struct()), 0, C.byref(out)) == api.TGS_OK
 
 
 def _gauss(n=10, deg=0, coeffs=1, ptr=1 << 20):
@@ -160,11 +167,35 @@ def test_bad_lds_batch_and_flags_rejected():
         st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()),
                                        C.byref(api.options_struct(16, lds_batch=lb)), 0, C.byref(out))
         assert st == api.TGS_OK
+    # TGS_SYNC_CHECK is the only defined flag
     opt = api.options_struct(16)
-    opt.flags = 1
-    st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()), C.byref(opt),
-                                   0, C.byref(out))
-    assert st == api.TGS_ERR_INVALID_ARG
+    for flags, want in ((api.SYNC_CHECK, api.TGS_OK), (2, api.TGS_ERR_INVALID_ARG),
+                        (api.SYNC_CHECK | 4, api.TGS_ERR_INVALID_ARG), (1 << 31, api.TGS_ERR_INVALID_ARG)):
+        opt.flags = flags
+        st = api.lib().tgs_query_sizes(10, C.byref(_cam()), C.byref(api.dilation_struct()),
+                                       C.byref(opt), 0, C.byref(out))
+        assert st == want, flags
+
+
+def test_pair_capacity_limit():
+    """The device pair count saturates at 2^32 - 1, so the largest capacity
+    is 2^32 - 2 (a saturated count then always reads as an overflow)."""
+    out = api.tgs_sizes()
+    lib = api.lib()
+    args = lambda cap: (10, C.byref(_cam()), C.byref(api.dilation_struct()),
+                        C.byref(api.options_struct(16)), cap, C.byref(out))
+    assert lib.tgs_query_sizes(*args(api.MAX_PAIR_CAPACITY)) == api.TGS_OK
+    assert out.workspace_bytes > 16 * api.MAX_PAIR_CAPACITY
+    assert lib.tgs_query_sizes(*args(api.MAX_PAIR_CAPACITY + 1)) == api.TGS_ERR_UNSUPPORTED
+    assert lib.tgs_query_sizes(*args((1 << 40))) == api.TGS_ERR_UNSUPPORTED
+    # the same limit on a state handed to a stage, before any device call
+    st = api.tgs_state()
+    st.workspace = 4096
+    st.workspace_bytes = 1 << 62
+    st.pair_capacity = api.MAX_PAIR_CAPACITY + 1
+    r = lib.tgs_bin_sort(None, C.byref(_gauss()), C.byref(_cam()), C.byref(api.dilation_struct()),
+                         C.byref(api.options_struct(16)), C.byref(st), None)
+    assert r == api.TGS_ERR_UNSUPPORTED and b"2^32 - 2" in lib.tgs_last_error()
 
 
 def _batch_args(nv, ws_bytes=1 << 30, stride=1 << 31):

@@ -317,14 +317,27 @@ def test_end_to_end_against_pure_oracle(name):
     frac = float((g["last_contrib"].to(torch.int64) != o["last_contrib"]).float().mean())
     say(f"[gpu] {name}: end-to-end last_contrib mismatch fraction {frac:.2e}")
     assert frac < 1e-3
-    # gradients: same signs of the L1 residual are needed for comparability
-    sg_gpu = torch.sign(g["dL"])
-    sg_o = torch.sign(o["dL_dimage"])
-    if bool((sg_gpu == sg_o).all()) and frac == 0.0:
-        for k, shape_fn in (("means", lambda t: t.T), ("scales", lambda t: t.T),
-                            ("quats", lambda t: t.T), ("opacities", lambda t: t),
-                            ("sh", lambda t: t.permute(2, 0, 1))):
-            grad_close(shape_fn(g["grads"][k]), o["grads"][k], rel=2e-3, name=f"{name} {k}")
+    # gradients, compared on every run: pixels where a float decision sits on
+    # its threshold (oracle flags), where the L1 residual's sign differs, or
+    # where the walk ended at a different entry take no upstream gradient on
+    # either side; both sides then backpropagate the same float32 values
+    same = ~o["flag"] & (torch.sign(g["dL"].to(F64)) == torch.sign(o["dL_dimage"])).all(0) & \
+        (g["last_contrib"].to(torch.int64) == o["last_contrib"])
+    masked = float((~same).float().mean())
+    say(f"[gpu] {name}: end-to-end gradient comparison, {masked:.2e} of the pixels masked")
+    assert masked < 0.01
+    dL = (o["dL_dimage"] * same.to(F64)[None]).to(torch.float32)
+    om = opipe.forward_backward(sc, cam, tgt, d, ox, oy, T, bg, dL_dimage=dL.to(F64))
+    view, dev = g["_view"], g["_dev"]
+    grads = view.backward(dev, g["_image"], dL.cuda())
+    torch.cuda.synchronize()
+    compared = 0
+    for k, shape_fn in (("means", lambda t: t.T), ("scales", lambda t: t.T),
+                        ("quats", lambda t: t.T), ("opacities", lambda t: t),
+                        ("sh", lambda t: t.permute(2, 0, 1))):
+        grad_close(shape_fn(getattr(grads, k).cpu()), om["grads"][k], name=f"{name} e2e {k}")
+        compared += 1
+    assert compared == 5
 
 
 # ---- closed forms and degenerate inputs through the whole HIP path --------
@@ -425,3 +438,35 @@ def test_capacity_growth_and_error():
     torch.cuda.synchronize()
     assert int(view.state.pair_count) == need and view.state.pair_capacity >= need
     assert bool(torch.isfinite(img).all())
+
+
+def test_pair_count_past_32_bits_is_reported_not_wrapped():
+    """1025 Gaussians that each cover all 4,194,304 tiles of a 1024 x 4096
+    tile grid (8192 x 32768 pixels, T = 8) make 1025 * 2^22 pairs, more than
+    a uint32 counts.  The device count saturates instead of wrapping (a
+    wrapped count, 2^22, would pass the capacity check and the emission
+    would write past the buffers): the synchronous bin/sort and the
+    asynchronous one with its later readback both report
+    TGS_ERR_UNSUPPORTED, and the asynchronous one leaves every range empty."""
+    from gpu_helpers import ctx
+    from paper_2412_13547_amd import api
+    n = 1025
+    cam = scenes.identity_camera(8192, 32768, 8192.0)
+    sc = _scene(np.tile([[0.0], [0.0], [3.0]], n), np.full((3, n), 4.0), np.tile([[1], [0], [0], [0]], n),
+                np.full(n, 0.5), np.full((3, n), 0.5))
+    dev = api.DeviceScene.from_scene(sc)
+    for sync in (True, False):
+        view = api.View(ctx(), n, cam, 1, 0, 0, 8, pair_capacity=5_000_000, sync_check=sync)
+        assert (view.sizes.grid_x, view.sizes.grid_y) == (1024, 4096)
+        view.preprocess_fwd(dev)
+        touched = view.tiles_touched().cpu().to(torch.int64)
+        assert int(touched.sum()) == n * (1 << 22) >= (1 << 32)
+        say(f"[gpu] {n * (1 << 22)} pairs requested (sync={sync})")
+        with pytest.raises(api.TgsError) as e:
+            view.bin_sort(dev, grow=False)
+            view.pair_count()
+        assert e.value.status == api.TGS_ERR_UNSUPPORTED
+        assert int(view.state.pair_count) == (1 << 32) - 1
+        if not sync:
+            assert int(view.ranges().abs().max()) == 0
+    torch.cuda.synchronize()
