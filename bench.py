@@ -129,6 +129,10 @@ class Runner:
         self.stride = stride
         self.ctx = api.Context(0)
         self.view = api.View(self.ctx, dev.n, cam, stride, 0, 0, tile)
+        # size the workspace once (the pairs do not depend on the phase), then
+        # step without reading the pair count back (the library's default)
+        self.view.fit_capacity(dev)
+        self.view.sync_check = False
         self.target = target
         n = dev.n
         self.grads = dev.zeros_like()
@@ -167,7 +171,7 @@ class Runner:
         rec(3)
         v.l1_grad(img, self.target, dL, self.loss)
         rec(4)
-        v.raster_bwd(img, dL)
+        v.raster_bwd(dL)
         rec(5)
         v.preprocess_bwd(self.dev, self.grads, self.pos, self.col, self.vis)
         rec(6)
@@ -360,7 +364,7 @@ def run_batched(args, api, torch, np):
         for v, img, dl, tg in zip(singles, imgs, dls, targets):
             v.forward(dev, img)
             v.l1_grad(img, tg, dl, loss)
-            v.backward(dev, img, dl, grads, pos, col, vis)
+            v.backward(dev, dl, grads, pos, col, vis)
     per_view()
     res["ms_per_view_calls"] = float(np.median(_time_events(torch, per_view, max(3, K // 2))))
     del singles, imgs, dls

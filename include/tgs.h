@@ -172,6 +172,12 @@ typedef struct tgs_state {
                                          them, and so does the next forward on this
                                          workspace before it overwrites them.  Any values
                                          give the same results: they only order the work */
+    uint64_t off_t_final;        /* out: float[H_ds][W_ds], every pixel's transmittance
+                                         after its walk, written by the last forward      */
+    uint64_t off_last_contrib;   /* out: uint32[H_ds][W_ds], 1-based index of every
+                                         pixel's last blended list entry (0: none), written
+                                         by the last forward; with off_t_final, what the
+                                         backward reads                                  */
 } tgs_state;
 
 /* st->pair_count after a batched bin/sort, until tgs_pair_counts reads the
@@ -183,7 +189,8 @@ typedef struct tgs_state {
 
 /* Per-view device buffers of the batched calls. */
 typedef struct tgs_view_io {
-    float* image;            /* [3][H_ds][W_ds]; written by the forward, read by the backward */
+    float* image;            /* [3][H_ds][W_ds]; written by the forward (the backward does not
+                                read it)                                                    */
     float* t_final;          /* optional [H_ds][W_ds] float, as tgs_raster_fwd               */
     uint32_t* last_contrib;  /* optional [H_ds][W_ds]                                        */
     uint32_t* n_eval;        /* optional [H_ds][W_ds]                                        */
@@ -258,10 +265,13 @@ tgs_status tgs_bin_sort(tgs_context* ctx, const tgs_gaussians* g, const tgs_came
  * each downsampled pixel walks its tile's list front to back with
  * alpha = min(0.99, o exp(-1/2 d^T Sigma^-1 d)), skips alpha < 1/255, stops
  * before the entry that would take T below 1e-4, and outputs C + T bg.
- * image: device [3][H_ds][W_ds].  Optional (may be NULL) device outputs per
- * downsampled pixel: t_final float, last_contrib uint32 (1-based index of the
- * last blended list entry), n_eval uint32 (entries examined, stop included),
- * n_blend uint32 (entries blended). */
+ * image: device [3][H_ds][W_ds], or NULL to write only the per-pixel state
+ * the backward reads.  That state -- every pixel's final transmittance and
+ * the 1-based index of its last blended list entry -- always goes to the
+ * workspace (st->off_t_final, st->off_last_contrib).  Optional (may be NULL)
+ * device outputs per downsampled pixel: t_final float and last_contrib
+ * uint32 (copies of that state), n_eval uint32 (entries examined, stop
+ * included), n_blend uint32 (entries blended). */
 tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
                           const tgs_options* opt, const tgs_state* st, int64_t n, float* image,
                           float* t_final, uint32_t* last_contrib, uint32_t* n_eval,
@@ -284,12 +294,16 @@ tgs_status tgs_l1_grad(tgs_context* ctx, const tgs_camera* cam, const tgs_dilati
 /* Stage (d1): the derivative of the forward (Sec. 3 Eq. 2; the paper's
  * backward follows prior work) with respect to every splat's
  * (u, v, A, B, C, o, r, g, b), summed over the rendered pixels, into the
- * workspace's float[n][9] grad2d.  image is the tgs_raster_fwd output of the
- * same state; the walk is replayed front to back, so no per-pixel state is
- * kept between forward and backward. */
+ * workspace's float[n][9] grad2d.  Every pixel walks its list back to front
+ * from the last entry it blended, starting from the final transmittance;
+ * both come from the last tgs_raster_fwd on this state (which must be the
+ * forward being differentiated).  The transmittance in front of each entry
+ * is recovered by division and the colour behind it accumulated from the
+ * back, so every quantity keeps its relative precision however deep the
+ * entry lies.  dL_dimage: device [3][H_ds][W_ds]. */
 tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
                           const tgs_options* opt, const tgs_state* st, int64_t n,
-                          const float* image, const float* dL_dimage, void* stream);
+                          const float* dL_dimage, void* stream);
 
 /* Stage (d2): chain rule from grad2d to the parameters, and the
  * densification statistics of Sec. 4.3: pos_stat = ||(dL/du W/2, dL/dv H/2)||
@@ -305,8 +319,8 @@ tgs_status tgs_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, const tg
 /* Stages (d1) and (d2) in order. */
 tgs_status tgs_backward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
                         const tgs_dilation* dil, const tgs_options* opt, const tgs_state* st,
-                        const float* image, const float* dL_dimage, const tgs_grads* out,
-                        float* pos_stat, float* col_stat, uint8_t* visible, void* stream);
+                        const float* dL_dimage, const tgs_grads* out, float* pos_stat,
+                        float* col_stat, uint8_t* visible, void* stream);
 
 /* ---- Batched views (several cameras and dilation patterns, one Gaussian set).
  *
@@ -366,8 +380,8 @@ tgs_status tgs_batch_l1_grad(tgs_context* ctx, int32_t views, const tgs_camera* 
                              void* stream);
 
 /* Stage (d1) for every view: one launch over the tiles of all views, from
- * io[v].image and io[v].dL_dimage into each view's grad2d (as
- * tgs_raster_bwd). */
+ * io[v].dL_dimage and the per-pixel state of each view's last forward into
+ * each view's grad2d (as tgs_raster_bwd). */
 tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views,
                                 const tgs_camera* cams, const tgs_dilation* dils,
                                 const tgs_options* opt, const tgs_state* states,

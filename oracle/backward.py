@@ -71,6 +71,25 @@ def preprocess_backward(p: pre.Params, cam: pre.Cam, g2d: torch.Tensor) -> dict:
             for n, gr, r in zip(names, grads, ref)}
 
 
+def unit_quaternion_gradient(p: pre.Params, cam: pre.Cam, g2d: torch.Tensor) -> torch.Tensor:
+    """(N, 4): dL/dq_hat, the gradient w.r.t. the unit quaternion q_hat = q/|q|
+    before the normalisation removes its radial part.
+
+    The parameter gradient is (I - q_hat q_hat^T) dL/dq_hat / |q|, a difference
+    of two terms that can nearly cancel; this returns the terms' source so that
+    a comparison can size the rounding such a difference carries."""
+    with torch.no_grad():
+        qn = p.quats.detach() / torch.linalg.norm(p.quats.detach(), dim=1, keepdim=True)
+    unit = pre.Params(p.means.detach(), p.scales.detach(), qn.clone().requires_grad_(True),
+                      p.opacities.detach(), p.sh.detach(), p.degree)
+    rec = pre.preprocess(unit, cam, unit_quats=True)
+    g2d = torch.as_tensor(g2d, dtype=F64)
+    s = sum((rec[k] * g2d[:, j]).sum() for j, k in enumerate(G2D_FIELDS))
+    s = s + (rec["rgb"] * g2d[:, 6:9]).sum()
+    (gq,) = torch.autograd.grad(s, [unit.quats], allow_unused=True)
+    return torch.zeros_like(qn) if gq is None else gq.detach()
+
+
 def densification_stats(g2d: torch.Tensor, visible: torch.Tensor, width: int, height: int):
     """(pos, col) per Gaussian, zero where not visible."""
     g2d = torch.as_tensor(g2d, dtype=F64)

@@ -75,9 +75,14 @@ def params(scene, requires_grad: bool = False) -> Params:
                   t(np.transpose(scene.sh, (2, 0, 1))), int(scene.sh_degree))
 
 
-def rotation(q: torch.Tensor) -> torch.Tensor:
-    """Rotation matrix of the normalised quaternion (w, x, y, z); (N, 4) -> (N, 3, 3)."""
-    q = q / torch.linalg.norm(q, dim=1, keepdim=True)
+def rotation(q: torch.Tensor, normalize: bool = True) -> torch.Tensor:
+    """Rotation matrix of the normalised quaternion (w, x, y, z); (N, 4) -> (N, 3, 3).
+
+    ``normalize=False`` takes q as already of unit length (the matrix formula
+    applied to q as given), so that a gradient w.r.t. the unit quaternion
+    itself, before the normalisation's projection, can be read off."""
+    if normalize:
+        q = q / torch.linalg.norm(q, dim=1, keepdim=True)
     w, x, y, z = q.unbind(1)
     rows = [
         torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
@@ -87,13 +92,13 @@ def rotation(q: torch.Tensor) -> torch.Tensor:
     return torch.stack(rows, 1)
 
 
-def covariance_3d(scales: torch.Tensor, quats: torch.Tensor) -> torch.Tensor:
+def covariance_3d(scales: torch.Tensor, quats: torch.Tensor, normalize: bool = True) -> torch.Tensor:
     """Sigma = R S S^T R^T with S = diag(scales) (Sec. 3)."""
-    m = rotation(quats) * scales[:, None, :]
+    m = rotation(quats, normalize) * scales[:, None, :]
     return m @ m.transpose(1, 2)
 
 
-def preprocess(p: Params, cam: Cam) -> dict:
+def preprocess(p: Params, cam: Cam, unit_quats: bool = False) -> dict:
     """All per-Gaussian quantities the rasterizer needs, in float64.
 
     Returns a dict of (N,)-leading tensors: u, v (full-resolution pixel centre),
@@ -101,6 +106,9 @@ def preprocess(p: Params, cam: Cam) -> dict:
     covariance with the low-pass), three_sigma (3 sqrt(lambda_max)), radius
     (int64), rgb (N, 3) after the clamp, rgb_raw, clamp (bool N x 3), culled
     (bool), opacity, and the FoV-guard flags fovx, fovy (True where clamped).
+    ``unit_quats=True`` skips the quaternion normalisation (the caller passes
+    unit quaternions); the values are the same, only the derivative w.r.t.
+    the quaternion keeps its radial part.
     """
     n = p.means.shape[0]
     finite = (torch.isfinite(p.means).all(1) & torch.isfinite(p.scales).all(1)
@@ -137,7 +145,7 @@ def preprocess(p: Params, cam: Cam) -> dict:
         torch.stack([zero, cam.fy / tz, -cam.fy * cyr / tz], 1),
     ], 1)                                        # (N, 2, 3)
     Tm = J @ cam.R                               # (N, 2, 3)
-    sigma = covariance_3d(scales, quats)
+    sigma = covariance_3d(scales, quats, normalize=not unit_quats)
     cov2 = Tm @ sigma @ Tm.transpose(1, 2)
     a = cov2[:, 0, 0] + LOW_PASS
     b = cov2[:, 0, 1]

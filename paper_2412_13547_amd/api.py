@@ -75,7 +75,8 @@ class tgs_state(C.Structure):
                 ("off_depth_order", C.c_uint64),
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
                 ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64),
-                ("off_depth_count", C.c_uint64), ("off_tile_work", C.c_uint64)]
+                ("off_depth_count", C.c_uint64), ("off_tile_work", C.c_uint64),
+                ("off_t_final", C.c_uint64), ("off_last_contrib", C.c_uint64)]
 
 
 class tgs_adam_group(C.Structure):
@@ -114,12 +115,12 @@ def _declare(lib):
                                   _P(tgs_options), _P(tgs_state), vp, vp]),
         "tgs_l1_grad": (C.c_int, [vp, _P(tgs_camera), _P(tgs_dilation), vp, vp, vp, vp, vp]),
         "tgs_raster_bwd": (C.c_int, [vp, _P(tgs_camera), _P(tgs_dilation), _P(tgs_options),
-                                     _P(tgs_state), C.c_int64, vp, vp, vp]),
+                                     _P(tgs_state), C.c_int64, vp, vp]),
         "tgs_preprocess_bwd": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
                                          _P(tgs_options), _P(tgs_state), _P(tgs_grads), vp, vp, vp,
                                          vp]),
         "tgs_backward": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
-                                   _P(tgs_options), _P(tgs_state), vp, vp, _P(tgs_grads), vp, vp,
+                                   _P(tgs_options), _P(tgs_state), vp, _P(tgs_grads), vp, vp,
                                    vp, vp]),
         "tgs_batch_forward": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
                                         _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
@@ -330,6 +331,8 @@ class View:
         self.workspace = None
         self.sizes = query_sizes(self.n, self.cam_s, self.dil, self.opt, 0)
         self._torch = torch
+        # bumped by every call that rewrites the workspace's forward results
+        self.generation = 0
         self.reserve(pair_capacity if pair_capacity is not None else max(1024, 16 * self.n))
 
     def set_offsets(self, off_x: int, off_y: int):
@@ -356,6 +359,7 @@ class View:
     # -- stages ------------------------------------------------------------
     def preprocess_fwd(self, scene: DeviceScene, stream=None):
         g = scene.struct()
+        self.generation += 1
         check(lib().tgs_preprocess_fwd(self.ctx.handle, C.byref(g), C.byref(self.cam_s),
                                        C.byref(self.dil), C.byref(self.opt), C.byref(self.state),
                                        _stream(stream)))
@@ -364,6 +368,7 @@ class View:
         """Pairs, sort and ranges.  sync (default: the view's sync_check) reads
         the count back and, with grow, enlarges the workspace and repeats."""
         g = scene.struct()
+        self.generation += 1
         sync = self.sync_check if sync is None else bool(sync)
         opt = self.opt_sync if sync else self.opt
         st = lib().tgs_bin_sort(self.ctx.handle, C.byref(g), C.byref(self.cam_s), C.byref(self.dil),
@@ -403,8 +408,11 @@ class View:
             self.reserve(min(int(need * slack) + 4096, MAX_PAIR_CAPACITY))
         raise TgsError(TGS_ERR_CAPACITY, "pair capacity did not converge")
 
-    def raster_fwd(self, image, t_final=None, last_contrib=None, n_eval=None, n_blend=None,
+    def raster_fwd(self, image=None, t_final=None, last_contrib=None, n_eval=None, n_blend=None,
                    stream=None):
+        """Blend forward; image None writes only the per-pixel state the
+        backward reads (final transmittance, last blended entry)."""
+        self.generation += 1
         check(lib().tgs_raster_fwd(self.ctx.handle, C.byref(self.cam_s), C.byref(self.dil),
                                    C.byref(self.opt), C.byref(self.state), self.n, _ptr(image),
                                    _ptr(t_final), _ptr(last_contrib), _ptr(n_eval), _ptr(n_blend),
@@ -431,9 +439,10 @@ class View:
                                 _stream(stream)))
         return dL_dimage, loss
 
-    def raster_bwd(self, image, dL_dimage, stream=None):
+    def raster_bwd(self, dL_dimage, stream=None):
+        """Blend backward of the last forward on this view's workspace."""
         check(lib().tgs_raster_bwd(self.ctx.handle, C.byref(self.cam_s), C.byref(self.dil),
-                                   C.byref(self.opt), C.byref(self.state), self.n, _ptr(image),
+                                   C.byref(self.opt), C.byref(self.state), self.n,
                                    _ptr(dL_dimage), _stream(stream)))
 
     def preprocess_bwd(self, scene: DeviceScene, grads: DeviceScene, pos_stat=None, col_stat=None,
@@ -446,15 +455,17 @@ class View:
                                        C.byref(out), _ptr(pos_stat), _ptr(col_stat), _ptr(visible),
                                        _stream(stream)))
 
-    def backward(self, scene: DeviceScene, image, dL_dimage, grads: DeviceScene | None = None,
+    def backward(self, scene: DeviceScene, dL_dimage, grads: DeviceScene | None = None,
                  pos_stat=None, col_stat=None, visible=None, stream=None):
+        """Blend and preprocess backward of the last forward on this view's
+        workspace."""
         if grads is None:
             grads = scene.zeros_like()
         g = scene.struct()
         out = tgs_grads(_ptr(grads.means), _ptr(grads.scales), _ptr(grads.quats),
                         _ptr(grads.opacities), _ptr(grads.sh))
         check(lib().tgs_backward(self.ctx.handle, C.byref(g), C.byref(self.cam_s), C.byref(self.dil),
-                                 C.byref(self.opt), C.byref(self.state), _ptr(image),
+                                 C.byref(self.opt), C.byref(self.state),
                                  _ptr(dL_dimage), C.byref(out), _ptr(pos_stat), _ptr(col_stat),
                                  _ptr(visible), _stream(stream)))
         return grads
@@ -490,6 +501,17 @@ class View:
     def grad2d(self):
         return self._view(self.state.off_grad2d, self.n * 9, self._torch.float32).view(self.n, 9)
 
+    def t_final(self):
+        """Every pixel's transmittance after the last forward's walk."""
+        h, w = int(self.sizes.h_ds), int(self.sizes.w_ds)
+        return self._view(self.state.off_t_final, h * w, self._torch.float32).view(h, w)
+
+    def last_contrib(self):
+        """Every pixel's 1-based index of its last blended entry (0: none),
+        from the last forward."""
+        h, w = int(self.sizes.h_ds), int(self.sizes.w_ds)
+        return self._view(self.state.off_last_contrib, h * w, self._torch.int32).view(h, w)
+
     def tile_work(self):
         """Entries the last forward walked per tile (the backward's tile order
         weights; any values give the same results)."""
@@ -520,6 +542,7 @@ class Batch:
         if not 1 <= nv <= MAX_VIEWS:
             raise ValueError(f"a batch holds 1..{MAX_VIEWS} views, got {nv}")
         self.ctx, self.n, self.nv = ctx, int(n), nv
+        self.generation = 0          # bumped by every forward stage
         self.states = (tgs_state * nv)()
         caps = pair_capacity if isinstance(pair_capacity, (list, tuple)) else [pair_capacity] * nv
         self.views = [View(ctx, n, cam, stride, ox, oy, tile, bg, pair_capacity=caps[k],
@@ -563,6 +586,7 @@ class Batch:
 
     def forward(self, scene: DeviceScene, stream=None):
         g = scene.struct()
+        self.generation += 1
         check(lib().tgs_batch_forward(self.ctx.handle, C.byref(g), self.nv, self.cams, self.dils,
                                       C.byref(self.opt), self.states, self.io, _stream(stream)))
         return self.images
@@ -570,16 +594,19 @@ class Batch:
     # -- stages (each one batched call) --------------------------------------
     def preprocess_fwd(self, scene: DeviceScene, stream=None):
         g = scene.struct()
+        self.generation += 1
         check(lib().tgs_batch_preprocess_fwd(self.ctx.handle, C.byref(g), self.nv, self.cams,
                                              self.dils, C.byref(self.opt), self.states,
                                              _stream(stream)))
 
     def bin_sort(self, scene: DeviceScene, stream=None):
         g = scene.struct()
+        self.generation += 1
         check(lib().tgs_batch_bin_sort(self.ctx.handle, C.byref(g), self.nv, self.cams, self.dils,
                                        C.byref(self.opt), self.states, _stream(stream)))
 
     def raster_fwd(self, stream=None):
+        self.generation += 1
         check(lib().tgs_batch_raster_fwd(self.ctx.handle, self.n, self.nv, self.cams, self.dils,
                                          C.byref(self.opt), self.states, self.io, _stream(stream)))
 

@@ -5,12 +5,13 @@ Argument marshalling only -- every stage runs in the HIP library:
 
 * ``rasterize(view, means, scales, quats, opacities, sh)`` -> image
   [3][H_ds][W_ds] of one view (camera + dilation pattern).  The backward
-  replays the forward walk to recover the transmittance in front of every
-  entry (nothing per pixel is kept between the passes but the image).  The
-  records and pair lists binned by the forward are reused if the view's
+  walks every pixel's list back to front from the final transmittance and
+  last blended entry the forward left in the view's workspace (8 bytes per
+  pixel), recovering the transmittance in front of every entry by division.
+  The records, pair lists and that per-pixel state are reused if the
   workspace still holds them; otherwise (``recompute=True``, or another
   forward ran on the same view in between) the backward re-derives them
-  from the saved parameters first.
+  from the saved parameters first (a forward pass without the image).
 * ``l1_loss(view, image, target)`` -> scalar L1 loss of the rendered pixels
   against the full-resolution target (Sec. 4.1); its gradient comes from the
   same kernel call.
@@ -69,26 +70,25 @@ class _Rasterize(torch.autograd.Function):
         dev = _scene(sh_degree, means, scales, quats, opacities, sh)
         image = torch.empty(view.image_shape, dtype=torch.float32, device=means.device)
         view.forward(dev, image)
-        view.generation = getattr(view, "generation", 0) + 1
         ctx.view, ctx.sh_degree, ctx.stats, ctx.recompute = view, sh_degree, stats, recompute
         ctx.generation = view.generation
-        ctx.save_for_backward(dev.means, dev.scales, dev.quats, dev.opacities, dev.sh, image)
+        ctx.save_for_backward(dev.means, dev.scales, dev.quats, dev.opacities, dev.sh)
         return image
 
     @staticmethod
     @torch.autograd.function.once_differentiable
     def backward(ctx, dL):
-        means, scales, quats, opacities, sh, image = ctx.saved_tensors
+        means, scales, quats, opacities, sh = ctx.saved_tensors
         view = ctx.view
         dev = api.DeviceScene(means, scales, quats, opacities, sh, ctx.sh_degree)
-        if ctx.recompute or getattr(view, "generation", 0) != ctx.generation:
+        if ctx.recompute or view.generation != ctx.generation:
             view.preprocess_fwd(dev)
             view.bin_sort(dev)
-            view.generation = getattr(view, "generation", 0) + 1
+            view.raster_fwd(None)
         grads = api.DeviceScene(*(torch.empty_like(t) for t in (means, scales, quats, opacities,
                                                                   sh)), ctx.sh_degree)
         bufs = ctx.stats.buffers() if ctx.stats is not None else (None, None, None)
-        view.backward(dev, image, dL.contiguous(), grads, *bufs)
+        view.backward(dev, dL.contiguous(), grads, *bufs)
         if ctx.stats is not None:
             ctx.stats.accumulate()
         return (None, None, None, None, grads.means, grads.scales, grads.quats, grads.opacities,
@@ -132,31 +132,32 @@ class _RasterizeBatch(torch.autograd.Function):
     def forward(ctx, batch, sh_degree, stats, means, scales, quats, opacities, sh):
         dev = _scene(sh_degree, means, scales, quats, opacities, sh)
         batch.forward(dev)
+        ctx.generation = batch.generation
         ctx.batch, ctx.sh_degree, ctx.stats = batch, sh_degree, stats
         images = tuple(t.clone() for t in batch.images)
-        ctx.save_for_backward(dev.means, dev.scales, dev.quats, dev.opacities, dev.sh, *images)
+        ctx.save_for_backward(dev.means, dev.scales, dev.quats, dev.opacities, dev.sh)
+        ctx.shapes = [t.shape for t in images]
         return images
 
     @staticmethod
     @torch.autograd.function.once_differentiable
     def backward(ctx, *dLs):
-        saved = ctx.saved_tensors
-        means, scales, quats, opacities, sh = saved[:5]
-        images = saved[5:]
+        means, scales, quats, opacities, sh = ctx.saved_tensors
         b = ctx.batch
         dev = api.DeviceScene(means, scales, quats, opacities, sh, ctx.sh_degree)
-        # the forward's binning may have been overwritten by a later forward:
-        # rebuild it from the saved parameters (cheap next to the backward)
-        b.preprocess_fwd(dev)
-        b.bin_sort(dev)
+        # when a later forward has overwritten the workspaces, rebuild the
+        # binning and per-pixel state from the saved parameters (the images
+        # it writes into the batch's own buffers are the same)
+        if b.generation != ctx.generation:
+            b.forward(dev)
         keep = []
         io = b.io
-        old = [(io[k].image, io[k].dL_dimage) for k in range(b.nv)]
+        old = [io[k].dL_dimage for k in range(b.nv)]
         for k in range(b.nv):
-            d = dLs[k] if dLs[k] is not None else torch.zeros_like(images[k])
+            d = dLs[k] if dLs[k] is not None else torch.zeros(ctx.shapes[k], dtype=torch.float32,
+                                                              device=means.device)
             d = d.contiguous()
             keep.append(d)
-            io[k].image = images[k].data_ptr()
             io[k].dL_dimage = d.data_ptr()
         grads = api.DeviceScene(*(torch.empty_like(t) for t in (means, scales, quats, opacities,
                                                                   sh)), ctx.sh_degree)
@@ -164,8 +165,8 @@ class _RasterizeBatch(torch.autograd.Function):
         try:
             b.backward(dev, grads, *bufs)
         finally:
-            for k, (im, dl) in enumerate(old):
-                io[k].image, io[k].dL_dimage = im, dl
+            for k, dl in enumerate(old):
+                io[k].dL_dimage = dl
         if ctx.stats is not None:
             ctx.stats.accumulate()
         return (None, None, None, grads.means, grads.scales, grads.quats, grads.opacities,

@@ -190,6 +190,8 @@ void publish_offsets(tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid,
     st->off_ranges = L.ranges;
     st->off_grad2d = L.grad2d;
     st->off_tile_work = L.tile_work;
+    st->off_t_final = L.pix_tfinal;
+    st->off_last_contrib = L.pix_last;
 }
 
 tgs_status use_device(tgs_context* ctx) {
@@ -228,6 +230,8 @@ tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const
     v.g2d = reinterpret_cast<float*>(ws + L.grad2d);
     v.work = reinterpret_cast<uint32_t*>(ws + L.tile_work);
     v.order = reinterpret_cast<uint32_t*>(ws + L.tile_order);
+    v.ws_tfinal = reinterpret_cast<float*>(ws + L.pix_tfinal);
+    v.ws_last = reinterpret_cast<uint32_t*>(ws + L.pix_last);
     return v;
 }
 
@@ -339,6 +343,8 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.ranges = take(uint64_t(grid.num_tiles()) * 8);
     L.tile_work = take(uint64_t(grid.num_tiles()) * 4);
     L.tile_order = take(uint64_t(grid.num_tiles()) * 4);
+    L.pix_tfinal = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
+    L.pix_last = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
     uint64_t most = radix_counts_elems(un);
@@ -556,7 +562,6 @@ tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     if (s != TGS_OK) return s;
     if (n < 0) return fail(TGS_ERR_INVALID_ARG, "n < 0");
     const tgs::Grid grid = tgs::make_grid(*cam, *dil, opt->tile);
-    if (!image) return fail(TGS_ERR_INVALID_ARG, "image is NULL");
     tgs::Layout L;
     if ((s = check_state(st, n, grid, &L)) != TGS_OK) return s;
     if ((s = check_binned(st, L, grid, true)) != TGS_OK) return s;
@@ -602,12 +607,12 @@ tgs_status tgs_l1_grad(tgs_context* ctx, const tgs_camera* cam, const tgs_dilati
 
 tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,
                           const tgs_options* opt, const tgs_state* st, int64_t n,
-                          const float* image, const float* dL_dimage, void* stream) {
+                          const float* dL_dimage, void* stream) {
     tgs_status s = check_common(cam, dil, opt);
     if (s == TGS_OK && !opt) s = fail(TGS_ERR_INVALID_ARG, "options is NULL");
     if (s != TGS_OK) return s;
     if (n < 0) return fail(TGS_ERR_INVALID_ARG, "n < 0");
-    if (!image || !dL_dimage) return fail(TGS_ERR_INVALID_ARG, "image or dL_dimage is NULL");
+    if (!dL_dimage) return fail(TGS_ERR_INVALID_ARG, "dL_dimage is NULL");
     const tgs::Grid grid = tgs::make_grid(*cam, *dil, opt->tile);
     tgs::Layout L;
     if ((s = check_state(st, n, grid, &L)) != TGS_OK) return s;
@@ -615,7 +620,6 @@ tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     if ((s = use_device(ctx)) != TGS_OK) return s;
     auto strm = static_cast<hipStream_t>(stream);
     tgs::RasterView v = raster_view(grid, *opt, *st, L);
-    v.image = const_cast<float*>(image);
     v.dL = dL_dimage;
     TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(v.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
     tgs::RasterViews t{};
@@ -648,11 +652,11 @@ tgs_status tgs_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, const tg
 
 tgs_status tgs_backward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
                         const tgs_dilation* dil, const tgs_options* opt, const tgs_state* st,
-                        const float* image, const float* dL_dimage, const tgs_grads* out,
-                        float* pos_stat, float* col_stat, uint8_t* visible, void* stream) {
+                        const float* dL_dimage, const tgs_grads* out, float* pos_stat,
+                        float* col_stat, uint8_t* visible, void* stream) {
     tgs_status s = check_gaussians(g);
     if (s != TGS_OK) return s;
-    s = tgs_raster_bwd(ctx, cam, dil, opt, st, g->n, image, dL_dimage, stream);
+    s = tgs_raster_bwd(ctx, cam, dil, opt, st, g->n, dL_dimage, stream);
     if (s == TGS_OK)
         s = tgs_preprocess_bwd(ctx, g, cam, dil, opt, st, out, pos_stat, col_stat, visible, stream);
     return s;
@@ -705,7 +709,7 @@ tgs_status check_binned_views(int32_t views, const tgs_state* states, const tgs:
 tgs_status check_io(int32_t views, const tgs_view_io* io, bool need_dL) {
     if (!io) return fail(TGS_ERR_INVALID_ARG, "io is NULL");
     for (int v = 0; v < views; ++v) {
-        if (!io[v].image) return fail(TGS_ERR_INVALID_ARG, "view %d: image is NULL", v);
+        if (!need_dL && !io[v].image) return fail(TGS_ERR_INVALID_ARG, "view %d: image is NULL", v);
         if (need_dL && !io[v].dL_dimage)
             return fail(TGS_ERR_INVALID_ARG, "view %d: dL_dimage is NULL", v);
     }
@@ -887,7 +891,6 @@ tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views, cons
     tgs::RasterViews rt{};
     for (int v = 0; v < views; ++v) {
         tgs::RasterView rv = raster_view(grids[v], *opt, states[v], Ls[v]);
-        rv.image = io[v].image;
         rv.dL = io[v].dL_dimage;
         TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(rv.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
         add_raster_view(rt, rv);

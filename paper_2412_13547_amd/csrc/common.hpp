@@ -65,6 +65,9 @@ struct Layout {
     uint64_t ranges;           // uint32[num_tiles][2]
     uint64_t tile_work;        // uint32[num_tiles], entries the forward walked per tile
     uint64_t tile_order;       // uint32[num_tiles], the backward's tile per workgroup
+    uint64_t pix_tfinal;       // float[h_ds][w_ds], transmittance after each pixel's walk
+    uint64_t pix_last;         // uint32[h_ds][w_ds], 1-based index of each pixel's last
+                               //   blended list entry (0: none)
     uint64_t grad2d;           // float[n][9]
     uint64_t sort_counts;      // uint32, radix digit counts, then the number of Gaussians
                                //   with tiles (at radix_kept_offset(n))
@@ -168,9 +171,11 @@ struct RasterView {
     const uint32_t* ranges;   // [num_tiles][2]
     const uint32_t* vals;     // pair values in (tile, depth, index) order
     const uint32_t* pair_count;   // device: pairs binned; above capacity = overflow
-    float* image;             // forward out / backward in
-    float* t_final;           // forward, optional
-    uint32_t* last_contrib;   // forward, optional
+    float* image;             // forward out (may be null)
+    float* ws_tfinal;         // forward out / backward in: per-pixel final transmittance
+    uint32_t* ws_last;        // forward out / backward in: per-pixel last blended entry
+    float* t_final;           // forward, optional copy of ws_tfinal for the caller
+    uint32_t* last_contrib;   // forward, optional copy of ws_last for the caller
     uint32_t* n_eval;         // forward, optional
     uint32_t* n_blend;        // forward, optional
     uint32_t* n_tested;       // forward, optional: entries evaluated pixel by pixel

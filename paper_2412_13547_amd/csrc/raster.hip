@@ -247,8 +247,9 @@ __device__ __forceinline__ void for_wave_entries(const uint32_t* s_m, int cnt, i
     }
 }
 
-// COUNTS adds the per-pixel counters last_contrib, n_eval, n_blend and
-// n_tested.
+// Every pixel's final transmittance and the 1-based index of its last
+// blended entry go to the workspace for the backward.  COUNTS adds the
+// per-pixel counters n_eval, n_blend and n_tested.
 //
 // A pixel's state is its transmittance with a sign: positive while it
 // still takes entries, negated (the magnitude kept) once it has stopped or
@@ -342,9 +343,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
                 c2[k] = fmaf(bb, w, c2[k]);
                 const float tn = Ts[k] - w;           // Ts itself when not blending
                 Ts[k] = stop ? -tn : tn;
+                const uint32_t pos = base - start + uint32_t(e) + 1;
+                last[k] = blend ? pos : last[k];
                 if constexpr (COUNTS) {
-                    const uint32_t pos = base - start + uint32_t(e) + 1;
-                    last[k] = blend ? pos : last[k];
                     nblend[k] += blend ? 1u : 0u;
                     neval[k] = stop ? pos : neval[k];
                 }
@@ -361,12 +362,17 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
         if (!(i < grid.w_ds && j < grid.h_ds)) continue;
         const uint64_t p = uint64_t(j) * grid.w_ds + i;
         const float Tr = fabsf(Ts[k]);
-        rv.image[p] = fmaf(Tr, rv.bg[0], c0[k]);
-        rv.image[pix + p] = fmaf(Tr, rv.bg[1], c1[k]);
-        rv.image[2 * pix + p] = fmaf(Tr, rv.bg[2], c2[k]);
+        if (rv.image) {
+            rv.image[p] = fmaf(Tr, rv.bg[0], c0[k]);
+            rv.image[pix + p] = fmaf(Tr, rv.bg[1], c1[k]);
+            rv.image[2 * pix + p] = fmaf(Tr, rv.bg[2], c2[k]);
+        }
+        // what the backward starts from
+        rv.ws_tfinal[p] = Tr;
+        rv.ws_last[p] = last[k];
         if (rv.t_final) rv.t_final[p] = Tr;
+        if (rv.last_contrib) rv.last_contrib[p] = last[k];
         if constexpr (COUNTS) {
-            if (rv.last_contrib) rv.last_contrib[p] = last[k];
             if (rv.n_eval) rv.n_eval[p] = neval[k];
             if (rv.n_blend) rv.n_blend[p] = nblend[k];
             if (rv.n_tested) rv.n_tested[p] = ntest[k];
@@ -374,6 +380,39 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     }
 }
 
+// Calls entry(e), from the last to the first, for the entries e < cnt of an
+// LDS batch whose wavefront mask has this wavefront's bit (the backward's
+// order: set bits of each 64-entry ballot taken from the highest).
+template <class F>
+__device__ __forceinline__ void for_wave_entries_reverse(const uint32_t* s_m, int cnt, int wave,
+                                                         F&& entry) {
+    for (int c = ((cnt - 1) >> 6) << 6; c >= 0; c -= 64) {
+        const int q = c + __lane_id();
+        uint64_t m = __ballot(q < cnt && ((s_m[q] >> wave) & 1u));
+        while (m != 0) {
+            const int hb = 63 - __builtin_clzll(m);
+            m ^= uint64_t(1) << hb;
+            entry(c + hb);
+        }
+    }
+}
+
+// The blend backward: each pixel walks its list back to front, from the
+// last entry it blended (ws_last) down to the first, starting from its
+// final transmittance (ws_tfinal); both were left by the forward.  With
+// T_k the transmittance in front of entry k and B_k the colour behind it
+// seen through it (the blended colours of the later entries and the
+// background, composited from the back):
+//   T_k = T_{k+1} / (1 - alpha_k),
+//   dC/dalpha_k = T_k (c_k - B_k),   B_{k-1} = alpha_k c_k + (1 - alpha_k) B_k,
+// B starting at the background.  Only the gradient-weighted S_k = sum_c
+// dL/dC_c B_k,c is needed, updated by the same convex combination, so every
+// quantity keeps its relative precision however small T gets (the colour
+// behind is never formed as a difference of the whole pixel colour and a
+// prefix).  The skip decisions (alpha < 1/255, exponent > 0) are the
+// forward's inline routine; an entry is blended iff it passes them and lies
+// before the pixel's last blended entry.
+//
 // Per blended entry the lane's contribution to the nine sums, as moments
 // that the wave reduces first; the splat's constants and the constant
 // factors of each component (ln 2 for u and v, -1/2, -1, -1/2 for A, B, C)
@@ -388,6 +427,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
     __shared__ uint32_t s_id[BATCH];
     __shared__ uint32_t s_m[BATCH];                              // wavefronts that look at it
+    __shared__ uint32_t s_end;                                   // entries the tile walks
     // multi-wavefront tiles add their wavefronts' sums in LDS and flush each
     // batch with one set of global atomics per entry
     constexpr bool kBlockSum = S::NT > 64;
@@ -409,48 +449,56 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     wr.init(grid, tx, ty, T);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
-    // r_c = colour still to come behind the current entry (image minus the
-    // colour accumulated so far), kept per channel and updated in place;
-    // Ts = transmittance, negated once the pixel has stopped (as in the
-    // forward)
-    float X[S::NP], Y[S::NP], Ts[S::NP], r0[S::NP], r1[S::NP], r2[S::NP];
+    // per pixel: the transmittance behind the current entry (T_final at the
+    // start), the gradient-weighted colour behind it (the background at the
+    // start), dL/dC and the 1-based index of the last blended entry
+    float X[S::NP], Y[S::NP], Ts[S::NP], Sb[S::NP];
     float g0[S::NP], g1[S::NP], g2[S::NP];
+    uint32_t last[S::NP];
+    uint32_t lmax = 0;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
         const int i = i0 + k % S::PX, j = j0 + k / S::PX;
         const bool in = i < grid.w_ds && j < grid.h_ds;
         X[k] = float(grid.stride * i + grid.off_x);
         Y[k] = float(grid.stride * j + grid.off_y);
-        Ts[k] = in ? 1.0f : -1.0f;
-        r0[k] = r1[k] = r2[k] = 0.0f;
+        Ts[k] = 1.0f;
         g0[k] = g1[k] = g2[k] = 0.0f;
+        last[k] = 0;
         if (in) {
             const uint64_t p = uint64_t(j) * grid.w_ds + i;
             g0[k] = rv.dL[p];
             g1[k] = rv.dL[pix + p];
             g2[k] = rv.dL[2 * pix + p];
-            r0[k] = rv.image[p];
-            r1[k] = rv.image[pix + p];
-            r2[k] = rv.image[2 * pix + p];
+            Ts[k] = rv.ws_tfinal[p];
+            last[k] = min(rv.ws_last[p], end - start);
         }
+        Sb[k] = fmaf(g2[k], rv.bg[2], fmaf(g1[k], rv.bg[1], g0[k] * rv.bg[0]));
+        lmax = max(lmax, last[k]);
     }
+    // entries [0, wend) hold every blend of this wavefront's pixels, [0, s_end)
+    // those of the tile
+    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, uint32_t(__shfl_xor(int(lmax), o)));
+    const uint32_t wend = uint32_t(__builtin_amdgcn_readfirstlane(int(lmax)));
+    if (S::NT > 64) {
+        if (tid == 0) s_end = 0;
+        __syncthreads();
+        if (__lane_id() == 0) atomicMax(&s_end, wend);
+        __syncthreads();
+    }
+    const uint32_t tend = S::NT > 64 ? uint32_t(__builtin_amdgcn_readfirstlane(int(s_end))) : wend;
     // factor of the component this lane owns after wave_sum9
     const int lane = __lane_id();
     const int own = (lane & 7) == 0 ? (lane >> 3) : (lane == 1 ? 8 : -1);
     const float scale = own == 0 || own == 1 ? kLn2
                         : own == 2 || own == 4 ? -0.5f
                         : own == 3 ? -1.0f : 1.0f;
-    auto live = [&]() {
-        bool l = false;
-#pragma unroll
-        for (int k = 0; k < S::NP; ++k) l = l || Ts[k] > 0.0f;
-        return l;
-    };
-    for (uint32_t base = start; base < end; base += BATCH) {
-        if (__syncthreads_count(live()) == 0) break;
-        const int cnt = min(BATCH, int(end - base));
+    for (int hi = int(tend); hi > 0; hi -= BATCH) {
+        const int lo = max(0, hi - BATCH);
+        const int cnt = hi - lo;
+        if (hi != int(tend)) __syncthreads();                    // the previous batch is done
         for (int q = tid; q < cnt; q += S::NT) {
-            const uint32_t id = rv.vals[base + q];
+            const uint32_t id = rv.vals[start + uint32_t(lo + q)];
             const float4* r = rv.rec + 3 * uint64_t(id);
             float4 ga, gb;
             stage_conic(r[0], r[1], ga, gb);
@@ -467,7 +515,8 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         auto entry = [&](int e) {
             const float4 a = s_a[e], b = s_b[e];
             const float4 c = s_c[e];                  // (b, qa2, qc2, unused)
-            // decisions, exactly as in the forward (same wavefront skip)
+            const uint32_t pos = uint32_t(lo + e);    // 0-based position in the list
+            // the forward's skip decisions; blended iff also before the last blend
             float dx[S::NP], dy[S::NP], t[S::NP], p2[S::NP], G[S::NP], raw[S::NP], alpha[S::NP];
             bool blend[S::NP];
 #pragma unroll
@@ -475,28 +524,23 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             uint64_t any = 0;                         // lanes with a blending pixel
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const bool hit = splat_test(b, p2[k], G[k], raw[k], alpha[k]) && Ts[k] > 0.0f;
-                const bool stop = hit && Ts[k] - alpha[k] * Ts[k] < kTMin;
-                blend[k] = hit != stop;
+                blend[k] = splat_test(b, p2[k], G[k], raw[k], alpha[k]) && pos < last[k];
                 any |= __ballot(blend[k]);
-                Ts[k] = stop ? -Ts[k] : Ts[k];
             }
             if (any == 0) return;                     // no pixel of the wavefront blends it
             float gv[kGrad2d];
-            // T0 is the pixel's transmittance where it blends; elsewhere every
-            // term it enters is selected away (w, dp and the G term are 0)
+            // where a pixel does not blend the entry every term it enters is
+            // selected away (w, dp and the G term are 0; T and S unchanged)
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const float T0 = Ts[k];
-                const float w = blend[k] ? alpha[k] * T0 : 0.0f;
-                r0[k] = fmaf(-b.z, w, r0[k]);
-                r1[k] = fmaf(-b.w, w, r1[k]);
-                r2[k] = fmaf(-c.x, w, r2[k]);
-                // dL/d alpha = sum_c dL/dC_c (rgb_c T - (colour behind)_c / (1 - alpha))
-                const float gcol = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
-                const float grest = fmaf(g2[k], r2[k], fmaf(g1[k], r1[k], g0[k] * r0[k]));
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[k]);
-                const float dal = fmaf(-grest, inv, gcol * T0);
+                const float T0 = blend[k] ? Ts[k] * inv : Ts[k];    // in front of the entry
+                const float w = blend[k] ? alpha[k] * T0 : 0.0f;
+                // dL/dalpha = T0 (sum_c dL/dC_c rgb_c - S)
+                const float gcol = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
+                const float diff = gcol - Sb[k];
+                const float dal = T0 * diff;
+                Sb[k] = blend[k] ? fmaf(alpha[k], diff, Sb[k]) : Sb[k];
                 // no gradient through the 0.99 clamp
                 const bool live = blend[k] && !(raw[k] > kAlphaMax);
                 const float dp = live ? alpha[k] * dal : 0.0f;
@@ -508,7 +552,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                     w * g0[k], w * g1[k], w * g2[k]};
 #pragma unroll
                 for (int q = 0; q < kGrad2d; ++q) gv[q] = k == 0 ? m[q] : gv[q] + m[q];
-                Ts[k] = T0 - w;
+                Ts[k] = T0;
             }
             int comp;
             float sum = wave_sum9(gv, comp);
@@ -522,7 +566,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
                 else atomicAdd(&rv.g2d[uint64_t(s_id[e]) * kGrad2d + comp], sum * scale);
             }
         };
-        for_wave_entries(s_m, cnt, wave, live, entry);
+        // entries at or past this wavefront's last blend change nothing
+        const int wcnt = min(cnt, max(0, int(wend) - lo));
+        for_wave_entries_reverse(s_m, wcnt, wave, entry);
         if constexpr (kBlockSum) {
             __syncthreads();
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) {
@@ -607,7 +653,7 @@ __global__ void l1_zero_kernel(L1Views vt) {
 
 bool wants_counts(const RasterViews& vt) {
     for (int k = 0; k < vt.count; ++k)
-        if (vt.v[k].last_contrib || vt.v[k].n_eval || vt.v[k].n_blend || vt.v[k].n_tested)
+        if (vt.v[k].n_eval || vt.v[k].n_blend || vt.v[k].n_tested)
             return true;
     return false;
 }

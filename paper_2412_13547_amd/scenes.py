@@ -266,3 +266,62 @@ def small_multiview(seed: int, n: int, sizes, sh_degree: int = 3, spread_angle: 
     cams = [cam0] + [ring_camera(w, h, ang0 + k * spread_angle) for k, (w, h) in
                      enumerate(sizes) if k > 0]
     return scene, cams
+
+
+def sweep_case(seed: int):
+    """One tiny random case of the property sweep: (scene, camera, stride,
+    off_x, off_y, tile, background).
+
+    1-64 Gaussians, images of 8-64 pixels a side, stride 1-4 with any
+    offsets, tile 8, 16 or 32, SH degree 0-3, seen by an identity camera
+    (camera space = world space).  Besides generic Gaussians it draws the
+    inputs where integer decisions sit close to their thresholds: centres
+    placed exactly on rendered pixels, on the boundaries of 8- and 16-pixel
+    blocks of the downsampled grid (the pixel rectangles of the rasterizer's
+    wavefronts) and half a stride beside them; opacities 0.1 % above and
+    below 1/255 and 0.99; needle-shaped Gaussians whose screen covariance is
+    close to singular before the low-pass term; very large ones.
+    """
+    rng = np.random.default_rng(seed)
+    w, h = int(rng.integers(8, 65)), int(rng.integers(8, 65))
+    d = int(rng.integers(1, 5))
+    ox, oy = int(rng.integers(0, d)), int(rng.integers(0, d))
+    tile = (8, 16, 32)[int(rng.integers(0, 3))]
+    n = int(rng.integers(1, 65))
+    deg = int(rng.integers(0, 4))
+    f = float(w) * float(rng.uniform(0.6, 1.6))
+    cam = identity_camera(w, h, f)
+    z = rng.uniform(1.0, 6.0, size=n)
+    # pixel-space centres
+    u = rng.uniform(-0.25 * w, 1.25 * w, size=n)
+    v = rng.uniform(-0.25 * h, 1.25 * h, size=n)
+    kind = rng.integers(0, 5, size=n)
+    for a, (off, size) in enumerate(((ox, w), (oy, h))):
+        coord = u if a == 0 else v
+        n_ds = max(1, -(-(size - off) // d))
+        blk = rng.choice([1, 8, 16], size=n)
+        k = rng.integers(0, n_ds // blk + 1, size=n) * blk
+        shift = rng.choice([0.0, -0.5 * d, 0.5 * d, -1e-3, 1e-3], size=n)
+        snapped = d * k + off + shift
+        coord[kind >= 2] = snapped[kind >= 2]
+    means = np.stack([(u - cam.cx) * z / f, (v - cam.cy) * z / f, z])
+    # screen sizes from a third of a pixel to about the image
+    px = np.exp(rng.uniform(np.log(0.3), np.log(0.6 * max(w, h)), size=(3, n)))
+    scales = px * z[None] / f
+    needle = rng.uniform(size=n) < 0.15
+    scales[1:, needle] = scales[:1, needle] * 1e-5
+    quats = rng.normal(0.0, 1.0, size=(4, n))
+    opac = 1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, size=n)))
+    special = rng.integers(0, 6, size=n)
+    edge = np.array([1.0 / 255.0 * (1 - 1e-3), 1.0 / 255.0 * (1 + 1e-3),
+                     0.99 * (1 - 1e-3), 0.99 * (1 + 1e-3), 1.0])
+    pick = (special >= 3) & (kind >= 2)
+    opac[pick] = edge[rng.integers(0, len(edge), size=int(pick.sum()))]
+    k_sh = (deg + 1) ** 2
+    sh = np.empty((k_sh, 3, n))
+    sh[0] = rng.uniform(-1.2, 1.2, size=(3, n))
+    if k_sh > 1:
+        sh[1:] = rng.normal(0.0, 0.2, size=(k_sh - 1, 3, n))
+    bg = (0.0, 0.0, 0.0) if rng.uniform() < 0.7 else tuple(float(x) for x in rng.uniform(0, 1, 3))
+    scene = Scene(_f32(means), _f32(scales), _f32(quats), _f32(opac), _f32(sh), deg)
+    return scene, cam, d, ox, oy, tile, bg

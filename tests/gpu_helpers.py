@@ -10,6 +10,7 @@ import torch
 
 from oracle import backward as obw
 from oracle import binning as obn
+from oracle import loss as ols
 from oracle import preprocess as opre
 from oracle import raster as ors
 from paper_2412_13547_amd import api
@@ -56,7 +57,7 @@ def run_gpu(scene, cam, stride=1, off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0),
         pos = torch.empty(n, dtype=torch.float32, device="cuda")
         col = torch.empty(n, dtype=torch.float32, device="cuda")
         vis = torch.empty(n, dtype=torch.uint8, device="cuda")
-        grads = view.backward(dev, image, dL, pos_stat=pos, col_stat=col, visible=vis)
+        grads = view.backward(dev, dL, pos_stat=pos, col_stat=col, visible=vis)
         out.update(dL=dL, grads=grads, pos_stat=pos, col_stat=col, visible=vis)
     torch.cuda.synchronize()
     host = {}
@@ -89,7 +90,27 @@ def records_to_oracle(rec32: torch.Tensor) -> dict:
                 fovx=(flags & 16) != 0, fovy=(flags & 32) != 0)
 
 
-def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name="", floor=None):
+def quat_floor(scene_or_params, cam, g2d, rel=1e-3) -> torch.Tensor:
+    """(N, 4) element allowance for the quaternion gradient.
+
+    An element of dL/dq is g_j/|q| - q_hat_j (q_hat . g)/|q|, with g = dL/dq_hat
+    (the gradient w.r.t. the unit quaternion, taken here from the oracle at
+    the given 2D gradients ``g2d``): the normalisation's projection subtracts
+    the radial part, and the two terms can cancel to far below either.  Each
+    side computes g to the bar ``rel`` of its own size, so the difference
+    carries rel (|g_j| + |q_hat_j| sum_k |q_hat_k g_k|) / |q|: the bar applied
+    to the terms before they cancel, propagated through the projection."""
+    p = scene_or_params if isinstance(scene_or_params, opre.Params) else opre.params(scene_or_params)
+    c = cam if isinstance(cam, opre.Cam) else opre.camera(cam)
+    gq = obw.unit_quaternion_gradient(p, c, torch.as_tensor(g2d).to(F64))
+    q = p.quats.detach().to(F64)
+    qn = torch.linalg.norm(q, dim=1, keepdim=True)
+    qh = q / qn
+    terms = (gq.abs() + qh.abs() * (qh.abs() * gq.abs()).sum(1, keepdim=True)) / qn
+    return rel * torch.nan_to_num(terms, nan=0.0, posinf=0.0, neginf=0.0)
+
+
+def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name="", floor=None, quiet=False):
     """The gradient bar: per tensor ||d|| / ||g|| <= rel, and per element
     |d| <= rel (|g| + rel max|g|).
 
@@ -110,9 +131,26 @@ def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name="", floor=N
         bound = bound + torch.as_tensor(floor, dtype=F64).flatten()
     ratio = d / bound
     worst = float(ratio.max())
-    say(f"[grad] {name}: norm-rel {nrel:.2e}, worst element {worst:.3f} of its bound")
+    if not quiet:
+        say(f"[grad] {name}: norm-rel {nrel:.2e}, worst element {worst:.3f} of its bound")
     assert nrel <= rel, f"{name}: norm-relative error {nrel:.3e}"
     bad = ratio > 1.0
     assert not bool(bad.any()), (f"{name}: {int(bad.sum())} elements out of bound, worst "
                                  f"{worst:.3e} of the bound")
     return nrel
+
+
+def l1_matches_oracle(image, dL, loss, target, grid, label):
+    """The L1 stage against ``oracle.loss.l1`` fed the HIP image: the sign of
+    every element of dL/dimage exactly, its magnitude 1/(3 pixels) within
+    the float32 rounding of that reciprocal, the loss (float64 sum of
+    float32 residuals) within 1e-6 relative."""
+    want_loss, want = ols.l1(image.to(F64), target, grid)
+    got = dL.to(F64)
+    assert got.shape == want.shape, label
+    assert torch.equal(torch.sign(got), torch.sign(want)), f"{label}: a residual sign differs"
+    inv = 1.0 / want.numel()
+    assert float((got - want).abs().max()) <= 2.0 ** -22 * inv, label
+    rel = abs(float(loss) - float(want_loss)) / float(want_loss)
+    assert rel <= 1e-6, (label, rel)
+    return rel

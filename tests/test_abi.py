@@ -147,7 +147,7 @@ def test_raster_refuses_unbinned_state():
                            None, None)
     assert r == api.TGS_ERR_INVALID_ARG and b"binned" in lib.tgs_last_error()
     r = lib.tgs_raster_bwd(None, C.byref(_cam()), C.byref(api.dilation_struct()),
-                           C.byref(api.options_struct()), C.byref(st), 10, 1 << 20, 1 << 20, None)
+                           C.byref(api.options_struct()), C.byref(st), 10, 1 << 20, None)
     assert r == api.TGS_ERR_INVALID_ARG and b"binned" in lib.tgs_last_error()
 
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import ctx, grad_close, run_gpu, say
+from gpu_helpers import ctx, grad_close, quat_floor, run_gpu, say
 from oracle import pipeline as opipe
 from paper_2412_13547_amd import api, autograd, scenes
 
@@ -40,8 +40,10 @@ def test_autograd_matches_direct_backward():
     torch.cuda.synchronize()
     assert torch.equal(img.detach().cpu(), ref["image"])
     assert abs(float(loss) - float(ref["loss"].item())) <= 1e-12 * float(loss)
+    qfloor = quat_floor(sc, cam, ref["grad2d"])
     for k, t in zip(PARAMS, leaves):
-        grad_close(t.grad.cpu(), ref["grads"][k].to(F64), name=f"autograd {k}")
+        grad_close(t.grad.cpu(), ref["grads"][k].to(F64), name=f"autograd {k}",
+                   floor=qfloor.T if k == "quats" else None)
     assert torch.equal(stats.count.cpu().to(torch.uint8), ref["visible"])
     grad_close(stats.pos.cpu(), ref["pos_stat"].to(F64), name="pos_stat")
 
@@ -65,8 +67,10 @@ def test_recomputation_gives_the_same_gradients(mode):
         with torch.no_grad():
             autograd.rasterize(view, *[t.detach() for t in _leaves(other)], sh_degree=3)
     autograd.l1_loss(view, img, target).backward()
+    qfloor = quat_floor(sc, cam, view.grad2d().cpu())
     for k, a, b in zip(PARAMS, leaves, base):
-        grad_close(a.grad.cpu(), b.grad.cpu().to(F64), name=f"{mode} {k}")
+        grad_close(a.grad.cpu(), b.grad.cpu().to(F64), name=f"{mode} {k}",
+                   floor=qfloor.T if k == "quats" else None)
 
 
 def test_batched_autograd_sums_views():
@@ -86,8 +90,10 @@ def test_batched_autograd_sums_views():
     b.step(dev, ref)
     torch.cuda.synchronize()
     assert abs(float(total) - float(b.loss.sum())) <= 1e-12 * float(total)
+    qfloor = sum(quat_floor(sc, cams[k], b.views[k].grad2d().cpu()) for k in range(3))
     for k, t in zip(PARAMS, leaves):
-        grad_close(t.grad.cpu(), getattr(ref, k).cpu().to(F64), name=f"batch autograd {k}")
+        grad_close(t.grad.cpu(), getattr(ref, k).cpu().to(F64), name=f"batch autograd {k}",
+                   floor=qfloor.T if k == "quats" else None)
 
 
 def _perturbed(sc, seed):

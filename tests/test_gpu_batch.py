@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import ctx, grad_close, records_to_oracle, run_gpu, say
+from gpu_helpers import ctx, grad_close, quat_floor, records_to_oracle, run_gpu, say
 from oracle import backward as obw
 from oracle import binning as obn
 from oracle import preprocess as opre
@@ -103,7 +103,8 @@ def test_batch_gradients_are_sums_of_single_views():
     singles = r["singles"]
     for name in PARAMS:
         want = sum(s["grads"][name].to(F64) for s in singles)
-        grad_close(r["grads"][name], want, name=f"batch {name}")
+        grad_close(r["grads"][name], want, name=f"batch {name}",
+                   floor=_qfloor(r) if name == "quats" else None)
     grad_close(r["pos"], sum(s["pos_stat"].to(F64) for s in singles), name="pos_stat")
     grad_close(r["col"], sum(s["col_stat"].to(F64) for s in singles), name="col_stat")
     assert torch.equal(r["vis"].to(torch.int64), sum(s["visible"].to(torch.int64) for s in singles))
@@ -112,22 +113,35 @@ def test_batch_gradients_are_sums_of_single_views():
 
 def test_batch_backward_against_oracle():
     """Each view's blend backward, then the summed preprocess backward, by the
-    oracle from the HIP path's own upstream outputs."""
+    oracle from the HIP path's own upstream outputs.  Pixels the oracle
+    flags (a float decision on its threshold) take no upstream gradient on
+    either side: the batch's backward is re-run with those dL values zeroed."""
     r = _setup()
-    sc = r["sc"]
+    sc, b, dev = r["sc"], r["batch"], r["dev"]
     params = opre.params(sc, requires_grad=True)
-    total = None
+    masked = []
+    for k, (_w, _h, d, ox, oy) in enumerate(SPECS):
+        cam = r["cams"][k]
+        g = obn.grid(cam.width, cam.height, d, ox, oy, 16)
+        rec = records_to_oracle(r["records"][k])
+        o = ors.raster_forward(rec, r["pair_vals"][k].to(torch.int64),
+                               r["ranges"][k].to(torch.int64), g)
+        say(f"[gpu] view {k}: {int(o['flag'].sum())} flagged pixels")
+        dl = r["dL"][k].to(F64) * (~o["flag"]).to(F64)[None]
+        masked.append(dl)
+        b.dL[k].copy_(dl.to(torch.float32).cuda())
+    b.raster_bwd()
+    grads = dev.zeros_like()
+    b.preprocess_bwd(dev, grads)
+    torch.cuda.synchronize()
+    total = qfloor = None
     for k, (_w, _h, d, ox, oy) in enumerate(SPECS):
         cam = r["cams"][k]
         g = obn.grid(cam.width, cam.height, d, ox, oy, 16)
         rec = records_to_oracle(r["records"][k])
         want2d = obw.raster_backward(rec, r["pair_vals"][k].to(torch.int64),
-                                     r["ranges"][k].to(torch.int64), g, r["dL"][k].to(F64))
-        o = ors.raster_forward(rec, r["pair_vals"][k].to(torch.int64),
-                               r["ranges"][k].to(torch.int64), g)
-        got2d = r["grad2d"][k]
-        if bool(o["flag"].any()):
-            say(f"[gpu] view {k}: {int(o['flag'].sum())} flagged pixels")
+                                     r["ranges"][k].to(torch.int64), g, masked[k])
+        got2d = b.views[k].grad2d().cpu()
         for c, nm in enumerate(("u", "v", "A", "B", "C", "opacity", "r", "g", "b")):
             grad_close(got2d[:, c], want2d[:, c], name=f"view {k} d{nm}")
         g2d = got2d.to(F64).clone()
@@ -135,12 +149,26 @@ def test_batch_backward_against_oracle():
         assert not bool(near.any())
         part = obw.preprocess_backward(params, opre.camera(cam), g2d)
         total = part if total is None else {n: total[n] + part[n] for n in total}
-    got = r["grads"]
+        qf = quat_floor(sc, cam, g2d)
+        qfloor = qf if qfloor is None else qfloor + qf
+    got = {k: getattr(grads, k).cpu() for k in PARAMS}
     grad_close(got["means"].T, total["means"], name="means")
     grad_close(got["scales"].T, total["scales"], name="scales")
-    grad_close(got["quats"].T, total["quats"], name="quats")
+    grad_close(got["quats"].T, total["quats"], name="quats", floor=qfloor)
     grad_close(got["opacities"], total["opacities"], name="opacities")
     grad_close(got["sh"].permute(2, 0, 1), total["sh"], name="sh")
+    for k in range(len(SPECS)):                  # the batch's own upstream gradients back
+        b.dL[k].copy_(r["dL"][k].cuda())
+
+
+def _qfloor(r):
+    """Quaternion allowance of a batch's summed gradient: the single views'
+    allowances (gpu_helpers.quat_floor) summed, laid out like the HIP
+    gradient (4 x N)."""
+    if "qfloor" not in r:
+        r["qfloor"] = sum(quat_floor(r["sc"], r["cams"][k], s["grad2d"])
+                          for k, s in enumerate(r["singles"])).T
+    return r["qfloor"]
 
 
 @pytest.mark.parametrize("lds_batch", [64, 128])
@@ -152,7 +180,8 @@ def test_lds_batch_does_not_change_results(lds_batch):
         assert torch.equal(r["n_eval"][k], base["n_eval"][k])
         assert torch.equal(r["last"][k], base["last"][k])
     for name in PARAMS:
-        grad_close(r["grads"][name], base["grads"][name].to(F64), name=f"lds{lds_batch} {name}")
+        grad_close(r["grads"][name], base["grads"][name].to(F64), name=f"lds{lds_batch} {name}",
+                   floor=_qfloor(base) if name == "quats" else None)
 
 
 @pytest.mark.parametrize("tile", [8, 32])
@@ -164,7 +193,7 @@ def test_batch_other_tile_sizes_match_single_views(tile):
         assert torch.equal(r["n_eval"][k], s["n_eval"]), k
     for name in PARAMS:
         grad_close(r["grads"][name], sum(s["grads"][name].to(F64) for s in r["singles"]),
-                   name=f"T{tile} {name}")
+                   name=f"T{tile} {name}", floor=_qfloor(r) if name == "quats" else None)
 
 
 def test_overflowing_view_renders_background_and_is_reported():
@@ -218,5 +247,6 @@ def test_graph_capture_replays_match_eager_step():
             assert torch.equal(b.images[k].cpu(), r["images"][k]), (rep, k)
             assert torch.equal(b.n_eval[k].cpu(), r["n_eval"][k]), (rep, k)
         for name in PARAMS:
-            grad_close(getattr(grads, name).cpu(), r["grads"][name].to(F64), name=f"replay {rep} {name}")
+            grad_close(getattr(grads, name).cpu(), r["grads"][name].to(F64), name=f"replay {rep} {name}",
+                       floor=_qfloor(r) if name == "quats" else None)
     say("[gpu] 3 graph replays match the eager step")

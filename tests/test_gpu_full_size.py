@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import ctx, grad_close, records_to_oracle, say
+from gpu_helpers import ctx, grad_close, l1_matches_oracle, quat_floor, records_to_oracle, say
 from oracle import backward as obw
 from oracle import binning as obn
 from oracle import preprocess as opre
@@ -46,7 +46,7 @@ def _run(name):
     view.forward(dev, img, t_final=tfin, last_contrib=last, n_eval=neval, n_blend=nblend)
     target = torch.as_tensor(tgt).cuda()
     dL, loss = view.l1_grad(img, target)
-    grads = view.backward(dev, img, dL)
+    grads = view.backward(dev, dL)
     torch.cuda.synchronize()
     g = obn.grid(cam.width, cam.height, stride, ox, oy, 16)
     r = dict(sc=sc, cam=cam, view=view, dev=dev, img=img, dL=dL, grads=grads, grid=g,
@@ -56,15 +56,29 @@ def _run(name):
              touched=view.tiles_touched().cpu().to(torch.int64),
              image=img.cpu(), last=last.cpu(), neval=neval.cpu(), nblend=nblend.cpu(),
              tfin=tfin.cpu())
-    rng = np.random.default_rng(17)
-    lens = (r["ranges"][:, 1] - r["ranges"][:, 0]).numpy()
-    busy = np.nonzero(lens > 0)[0]
-    # a few tiles from the densest quarter and a few at random
-    dense = busy[np.argsort(lens[busy])[-max(1, len(busy) // 4):]]
-    r["tiles"] = sorted(set(rng.choice(dense, 4, replace=False).tolist()
-                            + rng.choice(busy, 4, replace=False).tolist()))
+    r["tiles"] = sample_tiles(r["ranges"], g, np.random.default_rng(17))
+    say(f"[gpu] {name}: {len(r['tiles'])} sampled tiles")
     _CACHE[name] = r
     return r
+
+
+def sample_tiles(ranges, g, rng, n_dense=16, n_bottom=12, n_edge=12, n_random=20):
+    """At least 64 tiles: the 16 with the longest lists, tiles of the bottom
+    row (partial when the downsampled height is not a multiple of the tile),
+    tiles of the other three grid edges, the four corners, and tiles at
+    random."""
+    lens = (ranges[:, 1] - ranges[:, 0]).numpy()
+    busy = np.nonzero(lens > 0)[0]
+    dense = busy[np.argsort(lens[busy], kind="stable")[-n_dense:]].tolist()
+    bottom = [(g.gy - 1) * g.gx + x for x in range(g.gx)]
+    edges = ([x for x in range(g.gx)] + [y * g.gx for y in range(g.gy)]
+             + [y * g.gx + g.gx - 1 for y in range(g.gy)])
+    corners = [0, g.gx - 1, (g.gy - 1) * g.gx, g.gy * g.gx - 1]
+    pick = lambda pool, k: rng.choice(pool, min(k, len(pool)), replace=False).tolist()
+    chosen = set(dense) | set(corners) | set(pick(bottom, n_bottom)) | set(pick(edges, n_edge))
+    rest = [t for t in busy.tolist() if t not in chosen]
+    chosen |= set(pick(rest, max(n_random, 64 - len(chosen))))
+    return sorted(chosen)
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
@@ -86,6 +100,7 @@ def test_pairs_ranges_properties_and_sampled_lists(name):
         order = members[np.lexsort((members, zb[members]))]
         s, e = ranges[t].tolist()
         assert vals[s:e].numpy().tolist() == order.tolist(), f"tile {t}"
+    assert len(r["tiles"]) >= 64
     say(f"[gpu] {name}: {P} pairs, {len(r['tiles'])} sampled lists bit-exact")
 
 
@@ -118,7 +133,7 @@ def test_sampled_tiles_backward(name):
     keep = (mask & ~o["flag"]).to(F64)
     dL = r["dL"].cpu().to(F64) * keep[None]
     view = r["view"]
-    view.raster_bwd(r["img"], dL.to(torch.float32).cuda())
+    view.raster_bwd(dL.to(torch.float32).cuda())
     torch.cuda.synchronize()
     got = view.grad2d().cpu()
     want = obw.raster_backward(r["rec"], r["vals"], r["ranges"], g, dL, tiles=r["tiles"])
@@ -147,7 +162,7 @@ def test_sampled_gaussians_preprocess_forward_and_backward(name):
     assert float((rec["rgb"] - o["rgb"]).abs()[ok].max()) < 2e-6
     # backward of the sampled Gaussians from the HIP path's own grad2d rows
     # (of the full upstream gradient; an earlier test confined it to tiles)
-    r["view"].raster_bwd(r["img"], r["dL"])
+    r["view"].raster_bwd(r["dL"])
     torch.cuda.synchronize()
     g2d = r["view"].grad2d().cpu().to(F64)[idx]
     near = (o["rgb_raw"].abs() < 1e-5).any(1)
@@ -165,6 +180,31 @@ def test_sampled_gaussians_preprocess_forward_and_backward(name):
     got = {k: getattr(grads, k).cpu() for k in ("means", "scales", "quats", "opacities", "sh")}
     grad_close(got["means"][:, idx].T, want["means"], name=f"{name} means")
     grad_close(got["scales"][:, idx].T, want["scales"], name=f"{name} scales")
-    grad_close(got["quats"][:, idx].T, want["quats"], name=f"{name} quats")
+    grad_close(got["quats"][:, idx].T, want["quats"], name=f"{name} quats",
+               floor=quat_floor(sub, c, g2d))
     grad_close(got["opacities"][idx], want["opacities"], name=f"{name} opacities")
     grad_close(got["sh"][:, :, idx].permute(2, 0, 1), want["sh"], name=f"{name} sh")
+
+
+def test_l1_every_phase_at_4k():
+    """Stage a6 at the benchmark's 4K view (stride 2), all four pixel phases:
+    the HIP loss gradient element by element against the oracle's from the
+    same rendered image."""
+    r = _run("4k-3m-d2-o10")
+    view, dev, cam = r["view"], r["dev"], r["cam"]
+    _sc, _cam, tgt = scenes.workload(2)
+    target = torch.as_tensor(tgt).cuda()
+    img = torch.empty_like(r["img"])
+    for step in range(4):
+        ox, oy = scenes.phase_offsets(step, 2)
+        view.set_offsets(ox, oy)
+        view.forward(dev, img)
+        dL, loss = view.l1_grad(img, target)
+        torch.cuda.synchronize()
+        g = obn.grid(cam.width, cam.height, 2, ox, oy, 16)
+        rel = l1_matches_oracle(img.cpu(), dL.cpu(), loss[0], tgt, g, f"4k phase ({ox},{oy})")
+        say(f"[gpu] 4K phase ({ox},{oy}): {dL.numel()} dL/dimage values match, loss rel {rel:.1e}")
+    view.set_offsets(1, 0)                       # the cached forward state back
+    view.forward(dev, img)
+    torch.cuda.synchronize()
+    assert torch.equal(img.cpu(), r["image"])

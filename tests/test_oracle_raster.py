@@ -123,6 +123,28 @@ def test_tile_path_equals_per_pixel_loop(d, ox, oy, T):
             assert int(out["last_contrib"][j, i]) == last
 
 
+@pytest.mark.parametrize("seed", range(0, 240, 12))
+def test_tile_path_equals_per_pixel_loop_on_sweep_cases(seed):
+    """The same brute force on cases of the GPU property sweep (centres on
+    pixel and block edges, opacities beside 1/255 and 0.99, needles), with a
+    chunk of 8 entries so chunk boundaries fall inside the lists."""
+    sc, cam, d, ox, oy, T, bgc = scenes.sweep_case(seed)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    g = bn.grid(cam.width, cam.height, d, ox, oy, T)
+    b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+    out = rs.raster_forward(r, b["vals"], b["ranges"], g, bg=bgc, chunk=8)
+    order = sorted(range(sc.n), key=lambda i: (int(b["zbits"][i]), i))
+    rects = b["rects"].tolist()
+    for j in range(g.h_ds):
+        for i in range(g.w_ds):
+            tx, ty = i // T, j // T
+            member = lambda k: (rects[k][0] <= tx < rects[k][1] and rects[k][2] <= ty < rects[k][3])
+            col, Tf, last = rs.render_pixel_loop(r, order, member, d * i + ox, d * j + oy, bgc)
+            np.testing.assert_allclose(out["image"][:, j, i].numpy(), col, rtol=0, atol=1e-13)
+            assert abs(float(out["t_final"][j, i]) - Tf) <= 1e-15
+            assert int(out["last_contrib"][j, i]) == last
+
+
 def test_chunking_does_not_change_results():
     sc, cam = scenes.small_scene(9, 64, 64, 64, sh_degree=0)
     r = pre.preprocess(pre.params(sc), pre.camera(cam))
