@@ -59,7 +59,7 @@ __device__ __forceinline__ bool splat_test(const float4 gb, float p2, float& G, 
                                            float& alpha) {
     G = __builtin_amdgcn_exp2f(p2);
     raw = gb.y * G;
-    alpha = fminf(kAlphaMax, raw);
+    alpha = __builtin_amdgcn_fmed3f(raw, 0.0f, kAlphaMax);   // min(0.99, raw) for raw >= 0
     return p2 <= 0.0f && raw >= kAlphaMin;
 }
 
@@ -319,6 +319,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
         // branch-free per entry: a skipped entry adds exactly 0 and leaves T
         // (entries no pixel of the wavefront can reach are not visited)
         auto entry = [&](int e) {
+            bool any = false;
             if constexpr (COUNTS) {
 #pragma unroll
                 for (int k = 0; k < S::NP; ++k) ntest[k] += Ts[k] > 0.0f ? 1u : 0u;
@@ -345,13 +346,35 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
                 Ts[k] = stop ? -tn : tn;
                 const uint32_t pos = base - start + uint32_t(e) + 1;
                 last[k] = blend ? pos : last[k];
+                any = any || blend;
                 if constexpr (COUNTS) {
                     nblend[k] += blend ? 1u : 0u;
                     neval[k] = stop ? pos : neval[k];
                 }
             }
+            return __ballot(any) != 0;
         };
-        for_wave_entries(s_m, cnt, wave, live, entry);
+        // the same walk as for_wave_entries, also collecting per 64 entries
+        // the bits of those some pixel of this wavefront blended: they are
+        // all the backward has to visit
+        for (int c = 0; c < cnt; c += 64) {
+            const int q = c + __lane_id();
+            uint64_t m = __ballot(q < cnt && ((s_m[q] >> wave) & 1u));
+            uint64_t bm = 0;
+            while (m != 0 && __ballot(live()) != 0) {
+                const int j = int(__builtin_ctzll(m));
+                m &= m - 1;
+                if (entry(c + j)) bm |= uint64_t(1) << j;
+            }
+            if (bm != 0 && __lane_id() == 0) {
+                const uint64_t a = uint64_t(base) + uint64_t(c);        // pair of bit 0
+                unsigned long long* w = rv.bits + uint64_t(wave) * rv.bits_stride + (a >> 6);
+                const int sh = int(a & 63);
+                atomicOr(w, (unsigned long long)(bm << sh));
+                if (sh != 0 && (bm >> (64 - sh)) != 0)
+                    atomicOr(w + 1, (unsigned long long)(bm >> (64 - sh)));
+            }
+        }
     }
     // the tile's weight for the backward's schedule
     if (rv.work && tid == 0) rv.work[tile] = min(base, end) - start;
@@ -380,15 +403,25 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     }
 }
 
+// The blend bits of the 64 pairs from pair a on (bit j: pair a + j) of one
+// wavefront slot, read from two 64-bit words (the slot holds a spare word
+// past its last pair, so both are in bounds for any a below the capacity).
+__device__ __forceinline__ uint64_t blend_window(const unsigned long long* w, uint64_t a) {
+    const unsigned long long* p = w + (a >> 6);
+    const int sh = int(a & 63);
+    const uint64_t lo = p[0];
+    return sh == 0 ? lo : (lo >> sh) | (uint64_t(p[1]) << (64 - sh));
+}
+
 // Calls entry(e), from the last to the first, for the entries e < cnt of an
-// LDS batch whose wavefront mask has this wavefront's bit (the backward's
-// order: set bits of each 64-entry ballot taken from the highest).
+// LDS batch that some pixel of this wavefront blended in the forward (its
+// blend bits; the batch's entry e is pair a + e).
 template <class F>
-__device__ __forceinline__ void for_wave_entries_reverse(const uint32_t* s_m, int cnt, int wave,
-                                                         F&& entry) {
+__device__ __forceinline__ void for_blended_entries_reverse(const unsigned long long* bits,
+                                                            uint64_t a, int cnt, F&& entry) {
     for (int c = ((cnt - 1) >> 6) << 6; c >= 0; c -= 64) {
-        const int q = c + __lane_id();
-        uint64_t m = __ballot(q < cnt && ((s_m[q] >> wave) & 1u));
+        uint64_t m = blend_window(bits, a + uint64_t(c));
+        if (cnt - c < 64) m &= (uint64_t(1) << (cnt - c)) - 1;
         while (m != 0) {
             const int hb = 63 - __builtin_clzll(m);
             m ^= uint64_t(1) << hb;
@@ -399,7 +432,9 @@ __device__ __forceinline__ void for_wave_entries_reverse(const uint32_t* s_m, in
 
 // The blend backward: each pixel walks its list back to front, from the
 // last entry it blended (ws_last) down to the first, starting from its
-// final transmittance (ws_tfinal); both were left by the forward.  With
+// final transmittance (ws_tfinal); both were left by the forward, and so
+// were the blend bits, by which a wavefront visits only the entries some
+// of its pixels blended.  With
 // T_k the transmittance in front of entry k and B_k the colour behind it
 // seen through it (the blended colours of the later entries and the
 // background, composited from the back):
@@ -426,7 +461,6 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     using S = Shape<T, PPT>;
     __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
     __shared__ uint32_t s_id[BATCH];
-    __shared__ uint32_t s_m[BATCH];                              // wavefronts that look at it
     __shared__ uint32_t s_end;                                   // entries the tile walks
     // multi-wavefront tiles add their wavefronts' sums in LDS and flush each
     // batch with one set of global atomics per entry
@@ -445,9 +479,8 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     const int i0 = tx * T + S::px(tid), j0 = ty * T + S::py(tid);
     uint32_t start, end;
     tile_range(rv, tile, start, end);
-    WaveRects<S> wr;
-    wr.init(grid, tx, ty, T);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const unsigned long long* wbits = rv.bits + uint64_t(wave) * rv.bits_stride;
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
     // per pixel: the transmittance behind the current entry (T_final at the
     // start), the gradient-weighted colour behind it (the background at the
@@ -504,9 +537,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             stage_conic(r[0], r[1], ga, gb);
             s_a[q] = ga;
             s_b[q] = gb;
-            const float thr = skip_threshold(r[1].y);
             s_c[q] = make_float4(r[2].x, ga.z + ga.z, gb.x + gb.x, 0.0f);
-            s_m[q] = wave_mask<S>(ga, gb.x, thr, wr);
             s_id[q] = id;
         }
         if constexpr (kBlockSum)
@@ -521,37 +552,55 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
             bool blend[S::NP];
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) p2[k] = splat_exponent(a, b, X[k], Y[k], dx[k], dy[k], t[k]);
-            uint64_t any = 0;                         // lanes with a blending pixel
+            bool lane_any = false;                    // a pixel of this lane blends it
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
                 blend[k] = splat_test(b, p2[k], G[k], raw[k], alpha[k]) && pos < last[k];
-                any |= __ballot(blend[k]);
+                lane_any = lane_any || blend[k];
             }
-            if (any == 0) return;                     // no pixel of the wavefront blends it
+            if (__ballot(lane_any) == 0) return;      // no pixel of the wavefront blends it
             float gv[kGrad2d];
-            // where a pixel does not blend the entry every term it enters is
-            // selected away (w, dp and the G term are 0; T and S unchanged)
+            // ab = alpha where the pixel blends the entry, 0 elsewhere: then
+            // w, the S update, dp and the G term vanish by themselves (T is
+            // kept by a select, so it never picks up the rounding of a
+            // reciprocal of 1).  The lane's pixels are summed with FMAs.
 #pragma unroll
             for (int k = 0; k < S::NP; ++k) {
-                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha[k]);
+                const float ab = blend[k] ? alpha[k] : 0.0f;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - ab);
                 const float T0 = blend[k] ? Ts[k] * inv : Ts[k];    // in front of the entry
-                const float w = blend[k] ? alpha[k] * T0 : 0.0f;
+                const float w = ab * T0;
                 // dL/dalpha = T0 (sum_c dL/dC_c rgb_c - S)
                 const float gcol = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
                 const float diff = gcol - Sb[k];
                 const float dal = T0 * diff;
-                Sb[k] = blend[k] ? fmaf(alpha[k], diff, Sb[k]) : Sb[k];
+                Sb[k] = fmaf(ab, diff, Sb[k]);
                 // no gradient through the 0.99 clamp
                 const bool live = blend[k] && !(raw[k] > kAlphaMax);
-                const float dp = live ? alpha[k] * dal : 0.0f;
+                const float dp = (live ? alpha[k] : 0.0f) * dal;
+                const float Gl = live ? G[k] : 0.0f;
                 const float pdx = dp * dx[k], pdy = dp * dy[k];
-                const float m[kGrad2d] = {
-                    pdx, pdy,                               // dp dx, dp dy
-                    pdx * dx[k], pdx * dy[k], pdy * dy[k],
-                    live ? G[k] * dal : 0.0f,
-                    w * g0[k], w * g1[k], w * g2[k]};
-#pragma unroll
-                for (int q = 0; q < kGrad2d; ++q) gv[q] = k == 0 ? m[q] : gv[q] + m[q];
+                if (k == 0) {
+                    gv[0] = pdx;
+                    gv[1] = pdy;
+                    gv[2] = pdx * dx[k];
+                    gv[3] = pdx * dy[k];
+                    gv[4] = pdy * dy[k];
+                    gv[5] = Gl * dal;
+                    gv[6] = w * g0[k];
+                    gv[7] = w * g1[k];
+                    gv[8] = w * g2[k];
+                } else {
+                    gv[0] += pdx;
+                    gv[1] += pdy;
+                    gv[2] = fmaf(pdx, dx[k], gv[2]);
+                    gv[3] = fmaf(pdx, dy[k], gv[3]);
+                    gv[4] = fmaf(pdy, dy[k], gv[4]);
+                    gv[5] = fmaf(Gl, dal, gv[5]);
+                    gv[6] = fmaf(w, g0[k], gv[6]);
+                    gv[7] = fmaf(w, g1[k], gv[7]);
+                    gv[8] = fmaf(w, g2[k], gv[8]);
+                }
                 Ts[k] = T0;
             }
             int comp;
@@ -568,7 +617,7 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         };
         // entries at or past this wavefront's last blend change nothing
         const int wcnt = min(cnt, max(0, int(wend) - lo));
-        for_wave_entries_reverse(s_m, wcnt, wave, entry);
+        for_blended_entries_reverse(wbits, uint64_t(start) + uint64_t(lo), wcnt, entry);
         if constexpr (kBlockSum) {
             __syncthreads();
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) {
@@ -739,6 +788,15 @@ void launch_batch(bool fwd, int batch, const RasterViews& vt, hipStream_t s) {
 hipError_t launch_raster(bool fwd, int tile, int ppt, int batch, const RasterViews& vt,
                          hipStream_t s) {
     if (vt.count == 0 || vt.first_block[vt.count] == 0) return hipSuccess;
+    if (fwd) {
+        // the forward ORs the blend bits of its wavefront slots in: clear them
+        const uint64_t waves = uint64_t(tile) * tile / uint64_t(ppt) / 64;
+        for (int k = 0; k < vt.count; ++k) {
+            const hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(vt.v[k].bits), 0u,
+                                          2 * waves * vt.v[k].bits_stride, s);
+            if (e != hipSuccess) return e;
+        }
+    }
     if (tile == 8) {
         launch_batch<8, 1>(fwd, batch, vt, s);
     } else if (tile == 32) {

@@ -127,12 +127,14 @@ def grad_close(got: torch.Tensor, want: torch.Tensor, rel=1e-3, name="", floor=N
         return 0.0
     nrel = float(torch.linalg.norm(got - want) / torch.linalg.norm(want))
     bound = rel * (want.abs() + rel * gmax)
+    plain = float((d / bound).max())
     if floor is not None:
         bound = bound + torch.as_tensor(floor, dtype=F64).flatten()
     ratio = d / bound
     worst = float(ratio.max())
     if not quiet:
-        say(f"[grad] {name}: norm-rel {nrel:.2e}, worst element {worst:.3f} of its bound")
+        extra = f" ({plain:.3f} of the bar without the allowance)" if floor is not None else ""
+        say(f"[grad] {name}: norm-rel {nrel:.2e}, worst element {worst:.3f} of its bound{extra}")
     assert nrel <= rel, f"{name}: norm-relative error {nrel:.3e}"
     bad = ratio > 1.0
     assert not bool(bad.any()), (f"{name}: {int(bad.sum())} elements out of bound, worst "
