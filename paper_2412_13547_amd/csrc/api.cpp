@@ -233,7 +233,7 @@ tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const
     v.ws_tfinal = reinterpret_cast<float*>(ws + L.pix_tfinal);
     v.ws_last = reinterpret_cast<uint32_t*>(ws + L.pix_last);
     v.bits = reinterpret_cast<unsigned long long*>(ws + L.blend_bits);
-    v.bits_stride = tgs::blend_words(st.pair_capacity);
+    v.bits_stride = tgs::blend_words(st.pair_capacity, grid.num_tiles());
     return v;
 }
 
@@ -347,7 +347,7 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.tile_order = take(uint64_t(grid.num_tiles()) * 4);
     L.pix_tfinal = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
     L.pix_last = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
-    L.blend_bits = take(uint64_t(max_tile_waves(grid.tile)) * blend_words(cap) * 8);
+    L.blend_bits = take(uint64_t(max_tile_waves(grid.tile)) * blend_words(cap, grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
     uint64_t most = radix_counts_elems(un);

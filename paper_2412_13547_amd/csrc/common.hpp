@@ -68,9 +68,10 @@ struct Layout {
     uint64_t pix_tfinal;       // float[h_ds][w_ds], transmittance after each pixel's walk
     uint64_t pix_last;         // uint32[h_ds][w_ds], 1-based index of each pixel's last
                                //   blended list entry (0: none)
-    uint64_t blend_bits;       // uint64[max_tile_waves(T)][blend_words(capacity)]: per
-                               //   wavefront slot of a tile, bit i set when some pixel of
-                               //   that wavefront blended pair i (the forward writes it)
+    uint64_t blend_bits;       // uint64[max_tile_waves(T)][blend_words(capacity, tiles)]:
+                               //   per wavefront slot of a tile and per 64 list entries
+                               //   of the tile, the entries some pixel of that wavefront
+                               //   blended (written by the forward)
     uint64_t grad2d;           // float[n][9]
     uint64_t sort_counts;      // uint32, radix digit counts, then the number of Gaussians
                                //   with tiles (at radix_kept_offset(n))
@@ -82,10 +83,14 @@ Layout make_layout(int64_t n, uint64_t pair_capacity, const Grid& grid);
 
 // Wavefronts of a tile of every work split of a tile size (T = 8: 1; T = 16:
 // up to 4; T = 32: up to 8), and the 64-bit words of one wavefront slot's
-// blend bits (one bit per pair, plus a word so that a 64-bit window starting
-// at any pair stays inside).
+// blend bits.  Chunk c (entries [64 c, 64 c + 64) of the list) of the tile
+// whose pairs start at s has word floor(s / 64) + tile + c: every (tile,
+// chunk) owns a word of its own, so the forward writes them without
+// atomics or clearing.
 inline int max_tile_waves(int tile) { return tile == 8 ? 1 : tile == 16 ? 4 : 8; }
-inline uint64_t blend_words(uint64_t capacity) { return (capacity + 63) / 64 + 1; }
+inline uint64_t blend_words(uint64_t capacity, int64_t tiles) {
+    return (capacity + 63) / 64 + uint64_t(tiles) + 1;
+}
 
 // Device kernel launchers (stream-ordered, no synchronisation).
 struct CamDev {
@@ -194,7 +199,7 @@ struct RasterView {
     uint32_t* work;           // forward out, optional: entries walked per tile
     uint32_t* order;          // backward, optional: the tile of each workgroup, a
                               //   permutation of the tiles written before the walk
-    unsigned long long* bits; // forward out (zeroed first) / backward in: blend bits,
+    unsigned long long* bits; // forward out / backward in: blend bits,
                               //   bits_stride words per wavefront slot
     uint64_t bits_stride;
 };

@@ -366,14 +366,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
                 m &= m - 1;
                 if (entry(c + j)) bm |= uint64_t(1) << j;
             }
-            if (bm != 0 && __lane_id() == 0) {
-                const uint64_t a = uint64_t(base) + uint64_t(c);        // pair of bit 0
-                unsigned long long* w = rv.bits + uint64_t(wave) * rv.bits_stride + (a >> 6);
-                const int sh = int(a & 63);
-                atomicOr(w, (unsigned long long)(bm << sh));
-                if (sh != 0 && (bm >> (64 - sh)) != 0)
-                    atomicOr(w + 1, (unsigned long long)(bm >> (64 - sh)));
-            }
+            if (__lane_id() == 0)                    // entry base + c is chunk (base - start + c) / 64
+                rv.bits[uint64_t(wave) * rv.bits_stride + (start >> 6) + uint64_t(tile) +
+                        (base - start + uint32_t(c)) / 64u] = bm;
         }
     }
     // the tile's weight for the backward's schedule
@@ -403,24 +398,15 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
     }
 }
 
-// The blend bits of the 64 pairs from pair a on (bit j: pair a + j) of one
-// wavefront slot, read from two 64-bit words (the slot holds a spare word
-// past its last pair, so both are in bounds for any a below the capacity).
-__device__ __forceinline__ uint64_t blend_window(const unsigned long long* w, uint64_t a) {
-    const unsigned long long* p = w + (a >> 6);
-    const int sh = int(a & 63);
-    const uint64_t lo = p[0];
-    return sh == 0 ? lo : (lo >> sh) | (uint64_t(p[1]) << (64 - sh));
-}
-
 // Calls entry(e), from the last to the first, for the entries e < cnt of an
-// LDS batch that some pixel of this wavefront blended in the forward (its
-// blend bits; the batch's entry e is pair a + e).
+// LDS batch that some pixel of this wavefront blended in the forward: the
+// blend bits, one word per 64 entries from word `chunk` on (the batch
+// starts at a multiple of 64 entries of the tile's list).
 template <class F>
 __device__ __forceinline__ void for_blended_entries_reverse(const unsigned long long* bits,
-                                                            uint64_t a, int cnt, F&& entry) {
+                                                            uint64_t chunk, int cnt, F&& entry) {
     for (int c = ((cnt - 1) >> 6) << 6; c >= 0; c -= 64) {
-        uint64_t m = blend_window(bits, a + uint64_t(c));
+        uint64_t m = bits[chunk + uint64_t(c >> 6)];
         if (cnt - c < 64) m &= (uint64_t(1) << (cnt - c)) - 1;
         while (m != 0) {
             const int hb = 63 - __builtin_clzll(m);
@@ -526,10 +512,11 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     const float scale = own == 0 || own == 1 ? kLn2
                         : own == 2 || own == 4 ? -0.5f
                         : own == 3 ? -1.0f : 1.0f;
-    for (int hi = int(tend); hi > 0; hi -= BATCH) {
-        const int lo = max(0, hi - BATCH);
-        const int cnt = hi - lo;
-        if (hi != int(tend)) __syncthreads();                    // the previous batch is done
+    // batches of the list from the back, starting at multiples of BATCH
+    const int top = int(tend) == 0 ? -1 : (int(tend) - 1) / BATCH * BATCH;
+    for (int lo = top; lo >= 0; lo -= BATCH) {
+        const int cnt = min(BATCH, int(tend) - lo);
+        if (lo != top) __syncthreads();                          // the previous batch is done
         for (int q = tid; q < cnt; q += S::NT) {
             const uint32_t id = rv.vals[start + uint32_t(lo + q)];
             const float4* r = rv.rec + 3 * uint64_t(id);
@@ -617,7 +604,8 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         };
         // entries at or past this wavefront's last blend change nothing
         const int wcnt = min(cnt, max(0, int(wend) - lo));
-        for_blended_entries_reverse(wbits, uint64_t(start) + uint64_t(lo), wcnt, entry);
+        for_blended_entries_reverse(wbits, (start >> 6) + uint64_t(tile) + uint64_t(lo / 64), wcnt,
+                                    entry);
         if constexpr (kBlockSum) {
             __syncthreads();
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) {
@@ -788,15 +776,6 @@ void launch_batch(bool fwd, int batch, const RasterViews& vt, hipStream_t s) {
 hipError_t launch_raster(bool fwd, int tile, int ppt, int batch, const RasterViews& vt,
                          hipStream_t s) {
     if (vt.count == 0 || vt.first_block[vt.count] == 0) return hipSuccess;
-    if (fwd) {
-        // the forward ORs the blend bits of its wavefront slots in: clear them
-        const uint64_t waves = uint64_t(tile) * tile / uint64_t(ppt) / 64;
-        for (int k = 0; k < vt.count; ++k) {
-            const hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(vt.v[k].bits), 0u,
-                                          2 * waves * vt.v[k].bits_stride, s);
-            if (e != hipSuccess) return e;
-        }
-    }
     if (tile == 8) {
         launch_batch<8, 1>(fwd, batch, vt, s);
     } else if (tile == 32) {
