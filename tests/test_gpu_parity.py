@@ -192,9 +192,14 @@ def test_backward_tile_order_leaves_gradients_unchanged(name):
         torch.cuda.synchronize()
         a, b = view.grad2d().cpu().to(F64), ref["grad2d"].to(F64)
         assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, trial
+        # the parameter gradients at the gradient bar (the quaternion's with
+        # its projection allowance: another atomic order moves a component
+        # that is a near-cancelling difference by more than 1e-5 of the max)
+        qfloor = quat_floor(sc, cam, ref["grad2d"])
         for k in ("means", "scales", "quats", "opacities", "sh"):
             a, b = getattr(grads, k).cpu().to(F64), ref["grads"][k].to(F64)
-            assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max()) + 1e-12, (trial, k)
+            grad_close(a, b, name=f"{name} order {trial} {k}", quiet=True,
+                       floor=qfloor.T if k == "quats" else None)
         # the forward takes its order from the weights left in the workspace
         view.tile_work().copy_(w.to(torch.int32).cuda())
         img = torch.empty_like(image)
