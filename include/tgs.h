@@ -282,6 +282,26 @@ tgs_status tgs_forward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camer
                        const tgs_dilation* dil, const tgs_options* opt, tgs_state* st,
                        float* image, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid it): tgs_forward without a
+ * caller workspace.  Every intermediate lives in a static device array of
+ * TGS_STATIC_SCRATCH_BYTES bytes that each GPU the library runs on holds
+ * from the library's load to the end of the process; the call allocates
+ * nothing.  The caller passes the Gaussians, camera, dilation, options and
+ * the image [3][H_ds][W_ds] (device) and chooses pair_capacity.  A request
+ * whose workspace (n Gaussians, the tile grid, pair_capacity pairs; the
+ * bytes tgs_query_sizes reports) exceeds the array returns
+ * TGS_ERR_UNSUPPORTED before any device work.  Pairs beyond pair_capacity
+ * behave as in tgs_bin_sort: asynchronous by default (the image is the
+ * background), or TGS_ERR_CAPACITY with TGS_SYNC_CHECK in opt->flags.
+ * All calls on one GPU share its array and the array keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads)
+ * race, and no state survives for a backward. */
+#define TGS_STATIC_SCRATCH_BYTES (64ull << 20)
+tgs_status tgs_forward_static(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                              const tgs_dilation* dil, const tgs_options* opt,
+                              uint64_t pair_capacity, float* image, void* stream);
+
 /* L1 photometric loss of Sec. 4.1 / Fig. 2: each rendered pixel against the
  * full-resolution target pixel it was rendered at.  L = mean over rendered
  * pixels and channels of |image - target|; dL_dimage = sign(.) / (3 W_ds H_ds)

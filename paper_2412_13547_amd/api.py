@@ -20,12 +20,14 @@ TGS_OK, TGS_ERR_INVALID_ARG, TGS_ERR_CAPACITY, TGS_ERR_HIP, TGS_ERR_NO_DEVICE, T
 EXPORTED = (
     "tgs_status_str", "tgs_last_error", "tgs_version", "tgs_create", "tgs_destroy",
     "tgs_query_sizes", "tgs_default_launch", "tgs_preprocess_fwd", "tgs_bin_sort", "tgs_raster_fwd", "tgs_forward",
+    "tgs_forward_static",
     "tgs_l1_grad", "tgs_raster_bwd", "tgs_preprocess_bwd", "tgs_backward",
     "tgs_batch_preprocess_fwd", "tgs_batch_bin_sort", "tgs_batch_raster_fwd",
     "tgs_batch_forward", "tgs_batch_l1_grad", "tgs_batch_raster_bwd", "tgs_batch_preprocess_bwd",
     "tgs_batch_backward", "tgs_pair_counts", "tgs_adam_step", "tgs_densify_query",
     "tgs_densify_select",
 )
+STATIC_SCRATCH_BYTES = 64 << 20
 ADAM_STATE_BYTES = 16
 MAX_ADAM_GROUPS = 8
 
@@ -113,6 +115,8 @@ def _declare(lib):
                                      _P(tgs_state), C.c_int64, vp, vp, vp, vp, vp, vp]),
         "tgs_forward": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
                                   _P(tgs_options), _P(tgs_state), vp, vp]),
+        "tgs_forward_static": (C.c_int, [vp, _P(tgs_gaussians), _P(tgs_camera), _P(tgs_dilation),
+                                         _P(tgs_options), C.c_uint64, vp, vp]),
         "tgs_l1_grad": (C.c_int, [vp, _P(tgs_camera), _P(tgs_dilation), vp, vp, vp, vp, vp]),
         "tgs_raster_bwd": (C.c_int, [vp, _P(tgs_camera), _P(tgs_dilation), _P(tgs_options),
                                      _P(tgs_state), C.c_int64, vp, vp]),
@@ -516,6 +520,22 @@ class View:
         """Entries the last forward walked per tile (the backward's tile order
         weights; any values give the same results)."""
         return self._view(self.state.off_tile_work, int(self.sizes.num_tiles), self._torch.int32)
+
+
+def forward_static(ctx: Context, scene: DeviceScene, cam, image, pair_capacity: int, stride=1,
+                   off_x=0, off_y=0, tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0,
+                   pixels_per_thread=0, sync_check=False, stream=None):
+    """tgs_forward_static: the forward of one view into ``image`` with the
+    library's static per-GPU scratch as workspace (no allocation).  Raises
+    TgsError(TGS_ERR_UNSUPPORTED) when the request needs more workspace than
+    STATIC_SCRATCH_BYTES."""
+    g = scene.struct()
+    opt = options_struct(tile, bg, lds_batch, pixels_per_thread, SYNC_CHECK if sync_check else 0)
+    check(lib().tgs_forward_static(ctx.handle if ctx is not None else None, C.byref(g),
+                                   C.byref(camera_struct(cam)),
+                                   C.byref(dilation_struct(stride, off_x, off_y)), C.byref(opt),
+                                   int(pair_capacity), _ptr(image), _stream(stream)))
+    return image
 
 
 def _grads_struct(grads: DeviceScene) -> tgs_grads:

@@ -26,8 +26,15 @@ constexpr uint64_t kMaxPairCapacity = TGS_MAX_PAIR_CAPACITY;
 static_assert(kMaxPairCapacity == kSaturated - 1, "capacity limit below the saturated count");
 }
 
+// The workspace of tgs_forward_static: a device array every GPU the library
+// runs on holds once, for the whole process.  Host code never uses its name
+// as an address (that is a host-side stand-in); tgs_create looks up the
+// device address of this GPU's copy and keeps it in the context.
+static __device__ __align__(256) uint8_t scratch[TGS_STATIC_SCRATCH_BYTES];
+
 struct tgs_context {
     int device;
+    void* scratch;      // device address of this GPU's static scratch array
     uint64_t* pinned;   // host-pinned readback of the tile-row starts
     hipStream_t aux[kAuxStreams];
     hipEvent_t fork;
@@ -416,9 +423,14 @@ tgs_status tgs_create(int device, tgs_context** out) {
     auto* ctx = new (std::nothrow) tgs_context{};
     if (!ctx) return fail(TGS_ERR_HIP, "out of host memory");
     ctx->device = device;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kPinnedBytes,
-                                 hipHostMallocDefault);
-    const char* what = "hipHostMalloc";
+    // this device's copy of the static scratch array (device current)
+    hipError_t e = hipGetSymbolAddress(&ctx->scratch, HIP_SYMBOL(scratch));
+    const char* what = "hipGetSymbolAddress";
+    if (e == hipSuccess) {
+        what = "hipHostMalloc";
+        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kPinnedBytes,
+                          hipHostMallocDefault);
+    }
     // default-priority streams, not synchronising with the null stream
     for (int a = 0; a < kAuxStreams && e == hipSuccess; ++a) {
         what = "hipStreamCreateWithFlags";
@@ -592,6 +604,37 @@ tgs_status tgs_forward(tgs_context* ctx, const tgs_gaussians* g, const tgs_camer
         s = tgs_raster_fwd(ctx, cam, dil, opt, st, g->n, image, nullptr, nullptr, nullptr, nullptr,
                            stream);
     return s;
+}
+
+tgs_status tgs_forward_static(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
+                              const tgs_dilation* dil, const tgs_options* opt,
+                              uint64_t pair_capacity, float* image, void* stream) {
+    tgs_status s = check_gaussians(g);
+    if (s == TGS_OK) s = check_common(cam, dil, opt);
+    if (s == TGS_OK && !opt) s = fail(TGS_ERR_INVALID_ARG, "options is NULL");
+    if (s != TGS_OK) return s;
+    if (!image) return fail(TGS_ERR_INVALID_ARG, "image is NULL");
+    if (pair_capacity == 0 || pair_capacity > kMaxPairCapacity)
+        return fail(TGS_ERR_UNSUPPORTED, "pair_capacity %llu outside [1, %llu]",
+                    (unsigned long long)pair_capacity, (unsigned long long)kMaxPairCapacity);
+    const tgs::Grid grid = tgs::make_grid(*cam, *dil, opt->tile);
+    const tgs::Layout L = tgs::make_layout(g->n, pair_capacity, grid);
+    if (L.total > TGS_STATIC_SCRATCH_BYTES)
+        return fail(TGS_ERR_UNSUPPORTED,
+                    "%lld Gaussians, a %d x %d tile grid and %llu pairs need %llu bytes of "
+                    "workspace, above the static scratch of %llu bytes",
+                    (long long)g->n, grid.gx, grid.gy, (unsigned long long)pair_capacity,
+                    (unsigned long long)L.total, (unsigned long long)TGS_STATIC_SCRATCH_BYTES);
+    if (!ctx) return fail(TGS_ERR_INVALID_ARG, "context is NULL");
+    if (!ctx->scratch) return fail(TGS_ERR_HIP, "the static scratch was not set up");
+    // the same stages as tgs_forward on a state whose workspace is this
+    // GPU's scratch; nothing in it has to start at zero (every stage writes
+    // what it reads later in the call)
+    tgs_state st{};
+    st.workspace = ctx->scratch;
+    st.workspace_bytes = TGS_STATIC_SCRATCH_BYTES;
+    st.pair_capacity = pair_capacity;
+    return tgs_forward(ctx, g, cam, dil, opt, &st, image, stream);
 }
 
 tgs_status tgs_l1_grad(tgs_context* ctx, const tgs_camera* cam, const tgs_dilation* dil,

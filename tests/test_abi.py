@@ -250,3 +250,34 @@ def test_batch_backward_and_counts_refuse_unbinned_states():
     io[0].target = None
     r = lib.tgs_batch_l1_grad(None, 2, cams, dils, io, None, None)
     assert r == api.TGS_ERR_INVALID_ARG and b"view 0" in lib.tgs_last_error()
+
+
+def test_forward_static_rejects_what_exceeds_the_scratch_on_the_host():
+    """The no-allocation forward checks its request against the static
+    scratch before any device call: the same workspace tgs_query_sizes
+    reports must fit TGS_STATIC_SCRATCH_BYTES, else TGS_ERR_UNSUPPORTED."""
+    lib = api.lib()
+    cam, dil, opt = _cam(), api.dilation_struct(), api.options_struct(16)
+    out = api.tgs_sizes()
+    n_fit, cap_fit = 1000, 100_000
+    assert lib.tgs_query_sizes(n_fit, C.byref(cam), C.byref(dil), C.byref(opt), cap_fit,
+                               C.byref(out)) == api.TGS_OK
+    assert out.workspace_bytes <= api.STATIC_SCRATCH_BYTES
+    # fits: the first failure is the missing context
+    r = lib.tgs_forward_static(None, C.byref(_gauss(n_fit)), C.byref(cam), C.byref(dil),
+                               C.byref(opt), cap_fit, 1 << 20, None)
+    assert r == api.TGS_ERR_INVALID_ARG and b"context" in lib.tgs_last_error()
+    # too many pairs, and too many Gaussians
+    for n, cap in ((n_fit, 8_000_000), (2_000_000, cap_fit)):
+        assert lib.tgs_query_sizes(n, C.byref(cam), C.byref(dil), C.byref(opt), cap,
+                                   C.byref(out)) == api.TGS_OK
+        assert out.workspace_bytes > api.STATIC_SCRATCH_BYTES
+        r = lib.tgs_forward_static(None, C.byref(_gauss(n)), C.byref(cam), C.byref(dil),
+                                   C.byref(opt), cap, 1 << 20, None)
+        assert r == api.TGS_ERR_UNSUPPORTED and b"static scratch" in lib.tgs_last_error()
+    r = lib.tgs_forward_static(None, C.byref(_gauss(n_fit)), C.byref(cam), C.byref(dil),
+                               C.byref(opt), 0, 1 << 20, None)
+    assert r == api.TGS_ERR_UNSUPPORTED
+    r = lib.tgs_forward_static(None, C.byref(_gauss(n_fit)), C.byref(cam), C.byref(dil),
+                               C.byref(opt), cap_fit, None, None)
+    assert r == api.TGS_ERR_INVALID_ARG
