@@ -178,6 +178,9 @@ typedef struct tgs_state {
                                          pixel's last blended list entry (0: none), written
                                          by the last forward; with off_t_final, what the
                                          backward reads                                  */
+    uint64_t off_nonfinite_count;/* out: uint32 on the device, the Gaussians the last
+                                         preprocess culled because a parameter was not
+                                         finite (diagnostics)                            */
 } tgs_state;
 
 /* st->pair_count after a batched bin/sort, until tgs_pair_counts reads the
@@ -202,6 +205,10 @@ typedef struct tgs_view_io {
                                 its wavefront evaluated pixel by pixel (the others it skipped
                                 on a bound over its 8 x 8 pixel block); a measure of the
                                 rasterizer's work, not of the method's result              */
+    float* pos_stat;         /* optional [n]: this view's positional statistic (Sec. 4.3),
+                                written by the batched preprocess backward                  */
+    float* col_stat;         /* optional [n]: this view's appearance statistic               */
+    uint8_t* visible;        /* optional [n]: 1 where this view sees the Gaussian            */
 } tgs_view_io;
 
 typedef struct tgs_context tgs_context;
@@ -411,12 +418,14 @@ tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views,
  * over the views (the Gaussians are shared, so the gradient of the summed
  * loss is the sum).  The statistics of Sec. 4.3 are summed over the views
  * where the Gaussian is visible and visible[i] counts those views.  Each of
- * pos_stat, col_stat, visible may be NULL. */
+ * pos_stat, col_stat, visible may be NULL.  io may be NULL; where it is not,
+ * io[v].pos_stat / col_stat / visible (each optional) receive view v's own
+ * statistics (as tgs_preprocess_bwd of that view alone would write them). */
 tgs_status tgs_batch_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
                                     const tgs_camera* cams, const tgs_dilation* dils,
                                     const tgs_options* opt, const tgs_state* states,
-                                    const tgs_grads* out, float* pos_stat, float* col_stat,
-                                    uint8_t* visible, void* stream);
+                                    const tgs_view_io* io, const tgs_grads* out, float* pos_stat,
+                                    float* col_stat, uint8_t* visible, void* stream);
 
 /* Stages (d1)-(d2) for every view, the two calls above in order. */
 tgs_status tgs_batch_backward(tgs_context* ctx, const tgs_gaussians* g, int32_t views,

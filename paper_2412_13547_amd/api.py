@@ -78,7 +78,8 @@ class tgs_state(C.Structure):
                 ("off_pair_vals", C.c_uint64), ("off_ranges", C.c_uint64),
                 ("off_grad2d", C.c_uint64), ("off_pair_count", C.c_uint64),
                 ("off_depth_count", C.c_uint64), ("off_tile_work", C.c_uint64),
-                ("off_t_final", C.c_uint64), ("off_last_contrib", C.c_uint64)]
+                ("off_t_final", C.c_uint64), ("off_last_contrib", C.c_uint64),
+                ("off_nonfinite_count", C.c_uint64)]
 
 
 class tgs_adam_group(C.Structure):
@@ -89,7 +90,8 @@ class tgs_adam_group(C.Structure):
 class tgs_view_io(C.Structure):
     _fields_ = [("image", C.c_void_p), ("t_final", C.c_void_p), ("last_contrib", C.c_void_p),
                 ("n_eval", C.c_void_p), ("n_blend", C.c_void_p), ("target", C.c_void_p),
-                ("dL_dimage", C.c_void_p), ("n_tested", C.c_void_p)]
+                ("dL_dimage", C.c_void_p), ("n_tested", C.c_void_p), ("pos_stat", C.c_void_p),
+                ("col_stat", C.c_void_p), ("visible", C.c_void_p)]
 
 
 _P = C.POINTER
@@ -153,7 +155,7 @@ def _declare(lib):
                                            _P(tgs_view_io), vp]),
         "tgs_batch_preprocess_bwd": (C.c_int, [vp, _P(tgs_gaussians), C.c_int32, _P(tgs_camera),
                                                _P(tgs_dilation), _P(tgs_options), _P(tgs_state),
-                                               _P(tgs_grads), vp, vp, vp, vp]),
+                                               _P(tgs_view_io), _P(tgs_grads), vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -516,6 +518,11 @@ class View:
         h, w = int(self.sizes.h_ds), int(self.sizes.w_ds)
         return self._view(self.state.off_last_contrib, h * w, self._torch.int32).view(h, w)
 
+    def nonfinite_count(self) -> int:
+        """Gaussians the last preprocess culled for a non-finite parameter
+        (reads the device counter back)."""
+        return int(self._view(self.state.off_nonfinite_count, 1, self._torch.int32).item())
+
     def tile_work(self):
         """Entries the last forward walked per tile (the backward's tile order
         weights; any values give the same results)."""
@@ -555,7 +562,8 @@ class Batch:
     float32 device tensors set with ``set_targets``."""
 
     def __init__(self, ctx: Context, n: int, views, tile=16, bg=(0.0, 0.0, 0.0), lds_batch=0,
-                 pair_capacity=None, counts: bool = False, pixels_per_thread: int = 0):
+                 pair_capacity=None, counts: bool = False, pixels_per_thread: int = 0,
+                 view_stats: bool = False):
         import torch
         self._torch = torch
         nv = len(views)
@@ -586,10 +594,20 @@ class Batch:
             self.n_eval = [px(v, i32) for v in self.views]
             self.n_blend = [px(v, i32) for v in self.views]
             self.n_tested = [px(v, i32) for v in self.views]
+        # each view's own densification statistics (besides the summed ones)
+        self.view_pos = self.view_col = self.view_vis = None
+        if view_stats:
+            self.view_pos = [torch.zeros(n, dtype=f32, device="cuda") for _ in range(nv)]
+            self.view_col = [torch.zeros(n, dtype=f32, device="cuda") for _ in range(nv)]
+            self.view_vis = [torch.zeros(n, dtype=torch.uint8, device="cuda") for _ in range(nv)]
         for k in range(nv):
             io = self.io[k]
             io.image = _ptr(self.images[k])
             io.dL_dimage = _ptr(self.dL[k])
+            if view_stats:
+                io.pos_stat = _ptr(self.view_pos[k])
+                io.col_stat = _ptr(self.view_col[k])
+                io.visible = _ptr(self.view_vis[k])
             if counts:
                 io.t_final = _ptr(self.t_final[k])
                 io.last_contrib = _ptr(self.last_contrib[k])
@@ -639,7 +657,7 @@ class Batch:
         g = scene.struct()
         out = _grads_struct(grads)
         check(lib().tgs_batch_preprocess_bwd(self.ctx.handle, C.byref(g), self.nv, self.cams,
-                                             self.dils, C.byref(self.opt), self.states,
+                                             self.dils, C.byref(self.opt), self.states, self.io,
                                              C.byref(out), _ptr(pos_stat), _ptr(col_stat),
                                              _ptr(visible), _stream(stream)))
 

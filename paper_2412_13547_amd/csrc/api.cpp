@@ -199,6 +199,7 @@ void publish_offsets(tgs_state* st, const tgs::Layout& L, const tgs::Grid& grid,
     st->off_tile_work = L.tile_work;
     st->off_t_final = L.pix_tfinal;
     st->off_last_contrib = L.pix_last;
+    st->off_nonfinite_count = L.nonfinite;
 }
 
 tgs_status use_device(tgs_context* ctx) {
@@ -219,6 +220,7 @@ tgs::PrepView prep_view(const tgs_camera& cam, const tgs::Grid& grid, uint8_t* w
     v.depth_key = reinterpret_cast<uint32_t*>(ws + L.depth_key[0]);
     v.depth_val = reinterpret_cast<uint32_t*>(ws + L.depth_val[0]);
     v.g2d = reinterpret_cast<const float*>(ws + L.grad2d);
+    v.nonfinite = reinterpret_cast<uint32_t*>(ws + L.nonfinite);
     return v;
 }
 
@@ -354,6 +356,7 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.tile_order = take(uint64_t(grid.num_tiles()) * 4);
     L.pix_tfinal = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
     L.pix_last = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
+    L.nonfinite = take(4);
     L.blend_bits = take(uint64_t(max_tile_waves(grid.tile)) * blend_words(cap, grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
@@ -948,8 +951,8 @@ tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views, cons
 tgs_status tgs_batch_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, int32_t views,
                                     const tgs_camera* cams, const tgs_dilation* dils,
                                     const tgs_options* opt, const tgs_state* states,
-                                    const tgs_grads* out, float* pos_stat, float* col_stat,
-                                    uint8_t* visible, void* stream) {
+                                    const tgs_view_io* io, const tgs_grads* out, float* pos_stat,
+                                    float* col_stat, uint8_t* visible, void* stream) {
     tgs::Grid grids[TGS_MAX_VIEWS];
     tgs::Layout Ls[TGS_MAX_VIEWS];
     TGS_CHECK(check_gaussians(g));
@@ -958,8 +961,14 @@ tgs_status tgs_batch_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, in
     TGS_CHECK(use_device(ctx));
     tgs::PrepViews pt{};
     pt.count = views;
-    for (int v = 0; v < views; ++v)
+    for (int v = 0; v < views; ++v) {
         pt.v[v] = prep_view(cams[v], grids[v], static_cast<uint8_t*>(states[v].workspace), Ls[v]);
+        if (io) {
+            pt.v[v].pos_out = io[v].pos_stat;
+            pt.v[v].col_out = io[v].col_stat;
+            pt.v[v].vis_out = io[v].visible;
+        }
+    }
     TGS_HIP(tgs::launch_preprocess_bwd(*g, pt, *out, pos_stat, col_stat, visible,
                                        static_cast<hipStream_t>(stream)));
     return TGS_OK;
@@ -978,7 +987,7 @@ tgs_status tgs_batch_backward(tgs_context* ctx, const tgs_gaussians* g, int32_t 
     TGS_CHECK(check_io(views, io, true));
     TGS_CHECK(check_binned_views(views, states, grids, Ls));
     TGS_CHECK(tgs_batch_raster_bwd(ctx, g->n, views, cams, dils, opt, states, io, stream));
-    return tgs_batch_preprocess_bwd(ctx, g, views, cams, dils, opt, states, out, pos_stat,
+    return tgs_batch_preprocess_bwd(ctx, g, views, cams, dils, opt, states, io, out, pos_stat,
                                     col_stat, visible, stream);
 }
 

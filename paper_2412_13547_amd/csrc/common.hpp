@@ -68,6 +68,8 @@ struct Layout {
     uint64_t pix_tfinal;       // float[h_ds][w_ds], transmittance after each pixel's walk
     uint64_t pix_last;         // uint32[h_ds][w_ds], 1-based index of each pixel's last
                                //   blended list entry (0: none)
+    uint64_t nonfinite;        // uint32: Gaussians the last preprocess culled for a
+                               //   non-finite parameter (diagnostics)
     uint64_t blend_bits;       // uint64[max_tile_waves(T)][blend_words(capacity, tiles)]:
                                //   per wavefront slot of a tile and per 64 list entries
                                //   of the tile, the entries some pixel of that wavefront
@@ -117,6 +119,10 @@ struct PrepView {
     uint32_t* depth_key;      // forward out
     uint32_t* depth_val;      // forward out
     const float* g2d;         // backward in
+    uint32_t* nonfinite;      // forward out: count of Gaussians culled for non-finite input
+    float* pos_out;           // backward, optional: this view's positional statistic
+    float* col_out;           // backward, optional: this view's appearance statistic
+    uint8_t* vis_out;         // backward, optional: 1 where this view sees the Gaussian
 };
 struct PrepViews {
     int count;
@@ -124,6 +130,7 @@ struct PrepViews {
 };
 static_assert(sizeof(PrepViews) <= 3584, "preprocess view table too large for kernel arguments");
 
+// Zeroes every view's non-finite counter, then the per-Gaussian preprocess.
 hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s);
 // Gradients summed over the views; statistics summed over the views where the
 // Gaussian is visible, visible = number of such views.

@@ -253,6 +253,7 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
     const int nv = MULTI ? views.count : 1;
     for (int v = 0; v < nv; ++v) {
         const PrepView& pv = views.v[v];
+        if (!ok && pv.nonfinite) atomicAdd(pv.nonfinite, 1u);      // rare: diagnostics only
         float4 r[3];
         uint2 rect;
         const uint32_t nt = preprocess_one<DEG>(pv.cam, pv.grid, ok, m, s, q, op, sh, r, rect);
@@ -466,7 +467,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
         const PrepView& pv = views.v[v];
         const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
         const uint32_t flags = __float_as_uint(r2.w);
-        if (!(pv.touched[i] > 0 && !(flags & kCulled))) continue;
+        if (!(pv.touched[i] > 0 && !(flags & kCulled))) {
+            // this view's own statistics, when asked for: zero where unseen
+            if (pv.pos_out) pv.pos_out[i] = 0.0f;
+            if (pv.col_out) pv.col_out[i] = 0.0f;
+            if (pv.vis_out) pv.vis_out[i] = 0;
+            continue;
+        }
         float gr[kGrad2d];
         for (int k = 0; k < kGrad2d; ++k) gr[k] = pv.g2d[i * kGrad2d + k];
         float vm[3], vs[3], vq[4];
@@ -478,9 +485,14 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
         dop += gr[5];
         const float px = gr[0] * (0.5f * float(pv.cam.width));
         const float py = gr[1] * (0.5f * float(pv.cam.height));
-        pos += sqrtf(px * px + py * py);
-        col += sqrtf(gr[6] * gr[6] + gr[7] * gr[7] + gr[8] * gr[8]);
+        const float vpos = sqrtf(px * px + py * py);
+        const float vcol = sqrtf(gr[6] * gr[6] + gr[7] * gr[7] + gr[8] * gr[8]);
+        pos += vpos;
+        col += vcol;
         ++nvis;
+        if (pv.pos_out) pv.pos_out[i] = vpos;
+        if (pv.col_out) pv.col_out[i] = vcol;
+        if (pv.vis_out) pv.vis_out[i] = 1;
     }
     for (int k = 0; k < 3; ++k) out.means[k * n + i] = dm[k];
     for (int k = 0; k < 3; ++k) out.scales[k * n + i] = ds[k];
@@ -522,8 +534,17 @@ void launch_bwd(const tgs_gaussians& g, const PrepViews& views, const tgs_grads&
 
 }  // namespace
 
+// The views' non-finite counters to zero before the forward's atomics (one
+// small launch, so a captured step needs no memset node).
+__global__ void zero_nonfinite_kernel(PrepViews views) {
+    const int v = int(threadIdx.x);
+    if (v < views.count && views.v[v].nonfinite) *views.v[v].nonfinite = 0u;
+}
+
 hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s) {
-    if (g.n == 0 || views.count == 0) return hipSuccess;
+    if (views.count == 0) return hipSuccess;
+    zero_nonfinite_kernel<<<1, 64, 0, s>>>(views);
+    if (g.n == 0) return hipGetLastError();
     if (views.count == 1) launch_fwd<false>(g, views, s);
     else launch_fwd<true>(g, views, s);
     return hipGetLastError();
@@ -533,7 +554,10 @@ hipError_t launch_preprocess_bwd(const tgs_gaussians& g, const PrepViews& views,
                                  const tgs_grads& out, float* pos_stat, float* col_stat,
                                  uint8_t* visible, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    if (views.count == 1) launch_bwd<false>(g, views, out, pos_stat, col_stat, visible, s);
+    bool per_view = false;
+    for (int v = 0; v < views.count; ++v)
+        per_view = per_view || views.v[v].pos_out || views.v[v].col_out || views.v[v].vis_out;
+    if (views.count == 1 && !per_view) launch_bwd<false>(g, views, out, pos_stat, col_stat, visible, s);
     else launch_bwd<true>(g, views, out, pos_stat, col_stat, visible, s);
     return hipGetLastError();
 }

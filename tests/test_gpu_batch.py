@@ -40,7 +40,8 @@ def _setup(tile=16, lds_batch=0, specs=SPECS, seed=7, n=400, deg=3):
     say(f"[gpu] batch T={tile} lds={lds_batch} views={len(specs)} n={sc.n}")
     dev = api.DeviceScene.from_scene(sc)
     views = [(cams[k], d, ox, oy) for k, (_w, _h, d, ox, oy) in enumerate(specs)]
-    b = api.Batch(ctx(), sc.n, views, tile=tile, lds_batch=lds_batch, counts=True)
+    b = api.Batch(ctx(), sc.n, views, tile=tile, lds_batch=lds_batch, counts=True,
+                  view_stats=True)
     b.set_targets([torch.as_tensor(t).cuda() for t in targets])
     counts = b.fit_capacity(dev)
     grads = dev.zeros_like()
@@ -62,7 +63,9 @@ def _setup(tile=16, lds_batch=0, specs=SPECS, seed=7, n=400, deg=3):
                records=[v.records().cpu() for v in b.views],
                pair_vals=[v.pair_vals().cpu() for v in b.views],
                ranges=[v.ranges().cpu() for v in b.views],
-               grad2d=[v.grad2d().cpu() for v in b.views])
+               grad2d=[v.grad2d().cpu() for v in b.views],
+               view_pos=[t.cpu() for t in b.view_pos], view_col=[t.cpu() for t in b.view_col],
+               view_vis=[t.cpu() for t in b.view_vis])
     out["singles"] = [run_gpu(sc, cams[k], d, ox, oy, tile, target=targets[k])
                       for k, (_w, _h, d, ox, oy) in enumerate(specs)]
     _CACHE[key] = out
@@ -109,6 +112,21 @@ def test_batch_gradients_are_sums_of_single_views():
     grad_close(r["col"], sum(s["col_stat"].to(F64) for s in singles), name="col_stat")
     assert torch.equal(r["vis"].to(torch.int64), sum(s["visible"].to(torch.int64) for s in singles))
     assert int(r["vis"].max()) == len(singles)
+
+
+def test_batch_statistics_per_view_equal_single_views():
+    """Each view's own densification statistics from the batched backward
+    (Sec. 4.3's positional and appearance gradient norms and visibility)
+    equal the single-view call's; they also add up to the summed ones."""
+    r = _setup()
+    for k, s in enumerate(r["singles"]):
+        assert torch.equal(r["view_vis"][k], s["visible"]), k
+        grad_close(r["view_pos"][k], s["pos_stat"].to(F64), name=f"view {k} pos_stat")
+        grad_close(r["view_col"][k], s["col_stat"].to(F64), name=f"view {k} col_stat")
+    assert torch.equal(sum(t.to(torch.int64) for t in r["view_vis"]), r["vis"].to(torch.int64))
+    grad_close(r["pos"], sum(t.to(F64) for t in r["view_pos"]), name="pos_stat of the per-view sums")
+    grad_close(r["col"], sum(t.to(F64) for t in r["view_col"]), name="col_stat of the per-view sums")
+    say(f"[gpu] per-view statistics of {len(r['singles'])} views match the single-view calls")
 
 
 def test_batch_backward_against_oracle():

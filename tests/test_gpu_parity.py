@@ -434,6 +434,7 @@ def test_non_finite_gaussians_are_culled():
     g = run_gpu(sc, cam, target=tgt)
     rec = records_to_oracle(g["records"])
     assert bool(rec["culled"][[3, 7, 11]].all())
+    assert g["_view"].nonfinite_count() == 3
     assert bool(torch.isfinite(g["image"]).all())
     for k, v in g["grads"].items():
         assert bool(torch.isfinite(v).all()), k

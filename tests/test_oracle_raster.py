@@ -217,3 +217,70 @@ def test_merged_phases_close_to_full_render_reported():
     psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
     print(f"merged-phase PSNR vs full render: {psnr:.1f} dB")
     assert 0 < mse and psnr > 60.0
+
+
+@pytest.mark.parametrize("d,ox,oy,T", [(1, 0, 0, 16), (2, 1, 0, 8), (4, 3, 3, 8)])
+def test_unculled_sum_differs_only_where_an_excluded_splat_reaches_the_threshold(d, ox, oy, T):
+    """P9, the secondary reference: Eq. 2 summed over every Gaussian in depth
+    order (no tile culling, the same thresholds).  It equals the tile-list
+    render exactly at every pixel where no Gaussian left out of the pixel's
+    tile list reaches alpha >= 1/255 there; elsewhere the difference is the
+    tiling's disturbance (Sec. 4.1), reported as max |difference| and PSNR."""
+    sc, cam = scenes.small_scene(44, 60, 64, 48, sh_degree=1)
+    r = pre.preprocess(pre.params(sc), pre.camera(cam))
+    g = bn.grid(cam.width, cam.height, d, ox, oy, T)
+    b = bn.bin_gaussians(r["u"], r["v"], r["z"], r["radius"], r["culled"], g)
+    out = rs.raster_forward(r, b["vals"], b["ranges"], g)
+    alive = [k for k in range(sc.n) if not bool(r["culled"][k])]
+    order = sorted(alive, key=lambda k: (int(b["zbits"][k]), k))
+    rects = b["rects"].tolist()
+    sq, worst, touched = 0.0, 0.0, 0
+    for j in range(g.h_ds):
+        for i in range(g.w_ds):
+            X, Y = d * i + ox, d * j + oy
+            tx, ty = i // T, j // T
+            member = lambda k: rects[k][0] <= tx < rects[k][1] and rects[k][2] <= ty < rects[k][3]
+            col, _t, _l = rs.render_pixel_loop(r, order, lambda k: True, X, Y)
+            ref = out["image"][:, j, i].numpy()
+            diff = float(np.abs(np.asarray(col) - ref).max())
+            reach = False
+            for k in order:
+                if member(k):
+                    continue
+                dx, dy = float(r["u"][k]) - X, float(r["v"][k]) - Y
+                p = -0.5 * (float(r["A"][k]) * dx * dx + float(r["C"][k]) * dy * dy) \
+                    - float(r["B"][k]) * dx * dy
+                if p <= 0 and min(0.99, float(r["opacity"][k]) * math.exp(p)) >= 1.0 / 255.0:
+                    reach = True
+                    break
+            if not reach:
+                assert diff <= 1e-13, (i, j, diff)
+            else:
+                touched += 1
+            worst = max(worst, diff)
+            sq += float(((np.asarray(col) - ref) ** 2).sum())
+    mse = sq / (3 * g.w_ds * g.h_ds)
+    psnr = float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+    print(f"[oracle] un-culled Eq. 2 vs tile lists (d={d}): {touched} pixels reached by an "
+          f"excluded splat, max |diff| {worst:.3e}, PSNR {psnr:.1f} dB")
+    assert touched < g.w_ds * g.h_ds
+
+
+def test_unculled_sum_where_tiling_cuts_an_opaque_splat():
+    """P9 on a constructed case: an isotropic splat with o = 0.99 and
+    sigma = 5/3 px (so 3 sigma = 5 = its radius) centred at u = 10.9 has the
+    box [5.9, 15.9]: it is binned to tile 0 only (T = 16), yet at pixel
+    x = 16, 3.06 sigma away, its alpha 0.99 exp(-4.68) = 0.0092 >= 1/255.
+    The tile-list render leaves it out there, Eq. 2 over all splats does
+    not: the disturbance of Sec. 4.1, here 0.0092 * rgb at that pixel."""
+    sig2 = (5.0 / 3.0) ** 2
+    rec = _rec([10.9], [8.0], [1.0 / sig2], [0.0], [1.0 / sig2], [0.99], [[1.0, 0.5, 0.25]])
+    g = bn.grid(48, 16, 1, 0, 0, 16)
+    out, b = _render_records(rec, z=[2.0], radius=[5], g=g)
+    assert b["rects"].tolist() == [[0, 1, 0, 1]]
+    col, _t, _l = rs.render_pixel_loop(rec, [0], lambda k: True, 16.0, 8.0)
+    want = 0.99 * math.exp(-0.5 * (16.0 - 10.9) ** 2 / sig2)
+    assert want >= 1.0 / 255.0
+    np.testing.assert_allclose(col, [want * 1.0, want * 0.5, want * 0.25], rtol=1e-12)
+    assert float(out["image"][:, 8, 16].abs().max()) == 0.0
+    print(f"[oracle] tiling cuts an opaque splat: un-culled {col[0]:.4e} vs tile lists 0 at x = 16")
