@@ -4,12 +4,17 @@ cycling through the 4 phases), against the plain full-resolution path on the
 same view.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-plain]
-                    [--no-batched | --only-batched]
+                    [--no-batched | --only-batched] [--no-sweep | --only-sweep]
+                    [--no-autograd | --only-autograd]
 
 One step = preprocess -> pairs + sort + ranges -> dilated blend -> L1 loss
 gradient against the full-resolution target -> blend backward -> preprocess
 backward with densification statistics, on inputs already resident in HBM.
 Prints ONE JSON line (diagnostics go to stderr).
+
+Unless --no-sweep, it carries "sweep": per-stage ms, pair counts and
+workspace bytes of the same scene at 1080p, 1440p and 4K at strides 1, 2
+and 4 (the runtime breakdown and memory against resolution).
 
 Unless --no-autograd, it carries "autograd": a training step through the
 torch.autograd functions (1M Gaussians, 2560x1440, stride 2, fused Adam)
@@ -120,6 +125,10 @@ def parse():
     ap.add_argument("--only-autograd", action="store_true",
                     help="run only the autograd training step; prints its own JSON")
     ap.add_argument("--lds-batch", type=int, default=0)
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the resolution x stride sweep (per-stage ms and workspace bytes)")
+    ap.add_argument("--only-sweep", action="store_true",
+                    help="run only the resolution x stride sweep; prints its own JSON")
     return ap.parse_args()
 
 
@@ -308,6 +317,48 @@ def cpu_baseline(runner, seconds):
             "whole_step_small_scene": {"workload": scenes.WORKLOADS[0]["name"],
                                        "seconds": el0, "evals": ev0,
                                        "evals_per_s": ev0 / el0, "threads": torch.get_num_threads()}}
+
+
+SWEEP_RESOLUTIONS = ((1920, 1080), (2560, 1440), (3840, 2160))
+SWEEP_STRIDES = (1, 2, 4)
+
+
+def run_sweep(args, api, torch, np, dev=None, steps=5, warmup=2):
+    """Per-stage ms and memory against resolution and stride (the analogs of
+    the paper's runtime breakdown, Fig. 1, and memory curve, Fig. 9): the 3M
+    Gaussian scene of the benchmark seen from its camera angle at 1080p,
+    1440p and 4K, each at strides 1, 2 and 4 (phases cycling)."""
+    from paper_2412_13547_amd import scenes
+    w = scenes.WORKLOADS[2]
+    n = args.n or w["n"]
+    if dev is None:
+        dev = api.DeviceScene.from_scene(scenes.cluster_scene(2, n, w["sh_degree"]))
+    angle = scenes.ring_angle(2002)
+    rows = []
+    for (W, H) in SWEEP_RESOLUTIONS:
+        cam = scenes.ring_camera(W, H, angle)
+        target = torch.as_tensor(scenes.target_image(W, H, 1002)).cuda()
+        for d in SWEEP_STRIDES:
+            r = Runner(api, torch, dev, cam, target, d)
+            wall, per_step, stage = r.timed(steps, warmup)
+            v = r.view
+            pairs = r.view.pair_count()
+            sz = v.sizes
+            pix = int(sz.w_ds) * int(sz.h_ds)
+            cap = int(v.state.pair_capacity)
+            rows.append({"width": W, "height": H, "stride": d, "pixels": pix, "pairs": pairs,
+                         "ms_per_step": 1000.0 * wall / steps, "stages_ms": stage,
+                         "workspace_bytes": int(sz.workspace_bytes),
+                         "pair_list_bytes": 4 * pairs,
+                         "entry_bytes_capacity": 12 * cap,
+                         "per_pixel_state_bytes": 8 * pix})
+            log(f"# sweep {W}x{H} d={d}: {rows[-1]['ms_per_step']:.3f} ms, {pairs} pairs, "
+                f"workspace {int(sz.workspace_bytes) / 2**30:.2f} GiB")
+            del r, v
+            torch.cuda.empty_cache()
+        del target
+    return {"workload": f"{w['name']} views at 1080p/1440p/4K x stride 1/2/4", "gaussians": n,
+            "steps": steps, "warmup": warmup, "rows": rows}
 
 
 def _time_events(torch, fn, steps):
@@ -552,6 +603,9 @@ def main():
     if args.only_batched:
         print(json.dumps(run_batched(args, api, torch, np)), flush=True)
         return
+    if args.only_sweep:
+        print(json.dumps(run_sweep(args, api, torch, np)), flush=True)
+        return
     sc, cam, tgt = scenes.workload(args.workload, n=args.n)
     w = scenes.WORKLOADS[args.workload]
     stride = w.get("stride", 1)
@@ -627,8 +681,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dil, args.cpu_seconds)
+    del dil
+    torch.cuda.empty_cache()
+    if not args.no_sweep:
+        out["sweep"] = run_sweep(args, api, torch, np, dev=dev)
     if not args.no_batched:
-        del dil, dev, target
+        del dev, target
         torch.cuda.empty_cache()
         out["batched"] = run_batched(args, api, torch, np)
     if not args.no_autograd:

@@ -233,8 +233,12 @@ tgs_status tgs_query_sizes(int64_t n, const tgs_camera* cam, const tgs_dilation*
 
 /* Host only, no device needed.  The rasterizer launch a tile size gets when
  * tgs_options leaves lds_batch and pixels_per_thread at 0: the LDS batch and
- * pixels per thread written to *lds_batch and *pixels_per_thread.  Returns
- * TGS_ERR_INVALID_ARG for a tile other than 8, 16 or 32 or a NULL output. */
+ * pixels per thread written to *lds_batch and *pixels_per_thread, for a
+ * launch of many tiles.  A launch whose tiles (all its views') would leave
+ * SIMDs idle gets fewer pixels per thread: at T = 16, 2 below 6144 tiles and
+ * 1 below 3072; at T = 32, 2 below 1536.  Results do not depend on it.
+ * Returns TGS_ERR_INVALID_ARG for a tile other than 8, 16 or 32 or a NULL
+ * output. */
 tgs_status tgs_default_launch(int32_t tile, int32_t* lds_batch, int32_t* pixels_per_thread);
 
 /* Stage (a), Sec. 3 and Sec. 4.1: per Gaussian, view transform, near cull,

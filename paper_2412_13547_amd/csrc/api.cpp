@@ -243,6 +243,7 @@ tgs::RasterView raster_view(const tgs::Grid& grid, const tgs_options& opt, const
     v.ws_last = reinterpret_cast<uint32_t*>(ws + L.pix_last);
     v.bits = reinterpret_cast<unsigned long long*>(ws + L.blend_bits);
     v.bits_stride = tgs::blend_words(st.pair_capacity, grid.num_tiles());
+    v.fwd_split = reinterpret_cast<uint32_t*>(ws + L.fwd_split);
     return v;
 }
 
@@ -257,8 +258,9 @@ int lds_batch_of(const tgs_options& opt) {
     return opt.lds_batch ? opt.lds_batch : tgs::default_lds_batch(opt.tile);
 }
 
-int ppt_of(const tgs_options& opt) {
-    return opt.pixels_per_thread ? opt.pixels_per_thread : tgs::default_pixels_per_thread(opt.tile);
+int ppt_of(const tgs_options& opt, int64_t tiles) {
+    return opt.pixels_per_thread ? opt.pixels_per_thread
+                                 : tgs::default_pixels_per_thread(opt.tile, tiles);
 }
 
 // Depth sort and the pair counts per (tile row, chunk), up to the row starts
@@ -357,6 +359,7 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.pix_tfinal = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
     L.pix_last = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
     L.nonfinite = take(4);
+    L.fwd_split = take(4);
     L.blend_bits = take(uint64_t(max_tile_waves(grid.tile)) * blend_words(cap, grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
@@ -373,6 +376,14 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
 int default_lds_batch(int tile) { return tile == 8 ? 128 : tile == 16 ? 64 : 256; }
 
 int default_pixels_per_thread(int tile) { return tile == 8 ? 1 : 4; }
+
+int default_pixels_per_thread(int tile, int64_t tiles) {
+    if (tile == 8) return 1;
+    // wavefronts per tile at 4 pixels per thread: 1 (T = 16), 4 (T = 32)
+    const int64_t waves = tile == 16 ? tiles : 4 * tiles;
+    if (tile == 32) return waves >= 6144 ? 4 : 2;
+    return waves >= 6144 ? 4 : waves >= 3072 ? 2 : 1;
+}
 
 CamDev make_cam(const tgs_camera& c) {
     CamDev d{};
@@ -592,7 +603,7 @@ tgs_status tgs_raster_fwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     v.n_blend = n_blend;
     tgs::RasterViews t{};
     add_raster_view(t, v);
-    TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), t,
+    TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt, grid.num_tiles()), lds_batch_of(*opt), t,
                                    static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
@@ -673,7 +684,8 @@ tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
     TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(v.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
     tgs::RasterViews t{};
     add_raster_view(t, v);
-    TGS_HIP(tgs::launch_raster_bwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), t, strm));
+    TGS_HIP(tgs::launch_raster_bwd(opt->tile, ppt_of(*opt, grid.num_tiles()), lds_batch_of(*opt), t,
+                                   strm));
     return TGS_OK;
 }
 
@@ -884,7 +896,7 @@ tgs_status tgs_batch_raster_fwd(tgs_context* ctx, int64_t n, int32_t views, cons
         rv.n_tested = io[v].n_tested;
         add_raster_view(rt, rv);
     }
-    TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), rt,
+    TGS_HIP(tgs::launch_raster_fwd(opt->tile, ppt_of(*opt, rt.first_block[rt.count]), lds_batch_of(*opt), rt,
                                    static_cast<hipStream_t>(stream)));
     return TGS_OK;
 }
@@ -944,7 +956,8 @@ tgs_status tgs_batch_raster_bwd(tgs_context* ctx, int64_t n, int32_t views, cons
         TGS_HIP(tgs::fill_u32(reinterpret_cast<uint32_t*>(rv.g2d), 0u, uint64_t(n) * tgs::kGrad2d, strm));
         add_raster_view(rt, rv);
     }
-    TGS_HIP(tgs::launch_raster_bwd(opt->tile, ppt_of(*opt), lds_batch_of(*opt), rt, strm));
+    TGS_HIP(tgs::launch_raster_bwd(opt->tile, ppt_of(*opt, rt.first_block[rt.count]), lds_batch_of(*opt), rt,
+                                   strm));
     return TGS_OK;
 }
 

@@ -68,6 +68,7 @@ struct Layout {
     uint64_t pix_tfinal;       // float[h_ds][w_ds], transmittance after each pixel's walk
     uint64_t pix_last;         // uint32[h_ds][w_ds], 1-based index of each pixel's last
                                //   blended list entry (0: none)
+    uint64_t fwd_split;        // uint32: pixels per thread of the last forward
     uint64_t nonfinite;        // uint32: Gaussians the last preprocess culled for a
                                //   non-finite parameter (diagnostics)
     uint64_t blend_bits;       // uint64[max_tile_waves(T)][blend_words(capacity, tiles)]:
@@ -209,6 +210,8 @@ struct RasterView {
     unsigned long long* bits; // forward out / backward in: blend bits,
                               //   bits_stride words per wavefront slot
     uint64_t bits_stride;
+    uint32_t* fwd_split;      // forward out / backward in: the work split (pixels per
+                              //   thread) the bits were written with
 };
 struct RasterViews {
     int count;
@@ -222,6 +225,10 @@ static_assert(sizeof(RasterViews) <= 3584, "raster view table too large for kern
 // T = 32: 2, 4).  Results do not depend on either.
 int default_lds_batch(int tile);
 int default_pixels_per_thread(int tile);
+// The default work split of a launch over `tiles` tiles (all its views'):
+// fewer pixels per thread, hence more wavefronts per tile, when the tiles
+// alone would leave SIMDs idle (measured at 1080p-4K, strides 1-4).
+int default_pixels_per_thread(int tile, int64_t tiles);
 hipError_t launch_raster_fwd(int tile, int ppt, int lds_batch, const RasterViews& views,
                              hipStream_t s);
 hipError_t launch_raster_bwd(int tile, int ppt, int lds_batch, const RasterViews& views,

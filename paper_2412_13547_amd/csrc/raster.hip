@@ -371,8 +371,10 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
                         (base - start + uint32_t(c)) / 64u] = bm;
         }
     }
-    // the tile's weight for the backward's schedule
+    // the tile's weight for the backward's schedule; the work split the
+    // blend bits were written with (one workgroup of the view records it)
     if (rv.work && tid == 0) rv.work[tile] = min(base, end) - start;
+    if (tid == 0 && blockIdx.x == vt.first_block[v]) *rv.fwd_split = uint32_t(PPT);
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
 #pragma unroll
     for (int k = 0; k < S::NP; ++k) {
@@ -401,12 +403,15 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_fwd_kernel(RasterV
 // Calls entry(e), from the last to the first, for the entries e < cnt of an
 // LDS batch that some pixel of this wavefront blended in the forward: the
 // blend bits, one word per 64 entries from word `chunk` on (the batch
-// starts at a multiple of 64 entries of the tile's list).
+// starts at a multiple of 64 entries of the tile's list).  Without usable
+// bits (a forward with another work split has another wavefront
+// partition) every entry is visited; each pixel still decides its own.
 template <class F>
 __device__ __forceinline__ void for_blended_entries_reverse(const unsigned long long* bits,
-                                                            uint64_t chunk, int cnt, F&& entry) {
+                                                            bool use_bits, uint64_t chunk, int cnt,
+                                                            F&& entry) {
     for (int c = ((cnt - 1) >> 6) << 6; c >= 0; c -= 64) {
-        uint64_t m = bits[chunk + uint64_t(c >> 6)];
+        uint64_t m = use_bits ? uint64_t(bits[chunk + uint64_t(c >> 6)]) : ~uint64_t(0);
         if (cnt - c < 64) m &= (uint64_t(1) << (cnt - c)) - 1;
         while (m != 0) {
             const int hb = 63 - __builtin_clzll(m);
@@ -467,6 +472,9 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
     tile_range(rv, tile, start, end);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const unsigned long long* wbits = rv.bits + uint64_t(wave) * rv.bits_stride;
+    // the bits describe this launch's wavefronts only if the forward used the
+    // same work split
+    const bool use_bits = __builtin_amdgcn_readfirstlane(int(*rv.fwd_split)) == PPT;
     const uint64_t pix = uint64_t(grid.w_ds) * grid.h_ds;
     // per pixel: the transmittance behind the current entry (T_final at the
     // start), the gradient-weighted colour behind it (the background at the
@@ -604,8 +612,8 @@ __global__ void __launch_bounds__((Shape<T, PPT>::NT)) raster_bwd_kernel(RasterV
         };
         // entries at or past this wavefront's last blend change nothing
         const int wcnt = min(cnt, max(0, int(wend) - lo));
-        for_blended_entries_reverse(wbits, (start >> 6) + uint64_t(tile) + uint64_t(lo / 64), wcnt,
-                                    entry);
+        for_blended_entries_reverse(wbits, use_bits, (start >> 6) + uint64_t(tile) + uint64_t(lo / 64),
+                                    wcnt, entry);
         if constexpr (kBlockSum) {
             __syncthreads();
             for (int q = tid; q < cnt * kGrad2d; q += S::NT) {

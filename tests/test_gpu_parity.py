@@ -211,6 +211,26 @@ def test_backward_tile_order_leaves_gradients_unchanged(name):
     say(f"[gpu] {name}: image and gradients unchanged under arbitrary tile weights")
 
 
+@pytest.mark.parametrize("name", ["sh3-160x120-d2-o10-T16", "sh1-150x130-d4-o32-T32"])
+def test_backward_after_a_forward_with_another_work_split(name):
+    """The blend bits describe the forward's wavefronts; a backward launched
+    with another work split cannot use them and visits every entry, with the
+    same gradients up to the order of the float atomics."""
+    from paper_2412_13547_amd import api
+    sc, cam, tgt, ref = _case(name)
+    _, d, ox, oy, T, bg = CASES[name]
+    view = ref["_view"]
+    default = view.opt
+    for ppt in SPLITS[T]:
+        view.opt = api.options_struct(T, bg, 0, ppt)
+        view.raster_bwd(ref["dL"].cuda())
+        torch.cuda.synchronize()
+        grad_close(view.grad2d().cpu(), ref["grad2d"].to(F64), name=f"{name} backward P={ppt}",
+                   quiet=True)
+    view.opt = default
+    say(f"[gpu] {name}: backward with every work split after one forward: same gradients")
+
+
 @pytest.mark.parametrize("name", ["tiny128-d1-T16", "sh2-101x77-d3-o21-T8-bg",
                                   "sh1-150x130-d4-o32-T32", "sh0-333x200-d2-o11-T16"])
 def test_work_split_and_lds_batch_leave_results_unchanged(name):
