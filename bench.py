@@ -93,6 +93,13 @@ def raster_labels(tile=16):
     return (f"raster_fwd_kernel<{tile},{ppt},{lds},false>", f"raster_bwd_kernel<{tile},{ppt},{lds}>")
 
 
+def launch_ppt(tiles, tile=16):
+    """Pixels per thread of the library's default launch of `tiles` tiles of
+    16 x 16 (the rule tgs_default_launch documents)."""
+    assert tile == 16
+    return 4 if tiles >= 6144 else 2 if tiles >= 3072 else 1
+
+
 def fwd_ops(evals, tested, blended, pixels, wpix):
     return (OPS_BOUND / wpix * evals + OPS_EXAMINE * tested + OPS_HIT * (blended + pixels)
             + OPS_BLEND_FWD * blended)
@@ -209,6 +216,31 @@ class Runner:
         del b
         t.cuda.empty_cache()
         return res
+
+    def forward_orders(self, reps=4):
+        """Mean ms of raster_fwd with a cold tile order (tile_work zeroed, as on
+        a fresh workspace) and with the warm order the cold forward left (the
+        order every step after the first uses)."""
+        t = self.torch
+        v = self.view
+        img, _ = self._bufs()
+        cold, warm = [], []
+        for k in range(reps):
+            self._phase(k)
+            v.preprocess_fwd(self.dev)
+            v.bin_sort(self.dev)
+            v.tile_work().zero_()
+            ev = [t.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            v.raster_fwd(img)
+            ev[1].record()
+            ev[2].record()
+            v.raster_fwd(img)
+            ev[3].record()
+            t.cuda.synchronize()
+            cold.append(ev[0].elapsed_time(ev[1]))
+            warm.append(ev[2].elapsed_time(ev[3]))
+        return statistics.mean(cold), statistics.mean(warm)
 
     def timed(self, steps, warmup):
         t = self.torch
@@ -346,8 +378,19 @@ def run_sweep(args, api, torch, np, dev=None, steps=5, warmup=2):
             sz = v.sizes
             pix = int(sz.w_ds) * int(sz.h_ds)
             cap = int(v.state.pair_capacity)
+            # evaluation counts of phase 0 (stage times average the phases)
+            fe, be, bl, _, te = r.counts(0)
+            tiles = int(sz.num_tiles)
+            ppt = launch_ppt(tiles)
             rows.append({"width": W, "height": H, "stride": d, "pixels": pix, "pairs": pairs,
                          "ms_per_step": 1000.0 * wall / steps, "stages_ms": stage,
+                         "fwd_evals": fe, "bwd_evals": be, "blended": bl, "tested": te,
+                         "tiles": tiles, "pixels_per_thread": ppt,
+                         "raster_waves": tiles * 256 // (64 * ppt),
+                         "ps_per_fwd_eval": 1e9 * stage["raster_fwd"] / max(fe, 1),
+                         "ps_per_bwd_eval": 1e9 * stage["raster_bwd"] / max(be, 1),
+                         "fwd_frac": _alu(fwd_ops(fe, te, bl, pix, 64 * ppt), stage["raster_fwd"])["frac"],
+                         "bwd_frac": _alu(bwd_ops(bl), stage["raster_bwd"])["frac"],
                          "workspace_bytes": int(sz.workspace_bytes),
                          "pair_list_bytes": 4 * pairs,
                          "entry_bytes_capacity": 12 * cap,
@@ -623,6 +666,7 @@ def main():
     blended = float(np.mean([c[2] for c in cnt]))
     tested = float(np.mean([c[4] for c in cnt]))
     dil_pixels = int(dil.view.image_shape[1]) * int(dil.view.image_shape[2])
+    fwd_cold, fwd_warm = dil.forward_orders()
     pairs = float(np.mean([c[3] for c in cnt]))
     log(f"# dilated: {ms:.3f} ms/step, pairs {pairs:.0f}, stages {stage}")
 
@@ -674,6 +718,7 @@ def main():
         "pairs": pairs, "fwd_evals": fwd_evals, "bwd_evals": bwd_evals, "blended": blended,
         "tested": tested,
         "stages_ms": stage,
+        "raster_fwd_tile_order_ms": {"cold": fwd_cold, "warm": fwd_warm},
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms) if plain else None,
         "roofline": roof_bwd,

@@ -460,19 +460,21 @@ col_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* __restrict__ first_
 
 // Per slice: a lane per column, one wavefront per (group of 64 columns,
 // part of the slice's entries).  A wavefront walks its part's entries in
-// depth order; an entry covering the lane's column appends (Gaussian, output
-// slot) to the column's run in LDS, so every run is in depth order without
-// ranking.  Runs are laid out in column order (local slot of column c = the
-// slice's pairs in columns < c), the parts of a column one after the other:
-// a part's first slot in a column follows the earlier parts' pairs there,
+// depth order; an entry covering the lane's column appends the Gaussian to
+// the column's run in LDS, so every run is in depth order without ranking.
+// Runs are laid out in column order (local slot of column c = the slice's
+// pairs in columns < c), the parts of a column one after the other: a
+// part's first slot in a column follows the earlier parts' pairs there,
 // counted from difference arrays (+1 at an entry's first column, -1 after
 // its last) that the wavefronts fill before the walk.  For the walk, each
 // batch of 64 entries held in registers is compacted (ballot + lane prefix)
 // into a wavefront-private LDS list of the entries that touch the group;
 // the wavefront then reads the list back entry by entry with uniform
 // addresses (an LDS broadcast), so per covering entry the walk is a few
-// vector instructions and one LDS write by the covered lanes, with no
-// scalar work.  At the end each wavefront copies a share of its group's runs
+// vector instructions and one LDS write by the covered lanes.  A run's local
+// and output slots advance together (across the parts of a column too), so
+// beside each Gaussian the walk stores the column's constant (output slot -
+// local slot).  At the end each wavefront copies a share of its group's runs
 // out; a run's consecutive local slots go to consecutive output slots.
 //
 // The count of (slice b, column c) is base[b + 1][c] - base[b][c] for the
@@ -502,8 +504,9 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
     const int gx = grid.gx;
     const ScatterShape sh = scatter_shape(gx);
     const int waves = sh.groups * sh.parts;
-    uint2* s_pair = reinterpret_cast<uint2*>(smem);                // [kSlice] (Gaussian, output slot)
-    uint2* s_list = s_pair + kSlice;                               // [waves][kListLen] (Gaussian, lo | len << 16)
+    uint32_t* s_id = smem;                                         // [kSlice] Gaussian, then
+                                                                   // [kSlice] output - local slot
+    uint2* s_list = reinterpret_cast<uint2*>(smem + 2 * kSlice);   // [waves][kListLen] (Gaussian, lo | len << 16)
     int32_t* s_diff = reinterpret_cast<int32_t*>(s_list + kListLen * waves); // [waves][65]
     uint32_t* s_gtot = reinterpret_cast<uint32_t*>(s_diff + 65 * waves);  // [groups]
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = __lane_id();
@@ -558,9 +561,11 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
         hi = in && hi > cbeg ? hi - cbeg : 0u;
         if (hi < lo) hi = lo;
     };
-    // difference array of this wavefront's part over the group's columns
+    // difference array of this wavefront's part over the group's columns;
+    // when the part fits one load the spans are kept for the walk
     int32_t* diff = s_diff + 65 * w;
     constexpr uint32_t kBatch = 64u * kEntryBatch;
+    uint32_t span[kEntryBatch];
     for (uint32_t e = pe0; e < pe1; e += kBatch) {
         if (e != pe0) load(e);
 #pragma unroll
@@ -568,6 +573,7 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
             if (e + 64u * uint32_t(j) >= pe1) break;               // wave-uniform
             uint32_t lo, hi;
             cover(j, e, lo, hi);
+            span[j] = lo | (hi << 16);
             if (lo < hi) {
                 atomicAdd(&diff[lo], 1);
                 atomicAdd(&diff[hi], -1);
@@ -589,7 +595,8 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
     // the walk: the entries covering part of the group, in depth order,
     // compacted per batch into this wavefront's list and read back with
     // uniform addresses; padding entries (len 0) cover no column
-    uint2* pv = s_pair + slot;                                     // next slot of the column
+    uint32_t* pv = s_id + slot;                                    // next slot of the column
+    const uint32_t kofs = dst - slot;
     uint2* list = s_list + kListLen * w;
     const bool reload = pe1 - pe0 > kBatch;
     for (uint32_t e = pe0; e < pe1; e += kBatch) {
@@ -598,7 +605,12 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
         for (int j = 0; j < kEntryBatch; ++j) {
             if (e + 64u * uint32_t(j) >= pe1) break;               // wave-uniform
             uint32_t lo, hi;
-            cover(j, e, lo, hi);
+            if (reload) {
+                cover(j, e, lo, hi);
+            } else {
+                lo = span[j] & 0xFFFFu;
+                hi = span[j] >> 16;
+            }
             const bool has = lo < hi;
             const uint64_t m = __ballot(has);
             const uint32_t pos = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
@@ -614,8 +626,9 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
 #pragma unroll
                 for (int u = 0; u < kWalkUnroll; ++u) {
                     if (uint32_t(lane) - (v[u].y & 0xFFFFu) < (v[u].y >> 16)) {
-                        *pv++ = make_uint2(v[u].x, dst);
-                        ++dst;
+                        pv[0] = v[u].x;
+                        pv[kSlice] = kofs;
+                        ++pv;
                     }
                 }
             }
@@ -633,11 +646,13 @@ slice_scatter_kernel(const uint32_t* __restrict__ ent_id, const uint32_t* __rest
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t ii = i + 64u * uint32_t(q);
-            v[q] = ii < i1 ? s_pair[ii] : make_uint2(0u, capacity);
+            v[q] = ii < i1 ? make_uint2(s_id[ii], s_id[kSlice + ii]) : make_uint2(0u, capacity - ii);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (v[q].y < capacity) out[v[q].y] = v[q].x;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t o = i + 64u * uint32_t(q) + v[q].y;     // output slot
+            if (o < capacity) out[o] = v[q].x;
+        }
     }
 }
 
