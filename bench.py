@@ -5,16 +5,19 @@ same view.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-plain]
                     [--no-batched | --only-batched] [--no-sweep | --only-sweep]
-                    [--no-autograd | --only-autograd]
+                    [--no-autograd | --only-autograd] [--no-order-study]
 
 One step = preprocess -> pairs + sort + ranges -> dilated blend -> L1 loss
 gradient against the full-resolution target -> blend backward -> preprocess
 backward with densification statistics, on inputs already resident in HBM.
 Prints ONE JSON line (diagnostics go to stderr).
 
-Unless --no-sweep, it carries "sweep": per-stage ms, pair counts and
-workspace bytes of the same scene at 1080p, 1440p and 4K at strides 1, 2
-and 4 (the runtime breakdown and memory against resolution).
+Unless --no-sweep, it carries "sweep": per-stage ms, pair counts,
+evaluation counts, rasterizer VALU fractions and workspace bytes of the same
+scene at 1080p, 1440p and 4K at strides 1, 2 and 4 (the runtime breakdown
+and memory against resolution).  Unless --no-order-study, it carries
+"raster_fwd_tile_order_ms": the forward with a cold tile order (per-tile
+weights zeroed, as on a fresh workspace) and with the warm order.
 
 Unless --no-autograd, it carries "autograd": a training step through the
 torch.autograd functions (1M Gaussians, 2560x1440, stride 2, fused Adam)
@@ -136,6 +139,8 @@ def parse():
                     help="skip the resolution x stride sweep (per-stage ms and workspace bytes)")
     ap.add_argument("--only-sweep", action="store_true",
                     help="run only the resolution x stride sweep; prints its own JSON")
+    ap.add_argument("--no-order-study", action="store_true",
+                    help="skip the cold vs warm tile-order forward timing (for profiling)")
     return ap.parse_args()
 
 
@@ -666,7 +671,10 @@ def main():
     blended = float(np.mean([c[2] for c in cnt]))
     tested = float(np.mean([c[4] for c in cnt]))
     dil_pixels = int(dil.view.image_shape[1]) * int(dil.view.image_shape[2])
-    fwd_cold, fwd_warm = dil.forward_orders()
+    fwd_orders = None
+    if not args.no_order_study:
+        fwd_cold, fwd_warm = dil.forward_orders()
+        fwd_orders = {"cold": fwd_cold, "warm": fwd_warm}
     pairs = float(np.mean([c[3] for c in cnt]))
     log(f"# dilated: {ms:.3f} ms/step, pairs {pairs:.0f}, stages {stage}")
 
@@ -718,7 +726,7 @@ def main():
         "pairs": pairs, "fwd_evals": fwd_evals, "bwd_evals": bwd_evals, "blended": blended,
         "tested": tested,
         "stages_ms": stage,
-        "raster_fwd_tile_order_ms": {"cold": fwd_cold, "warm": fwd_warm},
+        "raster_fwd_tile_order_ms": fwd_orders,
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms) if plain else None,
         "roofline": roof_bwd,
