@@ -46,13 +46,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12                    # B/s, MI355X HBM3E
-# FP32 vector peak in lane operations, an FMA counted once: 256 CU x 4 SIMD x
-# 16 lanes x 2.4 GHz = 39.3 T/s (78.6 TFLOP/s), the rate of code without
-# packed FP32 instructions, which this build does not use.  The published
-# 157.3 TFLOP/s (78.65 T lane operations/s) counts packed FP32, two per lane
-# and cycle; fractions against it are reported beside.  Hardware counters
-# (profiles/) show the rasterizers issuing a VALU instruction every ~4
-# cycles per SIMD, the single-issue rate.
+# FP32 vector rate in lane operations, an FMA counted once: 256 CU x 4 SIMD x
+# 16 lanes x 2.4 GHz = 39.3 T/s (78.6 TFLOP/s), one wave64 instruction per
+# 4 cycles per SIMD without packed FP32 instructions, which this build does
+# not use.  The published 157.3 TFLOP/s (78.65 T lane operations/s) counts
+# packed FP32, two per lane and cycle, and is the bound; fractions against
+# it are reported beside.  Hardware counters (profiles/) show the
+# rasterizers issuing about one VALU instruction per 4 cycles per SIMD at
+# the 4K d = 2 view and one per 3.3 cycles at 4K d = 1, so the 4-cycle rate
+# is a reference, not a ceiling.
 PEAK_VALU = 256 * 4 * 16 * 2.4e9
 PEAK_VALU_PACKED = 157.3e12 / 2.0
 # The least FP32 arithmetic the method needs per list entry and pixel (lane
