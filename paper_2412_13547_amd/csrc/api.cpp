@@ -363,10 +363,8 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.blend_bits = take(uint64_t(max_tile_waves(grid.tile)) * blend_words(cap, grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);
     L.sort_counts = take(radix_counts_elems(un) * 4);
-    uint64_t most = radix_counts_elems(un);
-    if (table > most) most = table;
-    if (hist > most) most = hist;
-    L.scan_partials = take(scan_partials_elems(most) * 8);
+    // the row tables' device-wide scan (two arrays: 8 bytes per tile sum)
+    L.scan_partials = take(scan_partials_elems(table) * 8);
     L.total = o;
     return L;
 }

@@ -43,6 +43,7 @@ constexpr int kBinThreads = 256;                           // Gaussians per coun
 constexpr int kEntryBatch = 2;                             // 64-entry batches loaded at once
 constexpr int kScatterWaves = 8;                           // wavefronts per scatter block
 constexpr int kHistThreads = 256;
+constexpr int kHistLoads = 4;                              // 64-entry batches loaded at once
 constexpr int kColBatch = 16;                              // slices loaded together in col_scan
 
 // Orders this wavefront's LDS accesses: what its lanes wrote is visible to
@@ -60,14 +61,6 @@ __device__ __forceinline__ int wave_min(int x) {
 __device__ __forceinline__ int wave_max(int x) {
     for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
     return x;
-}
-
-// The packed tile rectangle (written by the preprocess, empty when culled or
-// off the grid) of the Gaussian at depth position s, gathered by id and kept
-// in depth order for the entry kernel; empty for s >= n.
-__device__ __forceinline__ uint2 gather_rect(const uint2* rects, const uint32_t* order, int64_t s,
-                                             int64_t n) {
-    return s < n ? rects[order[s]] : make_uint2(0u, 0u);
 }
 
 // Block-wide exclusive scan (blockDim.x = NT, one value per thread).
@@ -90,36 +83,57 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t* s_
 
 // Per block of kBinThreads depth positions and per row: entries and pairs.
 // ecnt[r * nblk + blk], pcnt[r * nblk + blk] (row-major, so one flat scan
-// gives the row starts and every block's offset inside every row).
-__global__ void __launch_bounds__(kBinThreads)
+// gives the row starts and every block's offset inside every row).  One
+// wavefront per block, each lane gathering kCountPer rectangles with all
+// their loads in flight (the gathers are the kernel's latency).
+constexpr int kCountThreads = 64;
+constexpr int kCountPer = kBinThreads / kCountThreads;
+
+__global__ void __launch_bounds__(kCountThreads)
 count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order, int64_t n,
              const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
              uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt, uint2* __restrict__ srect) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_w[kBinThreads / 64];
-    const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;    // Gaussians in the order
     const int gy = grid.gy;
+    const int lane = __lane_id();
     // difference arrays over the rows (+1 / +w at a Gaussian's first row,
     // -1 / -w after its last; modulo 2^32), then one prefix over the rows
     uint32_t* ce = lds;               // [gy + 1]
     uint32_t* cp = lds + (gy + 1);    // [gy + 1]
-    for (int r = threadIdx.x; r <= gy; r += kBinThreads) ce[r] = cp[r] = 0;
-    __syncthreads();
-    const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
-    const uint2 packed = gather_rect(rects, order, s, m);
-    if (s < n) srect[s] = packed;
-    const Rect rc = unpack_rect(packed);
-    const uint32_t w = uint32_t(rc.xhi - rc.xlo);
-    if (rc.ylo < rc.yhi) {
-        atomicAdd(&ce[rc.ylo], 1u);
-        atomicAdd(&cp[rc.ylo], w);
-        atomicSub(&ce[rc.yhi], 1u);
-        atomicSub(&cp[rc.yhi], w);
+    for (int r = lane; r <= gy; r += kCountThreads) ce[r] = cp[r] = 0;
+    // the ids first (the order holds n of them, m valid), then the rectangles
+    const int64_t s0 = int64_t(blockIdx.x) * kBinThreads + lane;
+    uint32_t id[kCountPer];
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int64_t s = s0 + int64_t(k) * kCountThreads;
+        id[k] = s < n ? order[s] : 0u;
     }
-    __syncthreads();
-    // thread t owns the consecutive rows [t * cpl, t * cpl + cpl)
-    const int cpl = (gy + kBinThreads - 1) / kBinThreads;
-    const int r0 = int(threadIdx.x) * cpl;
+    const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;     // Gaussians in the order
+    uint2 packed[kCountPer];
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int64_t s = s0 + int64_t(k) * kCountThreads;
+        packed[k] = s < m ? rects[id[k]] : make_uint2(0u, 0u);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int64_t s = s0 + int64_t(k) * kCountThreads;
+        if (s < n) srect[s] = packed[k];
+        const Rect rc = unpack_rect(packed[k]);
+        const uint32_t w = uint32_t(rc.xhi - rc.xlo);
+        if (rc.ylo < rc.yhi) {
+            atomicAdd(&ce[rc.ylo], 1u);
+            atomicAdd(&cp[rc.ylo], w);
+            atomicSub(&ce[rc.yhi], 1u);
+            atomicSub(&cp[rc.yhi], w);
+        }
+    }
+    wave_sync_lds();
+    // lane l owns the consecutive rows [l * cpl, l * cpl + cpl)
+    const int cpl = (gy + kCountThreads - 1) / kCountThreads;
+    const int r0 = lane * cpl;
     uint32_t se = 0, sp = 0;
     for (int j = 0; j < cpl; ++j) {
         if (r0 + j < gy) {
@@ -128,8 +142,8 @@ count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order
         }
     }
     uint32_t tot;
-    uint32_t re = block_exclusive_sum<kBinThreads>(se, s_w, tot);
-    uint32_t rp = block_exclusive_sum<kBinThreads>(sp, s_w, tot);
+    uint32_t re = wave_exclusive_sum(se, tot);
+    uint32_t rp = wave_exclusive_sum(sp, tot);
     for (int j = 0; j < cpl; ++j) {
         const int r = r0 + j;
         if (r < gy) {
@@ -224,9 +238,10 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int lane = __lane_id();
     const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
-    const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;
-    const uint32_t id = s < m ? order[s] : 0u;
+    const uint32_t oid = s < n ? order[s] : 0u;              // (loaded before m arrives)
     const uint2 packed = s < n ? srect[s] : make_uint2(0u, 0u);
+    const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;
+    const uint32_t id = s < m ? oid : 0u;
     const Rect rc = unpack_rect(packed);
     const uint32_t w = uint32_t(rc.xhi - rc.xlo);
     const uint32_t xpack = packed.x;
@@ -356,11 +371,23 @@ slice_hist_kernel(const uint32_t* __restrict__ ent_pp, const uint32_t* __restric
     int32_t* d = d_all[wv];
     for (int c = lane; c <= gx; c += 64) d[c] = 0;
     wave_sync_lds();
-    for (uint32_t e = s.e0 + uint32_t(lane); e < s.e1; e += 64) {
-        uint32_t c0, c1, p0;
-        if (clip_entry(ent_pp[e], ent_x[e], s.start, s.end, c0, c1, p0)) {
-            atomicAdd(&d[c0], 1);
-            atomicSub(&d[c1], 1);
+    // kHistLoads batches of 64 entries in flight at once
+    for (uint32_t e0 = s.e0; e0 < s.e1; e0 += 64u * kHistLoads) {
+        uint32_t pp[kHistLoads], xp[kHistLoads];
+#pragma unroll
+        for (int u = 0; u < kHistLoads; ++u) {
+            const uint32_t e = e0 + 64u * uint32_t(u) + uint32_t(lane);
+            pp[u] = e < s.e1 ? ent_pp[e] : 0u;
+            xp[u] = e < s.e1 ? ent_x[e] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kHistLoads; ++u) {
+            const uint32_t e = e0 + 64u * uint32_t(u) + uint32_t(lane);
+            uint32_t c0, c1, p0;
+            if (e < s.e1 && clip_entry(pp[u], xp[u], s.start, s.end, c0, c1, p0)) {
+                atomicAdd(&d[c0], 1);
+                atomicSub(&d[c1], 1);
+            }
         }
     }
     wave_sync_lds();
@@ -677,7 +704,7 @@ hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* ord
     const uint32_t nblk = bin_blocks(n);
     if (nblk > 0) {
         auto* w = const_cast<uint8_t*>(ws);
-        count_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy + 1) * 8, s>>>(
+        count_kernel<<<dim3(nblk), dim3(kCountThreads), size_t(grid.gy + 1) * 8, s>>>(
             reinterpret_cast<const uint2*>(ws + L.rects), order, n, dcount, grid, nblk,
             reinterpret_cast<uint32_t*>(w + L.ecnt), reinterpret_cast<uint32_t*>(w + L.pcnt),
             reinterpret_cast<uint2*>(w + L.srect));
