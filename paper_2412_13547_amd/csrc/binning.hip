@@ -5,20 +5,22 @@
 // pairs in any order but the final one:
 //   1. the Gaussians are sorted by their 32-bit depth key (stable, so equal
 //      depths keep ascending index; ``radix_sort``);
-//   2. count_kernel: per block of 256 consecutive Gaussians of that order and
+//   2. count_kernel: per block of 1024 consecutive Gaussians of that order and
 //      per tile row, the number of *entries* (Gaussian x row: a Gaussian
 //      covers the columns [xlo, xhi) of each row in [ylo, yhi)) and of pairs
 //      the block puts in the row; exclusive scans over (row, block) give every
 //      block's first entry and first pair in every row;
 //   3. entry_kernel: every block writes, row by row, its entries (Gaussian,
 //      first pair, columns) into the row's entry list -- in depth order --
-//      with one block-wide scan per row, and marks where every column-sort
-//      slice of kSlice pairs begins;
+//      with one wavefront scan per row a wavefront touches (four Gaussians
+//      per lane), and marks where every column-sort slice of kSlice pairs
+//      begins;
 //   4. slice_hist + col_scan + slice_scatter: a stable counting sort by column
 //      per slice.  The histogram comes from the slice's entries (two LDS
 //      updates per entry, then a prefix over the columns); the scatter
-//      expands the slice's entries into pairs in LDS, ranks them per column
-//      with wavefront ballots and writes each pair once, to its final place.
+//      expands the slice's entries into pairs in LDS, appending each entry
+//      to the runs of the columns it covers in depth order (no ranking),
+//      and writes each pair once, to its final place.
 //      Within a column the depth order of step 3 is kept, which is the
 //      (tile, depth, index) order.  col_scan also writes every tile's
 //      [start, end).
@@ -39,7 +41,9 @@
 namespace tgs {
 namespace {
 
-constexpr int kBinThreads = 256;                           // Gaussians per count/entry block
+constexpr int kBinThreads = 256;                           // threads per count/entry block
+constexpr int kBinPer = 4;                                 // Gaussians per thread
+constexpr int kBinGauss = kBinThreads * kBinPer;           // Gaussians per count/entry block
 constexpr int kEntryBatch = 2;                             // 64-entry batches loaded at once
 constexpr int kScatterWaves = 8;                           // wavefronts per scatter block
 constexpr int kHistThreads = 256;
@@ -81,45 +85,42 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t* s_
     return before + ex;
 }
 
-// Per block of kBinThreads depth positions and per row: entries and pairs.
+// Per block of kBinGauss depth positions and per row: entries and pairs.
 // ecnt[r * nblk + blk], pcnt[r * nblk + blk] (row-major, so one flat scan
-// gives the row starts and every block's offset inside every row).  One
-// wavefront per block, each lane gathering kCountPer rectangles with all
-// their loads in flight (the gathers are the kernel's latency).
-constexpr int kCountThreads = 64;
-constexpr int kCountPer = kBinThreads / kCountThreads;
-
-__global__ void __launch_bounds__(kCountThreads)
+// gives the row starts and every block's offset inside every row).  Each
+// thread gathers kBinPer rectangles with all their loads in flight.
+__global__ void __launch_bounds__(kBinThreads)
 count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order, int64_t n,
              const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
              uint32_t* __restrict__ ecnt, uint32_t* __restrict__ pcnt, uint2* __restrict__ srect) {
     extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_w[kBinThreads / 64];
     const int gy = grid.gy;
-    const int lane = __lane_id();
+    const int tid = threadIdx.x;
     // difference arrays over the rows (+1 / +w at a Gaussian's first row,
     // -1 / -w after its last; modulo 2^32), then one prefix over the rows
     uint32_t* ce = lds;               // [gy + 1]
     uint32_t* cp = lds + (gy + 1);    // [gy + 1]
-    for (int r = lane; r <= gy; r += kCountThreads) ce[r] = cp[r] = 0;
+    for (int r = tid; r <= gy; r += kBinThreads) ce[r] = cp[r] = 0;
     // the ids first (the order holds n of them, m valid), then the rectangles
-    const int64_t s0 = int64_t(blockIdx.x) * kBinThreads + lane;
-    uint32_t id[kCountPer];
+    const int64_t s0 = int64_t(blockIdx.x) * kBinGauss + tid;
+    uint32_t id[kBinPer];
 #pragma unroll
-    for (int k = 0; k < kCountPer; ++k) {
-        const int64_t s = s0 + int64_t(k) * kCountThreads;
+    for (int k = 0; k < kBinPer; ++k) {
+        const int64_t s = s0 + int64_t(k) * kBinThreads;
         id[k] = s < n ? order[s] : 0u;
     }
     const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;     // Gaussians in the order
-    uint2 packed[kCountPer];
+    uint2 packed[kBinPer];
 #pragma unroll
-    for (int k = 0; k < kCountPer; ++k) {
-        const int64_t s = s0 + int64_t(k) * kCountThreads;
+    for (int k = 0; k < kBinPer; ++k) {
+        const int64_t s = s0 + int64_t(k) * kBinThreads;
         packed[k] = s < m ? rects[id[k]] : make_uint2(0u, 0u);
     }
-    wave_sync_lds();
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kCountPer; ++k) {
-        const int64_t s = s0 + int64_t(k) * kCountThreads;
+    for (int k = 0; k < kBinPer; ++k) {
+        const int64_t s = s0 + int64_t(k) * kBinThreads;
         if (s < n) srect[s] = packed[k];
         const Rect rc = unpack_rect(packed[k]);
         const uint32_t w = uint32_t(rc.xhi - rc.xlo);
@@ -130,10 +131,10 @@ count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order
             atomicSub(&cp[rc.yhi], w);
         }
     }
-    wave_sync_lds();
-    // lane l owns the consecutive rows [l * cpl, l * cpl + cpl)
-    const int cpl = (gy + kCountThreads - 1) / kCountThreads;
-    const int r0 = lane * cpl;
+    __syncthreads();
+    // thread t owns the consecutive rows [t * cpl, t * cpl + cpl)
+    const int cpl = (gy + kBinThreads - 1) / kBinThreads;
+    const int r0 = tid * cpl;
     uint32_t se = 0, sp = 0;
     for (int j = 0; j < cpl; ++j) {
         if (r0 + j < gy) {
@@ -142,8 +143,8 @@ count_kernel(const uint2* __restrict__ rects, const uint32_t* __restrict__ order
         }
     }
     uint32_t tot;
-    uint32_t re = wave_exclusive_sum(se, tot);
-    uint32_t rp = wave_exclusive_sum(sp, tot);
+    uint32_t re = block_exclusive_sum<kBinThreads>(se, s_w, tot);
+    uint32_t rp = block_exclusive_sum<kBinThreads>(sp, s_w, tot);
     for (int j = 0; j < cpl; ++j) {
         const int r = r0 + j;
         if (r < gy) {
@@ -198,14 +199,19 @@ row_setup_kernel(const uint32_t* __restrict__ escan, const uint32_t* __restrict_
 // Every block writes its entries row by row: ent_id (Gaussian), ent_pp
 // (first pair of the entry), ent_x (xlo | xhi << 16).  A Gaussian's rank in
 // a row among the block's Gaussians counts entries and pairs at once
-// (packed: pairs << 12 | 1; a block holds 256 entries and at most
-// 256 * 1024 pairs of a row): per wavefront and row the packed totals come
-// from difference arrays over the rows and a prefix, a prefix over the
+// (packed: pairs << 11 | 1; a block holds at most 1024 entries and 1024 *
+// 1024 pairs of a row).  Lane l of wavefront w holds the kBinPer
+// consecutive depth positions 256 w + 4 l .. 256 w + 4 l + 3 of the block,
+// so a lane's sum followed by one wavefront scan ranks the wavefront's 256
+// Gaussians in a row.  Per wavefront and row the packed totals come from
+// difference arrays over the rows and a prefix, a prefix over the
 // wavefronts gives each wavefront's first rank in every row, and then each
-// wavefront walks its own rows with no barrier, ranking its lanes with one
-// wavefront scan per row.  The entry that holds the first pair of a
-// column-sort slice writes the slice's descriptor and closes the slice
-// before it.
+// wavefront walks its own rows with no barrier.  The entry that holds the
+// first pair of a column-sort slice writes the slice's descriptor and
+// closes the slice before it.
+constexpr uint32_t kRankShift = 11;                        // pairs << 11 | entries
+constexpr uint32_t kRankMask = (1u << kRankShift) - 1u;
+
 __global__ void __launch_bounds__(kBinThreads)
 entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order, int64_t n,
              const uint32_t* __restrict__ dcount, Grid grid, uint32_t nblk,
@@ -237,22 +243,34 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     for (int i = threadIdx.x; i < W * (gy + 1); i += kBinThreads) s_wr[i] = 0;
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int lane = __lane_id();
-    const int64_t s = int64_t(blockIdx.x) * kBinThreads + threadIdx.x;
-    const uint32_t oid = s < n ? order[s] : 0u;              // (loaded before m arrives)
-    const uint2 packed = s < n ? srect[s] : make_uint2(0u, 0u);
+    const int64_t s0 = int64_t(blockIdx.x) * kBinGauss + int64_t(threadIdx.x) * kBinPer;
+    uint32_t id[kBinPer], xpack[kBinPer], unit[kBinPer];
+    int ylo[kBinPer], yhi[kBinPer];
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        const int64_t s = s0 + k;
+        id[k] = s < n ? order[s] : 0u;                       // (loaded before m arrives)
+        const uint2 packed = s < n ? srect[s] : make_uint2(0u, 0u);
+        const Rect rc = unpack_rect(packed);
+        xpack[k] = packed.x;
+        ylo[k] = rc.ylo;
+        yhi[k] = rc.yhi;
+        unit[k] = (uint32_t(rc.xhi - rc.xlo) << kRankShift) | 1u;
+    }
     const int64_t m = dcount ? min(n, int64_t(*dcount)) : n;
-    const uint32_t id = s < m ? oid : 0u;
-    const Rect rc = unpack_rect(packed);
-    const uint32_t w = uint32_t(rc.xhi - rc.xlo);
-    const uint32_t xpack = packed.x;
-    const uint32_t unit = (w << 12) | 1u;
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k)
+        if (s0 + k >= m) id[k] = 0u;
     __syncthreads();
     // difference arrays of this wavefront's packed counts over the rows
-    // (modulo 2^32; a wavefront's count of a row stays below 4096)
+    // (modulo 2^32; a wavefront's count of a row stays below 2048)
     uint32_t* wr = s_wr + wv * (gy + 1);
-    if (rc.ylo < rc.yhi) {
-        atomicAdd(&wr[rc.ylo], unit);
-        atomicSub(&wr[rc.yhi], unit);
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        if (ylo[k] < yhi[k]) {
+            atomicAdd(&wr[ylo[k]], unit[k]);
+            atomicSub(&wr[yhi[k]], unit[k]);
+        }
     }
     wave_sync_lds();
     // prefix over the rows: lane l owns the rows [l * cpl, l * cpl + cpl)
@@ -284,35 +302,51 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     }
     __syncthreads();
     // this wavefront's rows
-    const int r0 = wave_min(rc.yhi > rc.ylo ? rc.ylo : gy), r1 = wave_max(rc.yhi);
+    int lo = gy, hi = 0;
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        if (ylo[k] < yhi[k]) {
+            lo = min(lo, ylo[k]);
+            hi = max(hi, yhi[k]);
+        }
+    }
+    const int r0 = wave_min(lo), r1 = wave_max(hi);
     for (int r = r0; r < r1; ++r) {
-        const bool in = r >= rc.ylo && r < rc.yhi;
-        const uint32_t x = in ? unit : 0u;
-        const uint32_t ex = wave_inclusive_sum(x) - x;
-        if (in) {
-            const uint32_t rank = wr[r] + ex;
-            const uint32_t e = s_e[r] + (rank & 0xFFFu);
-            const uint32_t p = s_p[r] + (rank >> 12);
-            ent_id[e] = id;
-            ent_pp[e] = p;
-            ent_x[e] = xpack;
-            // slices of the row that begin inside [p, p + w): their
-            // descriptors, and the end of the slice before each (entries
-            // overlapping a slice boundary belong to both slices; row_setup
-            // ends every row's last slice)
-            const uint32_t rs = s_rs[r];
-            const uint32_t rel = p - rs;
-            const uint32_t k0 = (rel + kSlice - 1) / kSlice, k1 = (rel + w - 1) / kSlice;
-            if (k0 <= k1) {
-                const uint32_t re = s_rs[r + 1];
-                const uint32_t fs = s_fs[r], ns = s_fs[r + 1] - fs;
-                for (uint32_t k = k0; k <= k1; ++k) {
-                    const uint32_t a = rs + k * kSlice;
-                    slice_desc[fs + k] = make_uint4(e, a, min(a + uint32_t(kSlice), re),
-                                                    uint32_t(r) | (k + 1 == ns ? 1u << 31 : 0u));
-                    if (k > 0) slice_e1[fs + k - 1] = e + 1;
+        uint32_t x[kBinPer], lsum = 0;
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            x[k] = (r >= ylo[k] && r < yhi[k]) ? unit[k] : 0u;
+            lsum += x[k];
+        }
+        uint32_t rank = wr[r] + wave_inclusive_sum(lsum) - lsum;
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            if (x[k] != 0u) {
+                const uint32_t e = s_e[r] + (rank & kRankMask);
+                const uint32_t p = s_p[r] + (rank >> kRankShift);
+                const uint32_t w = unit[k] >> kRankShift;
+                ent_id[e] = id[k];
+                ent_pp[e] = p;
+                ent_x[e] = xpack[k];
+                // slices of the row that begin inside [p, p + w): their
+                // descriptors, and the end of the slice before each (entries
+                // overlapping a slice boundary belong to both slices;
+                // row_setup ends every row's last slice)
+                const uint32_t rs = s_rs[r];
+                const uint32_t rel = p - rs;
+                const uint32_t k0 = (rel + kSlice - 1) / kSlice, k1 = (rel + w - 1) / kSlice;
+                if (k0 <= k1) {
+                    const uint32_t re = s_rs[r + 1];
+                    const uint32_t fs = s_fs[r], ns = s_fs[r + 1] - fs;
+                    for (uint32_t q = k0; q <= k1; ++q) {
+                        const uint32_t a = rs + q * kSlice;
+                        slice_desc[fs + q] = make_uint4(e, a, min(a + uint32_t(kSlice), re),
+                                                        uint32_t(r) | (q + 1 == ns ? 1u << 31 : 0u));
+                        if (q > 0) slice_e1[fs + q - 1] = e + 1;
+                    }
                 }
             }
+            rank += x[k];
         }
     }
 }
@@ -695,7 +729,7 @@ size_t entry_lds_bytes(int gy) { return size_t(gy + 1) * 4 * (4 + kBinThreads / 
 
 }  // namespace
 
-uint32_t bin_blocks(int64_t n) { return uint32_t((n + kBinThreads - 1) / kBinThreads); }
+uint32_t bin_blocks(int64_t n) { return uint32_t((n + kBinGauss - 1) / kBinGauss); }
 
 uint64_t bin_max_slices(uint64_t pairs, int gy) { return pairs / kSlice + uint64_t(gy) + 1; }
 
@@ -704,7 +738,7 @@ hipError_t launch_counts(const uint8_t* ws, const Layout& L, const uint32_t* ord
     const uint32_t nblk = bin_blocks(n);
     if (nblk > 0) {
         auto* w = const_cast<uint8_t*>(ws);
-        count_kernel<<<dim3(nblk), dim3(kCountThreads), size_t(grid.gy + 1) * 8, s>>>(
+        count_kernel<<<dim3(nblk), dim3(kBinThreads), size_t(grid.gy + 1) * 8, s>>>(
             reinterpret_cast<const uint2*>(ws + L.rects), order, n, dcount, grid, nblk,
             reinterpret_cast<uint32_t*>(w + L.ecnt), reinterpret_cast<uint32_t*>(w + L.pcnt),
             reinterpret_cast<uint2*>(w + L.srect));
