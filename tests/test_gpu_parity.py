@@ -159,6 +159,45 @@ def test_depth_order_ties_and_culled():
     say(f"[gpu] depth order with {len(tied)} exact ties and 60 culled or off-screen: bit-exact")
 
 
+def test_depth_order_across_sort_tiles():
+    """40,000 Gaussians: ten tiles of the depth sort, whose later tiles take
+    their offsets from the earlier ones' published counts.  10,000 exact
+    depth ties between Gaussians 20,000 indices apart (so in different
+    tiles) keep id order, 4,000 culled or off-screen Gaussians interleaved
+    with the rest are left out; the depth order and the pair lists are
+    bit-exact."""
+    n = 40_000
+    sc, cam = scenes.small_scene(11, n, 320, 240, sh_degree=0)
+    sc = sc.copy()
+    sc.means[:, 20000:30000] = sc.means[:, 0:10000]      # exact depth ties across tiles
+    sc.scales[:, 20000:30000] = sc.scales[:, 0:10000]
+    sc.quats[:, 20000:30000] = sc.quats[:, 0:10000]
+    r = cam.w2c[:, :3].astype(np.float64)
+    t = cam.w2c[:, 3].astype(np.float64)
+    behind = (r.T @ (np.array([[0.0], [0.0], [-1.0]]) - t[:, None])).astype(np.float32)
+    off = (r.T @ (np.array([[50.0], [0.0], [3.0]]) - t[:, None])).astype(np.float32)
+    sc.means[:, 5:n:20] = behind                         # every 20th: culled
+    sc.means[:, 15:n:40] = off                           # every 40th: no tiles
+    g = run_gpu(sc, cam, 1, 0, 0, 16, target=scenes.target_image(320, 240, 11), backward=False)
+    rec = records_to_oracle(g["records"])
+    b = obn.bin_gaussians(rec["u"], rec["v"], rec["z"], rec["radius"], rec["culled"], g["grid"])
+    got = g["_view"].depth_order().cpu().to(torch.int64).numpy()
+    want = _expected_depth_order(b)
+    assert got.size > 4096 * 5
+    assert np.array_equal(got, want)
+    zb = b["zbits"].numpy()
+    kept = set(got.tolist())
+    tied = [k for k in range(10000) if zb[k] == zb[20000 + k] and k in kept and 20000 + k in kept]
+    assert len(tied) > 1000
+    pos = {int(v): i for i, v in enumerate(got)}
+    assert all(pos[k] < pos[20000 + k] for k in tied)
+    assert g["pair_count"] == b["keys"].numel()
+    assert torch.equal(g["pair_vals"].to(torch.int64), b["vals"])
+    assert torch.equal(g["ranges"].to(torch.int64), b["ranges"])
+    say(f"[gpu] depth order over {got.size} Gaussians ({(got.size + 4095) // 4096} sort tiles), "
+        f"{len(tied)} ties across tiles: bit-exact; {g['pair_count']} pairs bit-exact")
+
+
 SPLITS = {8: (1,), 16: (1, 2, 4), 32: (2, 4)}
 
 
