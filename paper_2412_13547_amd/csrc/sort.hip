@@ -89,7 +89,7 @@ sort_hist(const uint32_t* __restrict__ keys, uint64_t count, int passes, bool dr
     uint32_t* mine = hist[(tid >> 6) & (kCopies - 1)];
     for (uint32_t i = tid; i < kCopies * kMaxPasses * kRadixBuckets; i += blockDim.x)
         (&hist[0][0])[i] = 0u;
-    // the look-back states start empty, the tickets at 0
+    // the look-back states start empty (the totals and tickets were filled)
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + tid; i < state_words;
          i += uint64_t(gridDim.x) * blockDim.x)
         area.states[i] = 0u;
