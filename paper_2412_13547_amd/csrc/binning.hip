@@ -231,6 +231,7 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
     uint32_t* s_rs = s_row + 2 * (gy + 1);
     uint32_t* s_fs = s_row + 3 * (gy + 1);
     uint32_t* s_wr = s_row + 4 * (gy + 1);                  // [W][gy + 1]
+    __shared__ uint32_t s_stage[W][3][kBinThreads];         // a row's entries per wavefront
     if (row_start[gy] > capacity) return;               // overflow: block-uniform
     for (int r = threadIdx.x; r <= gy; r += kBinThreads) {
         if (r < gy) {
@@ -311,6 +312,12 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
         }
     }
     const int r0 = wave_min(lo), r1 = wave_max(hi);
+    // per row: the wavefront's entries of the row are consecutive in the
+    // row's list; they are staged in LDS by their index among them and
+    // written with full-wavefront stores
+    uint32_t* st_id = s_stage[wv][0];
+    uint32_t* st_pp = s_stage[wv][1];
+    uint32_t* st_x = s_stage[wv][2];
     for (int r = r0; r < r1; ++r) {
         uint32_t x[kBinPer], lsum = 0;
 #pragma unroll
@@ -318,36 +325,49 @@ entry_kernel(const uint2* __restrict__ srect, const uint32_t* __restrict__ order
             x[k] = (r >= ylo[k] && r < yhi[k]) ? unit[k] : 0u;
             lsum += x[k];
         }
-        uint32_t rank = wr[r] + wave_inclusive_sum(lsum) - lsum;
+        const uint32_t incl = wave_inclusive_sum(lsum);
+        const uint32_t first = wr[r];                        // the wavefront's first rank
+        const uint32_t cnt = uint32_t(__builtin_amdgcn_readlane(int(incl), 63)) & kRankMask;
+        const uint32_t pbase = s_p[r];
+        uint32_t rank = first + incl - lsum;
 #pragma unroll
         for (int k = 0; k < kBinPer; ++k) {
             if (x[k] != 0u) {
-                const uint32_t e = s_e[r] + (rank & kRankMask);
-                const uint32_t p = s_p[r] + (rank >> kRankShift);
-                const uint32_t w = unit[k] >> kRankShift;
-                ent_id[e] = id[k];
-                ent_pp[e] = p;
-                ent_x[e] = xpack[k];
-                // slices of the row that begin inside [p, p + w): their
-                // descriptors, and the end of the slice before each (entries
-                // overlapping a slice boundary belong to both slices;
-                // row_setup ends every row's last slice)
-                const uint32_t rs = s_rs[r];
-                const uint32_t rel = p - rs;
-                const uint32_t k0 = (rel + kSlice - 1) / kSlice, k1 = (rel + w - 1) / kSlice;
-                if (k0 <= k1) {
-                    const uint32_t re = s_rs[r + 1];
-                    const uint32_t fs = s_fs[r], ns = s_fs[r + 1] - fs;
-                    for (uint32_t q = k0; q <= k1; ++q) {
-                        const uint32_t a = rs + q * kSlice;
-                        slice_desc[fs + q] = make_uint4(e, a, min(a + uint32_t(kSlice), re),
-                                                        uint32_t(r) | (q + 1 == ns ? 1u << 31 : 0u));
-                        if (q > 0) slice_e1[fs + q - 1] = e + 1;
-                    }
-                }
+                const uint32_t i = (rank & kRankMask) - (first & kRankMask);
+                st_id[i] = id[k];
+                st_pp[i] = pbase + (rank >> kRankShift);
+                st_x[i] = xpack[k];
             }
             rank += x[k];
         }
+        wave_sync_lds();
+        const uint32_t e0 = s_e[r] + (first & kRankMask);
+        const uint32_t rs = s_rs[r];
+        for (uint32_t i = uint32_t(lane); i < cnt; i += 64u) {
+            const uint32_t e = e0 + i;
+            const uint32_t p = st_pp[i], xp = st_x[i];
+            ent_id[e] = st_id[i];
+            ent_pp[e] = p;
+            ent_x[e] = xp;
+            // slices of the row that begin inside [p, p + w): their
+            // descriptors, and the end of the slice before each (entries
+            // overlapping a slice boundary belong to both slices; row_setup
+            // ends every row's last slice)
+            const uint32_t w = (xp >> 16) - (xp & 0xFFFFu);
+            const uint32_t rel = p - rs;
+            const uint32_t k0 = (rel + kSlice - 1) / kSlice, k1 = (rel + w - 1) / kSlice;
+            if (k0 <= k1) {
+                const uint32_t re = s_rs[r + 1];
+                const uint32_t fs = s_fs[r], ns = s_fs[r + 1] - fs;
+                for (uint32_t q = k0; q <= k1; ++q) {
+                    const uint32_t a = rs + q * kSlice;
+                    slice_desc[fs + q] = make_uint4(e, a, min(a + uint32_t(kSlice), re),
+                                                    uint32_t(r) | (q + 1 == ns ? 1u << 31 : 0u));
+                    if (q > 0) slice_e1[fs + q - 1] = e + 1;
+                }
+            }
+        }
+        wave_sync_lds();                                     // stage read before the next row
     }
 }
 
