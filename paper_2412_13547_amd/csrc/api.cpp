@@ -337,6 +337,7 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     const uint64_t hist = gx * slices;
     L.records = take(un * kRecordBytes);
     L.tiles_touched = take(un * 4);
+    L.jac = take(un * kJacWords * 4);     // directly after the tile counts (jac_rows)
     L.rects = take(un * 8);
     L.srect = take(un * 8);
     for (int b = 0; b < 2; ++b) L.depth_key[b] = take(un * 4);
@@ -358,7 +359,7 @@ Layout make_layout(int64_t n, uint64_t cap, const Grid& grid) {
     L.tile_order = take(uint64_t(grid.num_tiles()) * 4);
     L.pix_tfinal = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
     L.pix_last = take(uint64_t(grid.w_ds) * uint64_t(grid.h_ds) * 4);
-    L.nonfinite = take(4);
+    L.nonfinite = take(8);                // the counter, then whether jac is current
     L.fwd_split = take(4);
     L.blend_bits = take(uint64_t(max_tile_waves(grid.tile)) * blend_words(cap, grid.num_tiles()) * 8);
     L.grad2d = take(un * kGrad2d * 4);

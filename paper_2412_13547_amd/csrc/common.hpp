@@ -30,8 +30,10 @@ constexpr int kSlice = 4096;
 constexpr int kMaxCols = 1024;
 
 enum RecordFlags : uint32_t {
-    kClampR = 1u, kClampG = 2u, kClampB = 4u, kCulled = 8u, kFovX = 16u, kFovY = 32u
+    kClampR = 1u, kClampG = 2u, kClampB = 4u, kCulled = 8u, kFovX = 16u, kFovY = 32u,
+    kHasTiles = 64u           // only in the backward's flags word (Layout::jac)
 };
+constexpr int kJacWords = 10;   // Layout::jac: d rgb / d dir (3 x 3), then the flags word
 
 struct Grid {
     int width, height;        // full resolution
@@ -71,6 +73,11 @@ struct Layout {
     uint64_t fwd_split;        // uint32: pixels per thread of the last forward
     uint64_t nonfinite;        // uint32: Gaussians the last preprocess culled for a
                                //   non-finite parameter (diagnostics)
+    uint64_t jac;              // float[kJacWords][n], written by a one-view preprocess:
+                               //   d rgb_c / d dir_a at row 3c + a (SH degree >= 1), then
+                               //   the record's flags | kHasTiles as a word; it follows
+                               //   tiles_touched directly (jac_rows), and the word after
+                               //   nonfinite is 1 when the last preprocess wrote it
     uint64_t blend_bits;       // uint64[max_tile_waves(T)][blend_words(capacity, tiles)]:
                                //   per wavefront slot of a tile and per 64 list entries
                                //   of the tile, the entries some pixel of that wavefront
@@ -125,6 +132,14 @@ struct PrepView {
     float* col_out;           // backward, optional: this view's appearance statistic
     uint8_t* vis_out;         // backward, optional: 1 where this view sees the Gaussian
 };
+
+// Layout::jac of a view of n Gaussians (it follows the tile counts, whose
+// size rounds up to the 256-byte alignment of the workspace's arrays), and
+// the word beside the non-finite counter that says whether it is current.
+__host__ __device__ inline float* jac_rows(const PrepView& v, int64_t n) {
+    return reinterpret_cast<float*>(v.touched + ((n + 63) / 64) * 64);
+}
+__host__ __device__ inline uint32_t* jac_current(const PrepView& v) { return v.nonfinite + 1; }
 struct PrepViews {
     int count;
     PrepView v[kMaxViews];

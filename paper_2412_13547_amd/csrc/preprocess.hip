@@ -181,12 +181,14 @@ __device__ __forceinline__ bool finite_all(const float* x, int k) {
 }
 
 // The record of one Gaussian in one view and its packed tile rectangle
-// (empty when culled or off the grid); returns the tiles it overlaps.
-template <int DEG>
+// (empty when culled or off the grid); returns the tiles it overlaps.  With
+// JAC, jac receives d(sum_k sh_k,c Y_k)/d dir_a at 3c + a (zero when culled),
+// the only use the backward makes of the SH coefficients besides the basis.
+template <int DEG, bool JAC>
 __device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid& grid, bool ok,
                                                    const float m[3], const float s[3],
                                                    const float q[4], float op, const float* sh,
-                                                   float4 out[3], uint2& rect) {
+                                                   float4 out[3], uint2& rect, float jac[9]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     Proj p;
     ok = ok && project(cam, m, s, q, p);
@@ -203,6 +205,8 @@ __device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid
         ok = radius > 0;
     }
     rect = make_uint2(0u, 0u);
+    if constexpr (JAC)
+        for (int k = 0; k < 9; ++k) jac[k] = 0.0f;
     if (!ok) {
         out[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -224,6 +228,13 @@ __device__ __forceinline__ uint32_t preprocess_one(const CamDev& cam, const Grid
         acc += 0.5f;
         if (acc < 0.0f) flags |= (1u << c);
         rgb[c] = fmaxf(acc, 0.0f);
+    }
+    if constexpr (JAC && DEG >= 1) {
+        for (int c = 0; c < 3; ++c) {
+            float w[K];
+            for (int k = 0; k < K; ++k) w[k] = sh[k * 3 + c];
+            sh_basis_grad<DEG>(dx, dy, dz, w, jac[3 * c], jac[3 * c + 1], jac[3 * c + 2]);
+        }
     }
     out[0] = make_float4(p.u, p.v, A, B);
     out[1] = make_float4(C, op, rgb[0], rgb[1]);
@@ -256,11 +267,21 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
         if (!ok && pv.nonfinite) atomicAdd(pv.nonfinite, 1u);      // rare: diagnostics only
         float4 r[3];
         uint2 rect;
-        const uint32_t nt = preprocess_one<DEG>(pv.cam, pv.grid, ok, m, s, q, op, sh, r, rect);
+        float jac[9];
+        const uint32_t nt = preprocess_one<DEG, !MULTI>(pv.cam, pv.grid, ok, m, s, q, op, sh, r,
+                                                        rect, jac);
         float4* dst = reinterpret_cast<float4*>(pv.rec + i);
         dst[0] = r[0];
         dst[1] = r[1];
         dst[2] = r[2];
+        if constexpr (!MULTI) {
+            // what the one-view backward reads instead of the SH coefficients,
+            // the record and the tile count
+            float* jr = jac_rows(pv, n);
+            if constexpr (DEG >= 1)
+                for (int k = 0; k < 9; ++k) jr[k * n + i] = jac[k];
+            jr[9 * n + i] = __uint_as_float(__float_as_uint(r[2].w) | (nt > 0 ? kHasTiles : 0u));
+        }
         pv.touched[i] = nt;
         pv.rects[i] = rect;
         pv.depth_key[i] = nt > 0 ? __float_as_uint(r[2].y) : 0xFFFFFFFFu;
@@ -269,14 +290,17 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
 }
 
 // Parameter gradients of Gaussian i in one view, written to (dm, ds, dq);
-// gr = dL/d(u, v, A, B, C, o, r, g, b).  The SH coefficients are read from
-// sh_g ([K*3][n]); their gradients are added to dsh_acc (ACC) or written to
-// dsh_g (single view, zero where !vis: every lane stores, so each store of
-// the wavefront covers whole cache lines).
+// gr = dL/d(u, v, A, B, C, o, r, g, b).  The colour's gradient in the view
+// direction comes from the forward's Jacobian rows jac ([9][n]) when given,
+// else from the SH coefficients sh_g ([K*3][n]); the coefficients'
+// gradients are added to dsh_acc (ACC) or written to dsh_g (single view,
+// zero where !vis: every lane stores, so each store of the wavefront covers
+// whole cache lines).
 template <int DEG, bool ACC>
 __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const float m[3],
                                                     const float s[3], const float q[4],
-                                                    const float* sh_g, float* dsh_g, int64_t n,
+                                                    const float* sh_g, const float* jac,
+                                                    float* dsh_g, int64_t n,
                                                     int64_t i, uint32_t flags,
                                                     const float gr[kGrad2d], float dm_out[3],
                                                     float ds_out[3], float dq_out[4],
@@ -297,20 +321,38 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
         sh_basis<DEG>(dx, dy, dz, Y);
         float graw[3];
         for (int c = 0; c < 3; ++c) graw[c] = (flags & (1u << c)) ? 0.0f : gr[6 + c];
-        float w[16];
-        for (int k = 0; k < K; ++k) {
-            float acc = 0.0f;
-            for (int c = 0; c < 3; ++c) {
-                const float d = Y[k] * graw[c];
-                if constexpr (ACC) dsh_acc[k * 3 + c] += d;
-                else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
-                // a Gaussian the view does not see skips the read (result unused)
-                acc += (vis ? sh_g[(k * 3 + c) * n + i] : 0.0f) * graw[c];
+        float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+        if (jac) {
+            for (int k = 0; k < K; ++k) {
+                for (int c = 0; c < 3; ++c) {
+                    const float d = Y[k] * graw[c];
+                    if constexpr (ACC) dsh_acc[k * 3 + c] += d;
+                    else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
+                }
             }
-            w[k] = acc;
+            if constexpr (DEG >= 1) {
+                // a Gaussian the view does not see skips the reads (result unused)
+                for (int c = 0; c < 3; ++c) {
+                    gdx += (vis ? jac[(3 * c) * n + i] : 0.0f) * graw[c];
+                    gdy += (vis ? jac[(3 * c + 1) * n + i] : 0.0f) * graw[c];
+                    gdz += (vis ? jac[(3 * c + 2) * n + i] : 0.0f) * graw[c];
+                }
+            }
+        } else {
+            float w[16];
+            for (int k = 0; k < K; ++k) {
+                float acc = 0.0f;
+                for (int c = 0; c < 3; ++c) {
+                    const float d = Y[k] * graw[c];
+                    if constexpr (ACC) dsh_acc[k * 3 + c] += d;
+                    else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
+                    // a Gaussian the view does not see skips the read (result unused)
+                    acc += (vis ? sh_g[(k * 3 + c) * n + i] : 0.0f) * graw[c];
+                }
+                w[k] = acc;
+            }
+            sh_basis_grad<DEG>(dx, dy, dz, w, gdx, gdy, gdz);
         }
-        float gdx, gdy, gdz;
-        sh_basis_grad<DEG>(dx, dy, dz, w, gdx, gdy, gdz);
         // through the normalisation of dir
         const float dot = gdx * dx + gdy * dy + gdz * dz;
         dm[0] += (gdx - dx * dot) / len;
@@ -414,9 +456,20 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int kc = g.sh_coeffs;
     const PrepView& pv = views.v[0];
-    const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
-    const uint32_t flags = __float_as_uint(r2.w);
-    const bool vis = pv.touched[i] > 0 && !(flags & kCulled);
+    // after a one-view forward its flags word and Jacobian rows replace the
+    // record, the tile count and the SH coefficients
+    const bool use_jac = pv.nonfinite && *jac_current(pv) != 0u;
+    const float* jr = jac_rows(pv, n);
+    uint32_t flags;
+    bool vis;
+    if (use_jac) {
+        flags = __float_as_uint(jr[9 * n + i]);
+        vis = (flags & kHasTiles) && !(flags & kCulled);
+    } else {
+        const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
+        flags = __float_as_uint(r2.w);
+        vis = pv.touched[i] > 0 && !(flags & kCulled);
+    }
     float gr[kGrad2d];
     for (int k = 0; k < kGrad2d; ++k) gr[k] = vis ? pv.g2d[i * kGrad2d + k] : 0.0f;
     // parameters only of Gaussians the view sees: the others' gradients and
@@ -426,8 +479,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     for (int k = 0; k < 3; ++k) s[k] = vis ? g.scales[k * n + i] : 1.0f;
     for (int k = 0; k < 4; ++k) q[k] = vis ? g.quats[k * n + i] : 1.0f;
     float dm[3], ds[3], dq[4];
-    preprocess_grad_one<DEG, false>(pv.cam, m, s, q, g.sh, out.sh, n, i, flags, gr, dm, ds, dq,
-                                    nullptr, vis);
+    preprocess_grad_one<DEG, false>(pv.cam, m, s, q, g.sh, use_jac ? jr : nullptr, out.sh, n,
+                                    i, flags, gr, dm, ds, dq, nullptr, vis);
     for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
     for (int k = 0; k < 4; ++k) out.quats[k * n + i] = vis ? dq[k] : 0.0f;
     for (int k = 0; k < 3; ++k) out.scales[k * n + i] = vis ? ds[k] : 0.0f;
@@ -477,8 +530,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
         float gr[kGrad2d];
         for (int k = 0; k < kGrad2d; ++k) gr[k] = pv.g2d[i * kGrad2d + k];
         float vm[3], vs[3], vq[4];
-        preprocess_grad_one<DEG, true>(pv.cam, m, s, q, g.sh, nullptr, n, i, flags, gr, vm, vs,
-                                       vq, dsh);
+        preprocess_grad_one<DEG, true>(pv.cam, m, s, q, g.sh, nullptr, nullptr, n, i, flags, gr,
+                                       vm, vs, vq, dsh);
         for (int k = 0; k < 3; ++k) dm[k] += vm[k];
         for (int k = 0; k < 3; ++k) ds[k] += vs[k];
         for (int k = 0; k < 4; ++k) dq[k] += vq[k];
@@ -539,6 +592,8 @@ void launch_bwd(const tgs_gaussians& g, const PrepViews& views, const tgs_grads&
 __global__ void zero_nonfinite_kernel(PrepViews views) {
     const int v = int(threadIdx.x);
     if (v < views.count && views.v[v].nonfinite) *views.v[v].nonfinite = 0u;
+    // a one-view launch writes the backward's Jacobian and flags words
+    if (v < views.count && views.v[v].nonfinite) *jac_current(views.v[v]) = views.count == 1 ? 1u : 0u;
 }
 
 hipError_t launch_preprocess_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s) {

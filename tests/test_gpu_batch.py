@@ -268,3 +268,41 @@ def test_graph_capture_replays_match_eager_step():
             grad_close(getattr(grads, name).cpu(), r["grads"][name].to(F64), name=f"replay {rep} {name}",
                        floor=_qfloor(r) if name == "quats" else None)
     say("[gpu] 3 graph replays match the eager step")
+
+
+def test_one_view_backward_after_batched_forward_reads_the_coefficients():
+    """A one-view preprocess backward takes the colour's gradient in the view
+    direction (Sec. 3, view-dependent SH colour) from the Jacobian rows that a
+    one-view forward leaves in the workspace.  After a batched forward of
+    several views, which leaves none and clears the word beside the
+    non-finite counter, it reads the SH coefficients instead.  From the same
+    grad2d the two give bit-equal gradients of every parameter but the means,
+    where only the rounding order of the colour term differs."""
+    r = _setup()
+    b, dev = r["batch"], r["dev"]
+    n = r["sc"].n
+    b.step(dev, dev.zeros_like())                # a batched forward: no Jacobian rows
+    torch.cuda.synchronize()
+    for k, v in enumerate(b.views):
+        current = v._view(v.state.off_nonfinite_count + 4, 1, torch.int32)
+        assert int(current.item()) == 0, k
+        outs = []
+        for step in ("coefficients", "jacobian"):
+            if step == "jacobian":
+                v.preprocess_fwd(dev)            # records as before, plus the rows
+                torch.cuda.synchronize()
+                assert int(current.item()) == 1, k
+            g = dev.zeros_like()
+            pos = torch.empty(n, dtype=torch.float32, device="cuda")
+            col = torch.empty(n, dtype=torch.float32, device="cuda")
+            vis = torch.empty(n, dtype=torch.uint8, device="cuda")
+            v.preprocess_bwd(dev, g, pos, col, vis)
+            torch.cuda.synchronize()
+            outs.append(({p: getattr(g, p).cpu() for p in PARAMS}, pos.cpu(), col.cpu(), vis.cpu()))
+        (ga, pa, ca, va), (gb, pb, cb, vb) = outs
+        assert torch.equal(pa, pb) and torch.equal(ca, cb) and torch.equal(va, vb), k
+        assert int(va.sum()) > 0, k
+        for p in ("scales", "quats", "opacities", "sh"):
+            assert torch.equal(ga[p], gb[p]), (k, p)
+        grad_close(gb["means"], ga["means"].to(F64), name=f"view {k} means, Jacobian rows vs SH")
+    say(f"[gpu] {len(b.views)} views: one-view backward after a batched forward matches the rows")
