@@ -246,7 +246,9 @@ tgs_status tgs_default_launch(int32_t tile, int32_t* lds_batch, int32_t* pixels_
  * plus a 0.3 px^2 low-pass, conic, radius, SH colour, and the number of
  * tiles of the DOWNSAMPLED grid its box [u_ds +- r/d] x [v_ds +- r/d]
  * overlaps, with u_ds = (u - (d-1)/2) / d (Eq. 3-4 read as the inverse of
- * Eq. 5).  Writes records and tiles_touched into the workspace. */
+ * Eq. 5).  Writes records and tiles_touched into the workspace, and for
+ * tgs_preprocess_bwd the colour's Jacobian in the view direction (the
+ * coefficients' only other use in the backward). */
 tgs_status tgs_preprocess_fwd(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
                               const tgs_dilation* dil, const tgs_options* opt, tgs_state* st,
                               void* stream);
@@ -341,7 +343,10 @@ tgs_status tgs_raster_bwd(tgs_context* ctx, const tgs_camera* cam, const tgs_dil
  * (view-space positional gradient in NDC units of the full-resolution image),
  * col_stat = ||dL/d(r,g,b)|| (appearance gradient), visible = 1 where the
  * Gaussian overlapped at least one tile.  pos_stat, col_stat: device float[n];
- * visible: device uint8[n]; each may be NULL. */
+ * visible: device uint8[n]; each may be NULL.  Reads the records of the
+ * last preprocess on this state; after tgs_preprocess_fwd it takes the
+ * colour term from the Jacobian that call stored, after a batched
+ * preprocess of several views from the SH coefficients. */
 tgs_status tgs_preprocess_bwd(tgs_context* ctx, const tgs_gaussians* g, const tgs_camera* cam,
                               const tgs_dilation* dil, const tgs_options* opt, const tgs_state* st,
                               const tgs_grads* out, float* pos_stat, float* col_stat,
