@@ -73,11 +73,12 @@ struct Layout {
     uint64_t fwd_split;        // uint32: pixels per thread of the last forward
     uint64_t nonfinite;        // uint32: Gaussians the last preprocess culled for a
                                //   non-finite parameter (diagnostics)
-    uint64_t jac;              // float[kJacWords][n], written by a one-view preprocess:
-                               //   d rgb_c / d dir_a at row 3c + a (SH degree >= 1), then
-                               //   the record's flags | kHasTiles as a word; it follows
-                               //   tiles_touched directly (jac_rows), and the word after
-                               //   nonfinite is 1 when the last preprocess wrote it
+    uint64_t jac;              // float[kJacWords][n]: d rgb_c / d dir_a at row 3c + a
+                               //   (SH degree >= 1), written by a one-view preprocess
+                               //   (the word after nonfinite is 1 when the last one
+                               //   wrote them); row 9 the record's flags | kHasTiles as a
+                               //   word, written by every preprocess.  It follows
+                               //   tiles_touched directly (jac_rows)
     uint64_t blend_bits;       // uint64[max_tile_waves(T)][blend_words(capacity, tiles)]:
                                //   per wavefront slot of a tile and per 64 list entries
                                //   of the tile, the entries some pixel of that wavefront

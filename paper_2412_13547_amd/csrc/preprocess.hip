@@ -19,6 +19,8 @@ namespace {
 
 // Real SH basis (Condon-Shortley phase, m = -l..l), Cartesian form on the
 // unit sphere.  Constants are the closed forms in the comments.
+constexpr int kPrepThreads = 256;              // threads per block of the preprocess kernels
+
 constexpr float kC0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
 constexpr float kC1 = 0.4886025119029199f;    // sqrt(3/(4 pi))
 constexpr float kC2a = 1.0925484305920792f;   // sqrt(15/(4 pi))
@@ -274,14 +276,12 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
         dst[0] = r[0];
         dst[1] = r[1];
         dst[2] = r[2];
-        if constexpr (!MULTI) {
-            // what the one-view backward reads instead of the SH coefficients,
-            // the record and the tile count
-            float* jr = jac_rows(pv, n);
-            if constexpr (DEG >= 1)
-                for (int k = 0; k < 9; ++k) jr[k * n + i] = jac[k];
-            jr[9 * n + i] = __uint_as_float(__float_as_uint(r[2].w) | (nt > 0 ? kHasTiles : 0u));
-        }
+        // what the backward reads instead of the record and the tile count
+        // (every forward), and in place of the SH coefficients (one view)
+        float* jr = jac_rows(pv, n);
+        if constexpr (!MULTI && DEG >= 1)
+            for (int k = 0; k < 9; ++k) jr[k * n + i] = jac[k];
+        jr[9 * n + i] = __uint_as_float(__float_as_uint(r[2].w) | (nt > 0 ? kHasTiles : 0u));
         pv.touched[i] = nt;
         pv.rects[i] = rect;
         pv.depth_key[i] = nt > 0 ? __float_as_uint(r[2].y) : 0xFFFFFFFFu;
@@ -293,9 +293,10 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(tgs_gaussians g, Pr
 // gr = dL/d(u, v, A, B, C, o, r, g, b).  The colour's gradient in the view
 // direction comes from the forward's Jacobian rows jac ([9][n]) when given,
 // else from the SH coefficients sh_g ([K*3][n]); the coefficients'
-// gradients are added to dsh_acc (ACC) or written to dsh_g (single view,
-// zero where !vis: every lane stores, so each store of the wavefront covers
-// whole cache lines).
+// gradients are added to dsh_acc (ACC: this thread's column of an LDS
+// array [K*3][kPrepThreads]) or written to dsh_g (single view, zero where
+// !vis: every lane stores, so each store of the wavefront covers whole
+// cache lines).  `reload` (zero) offsets the coefficient reads.
 template <int DEG, bool ACC>
 __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const float m[3],
                                                     const float s[3], const float q[4],
@@ -304,12 +305,10 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
                                                     int64_t i, uint32_t flags,
                                                     const float gr[kGrad2d], float dm_out[3],
                                                     float ds_out[3], float dq_out[4],
-                                                    float* dsh_acc, bool vis = true) {
+                                                    float* dsh_acc, bool vis = true,
+                                                    int64_t reload = 0) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
-    Proj p;
-    if constexpr (!ACC) p = Proj{};      // lanes the view does not see compute too (and discard)
-    project(cam, m, s, q, p);
     float dm[3] = {0.0f, 0.0f, 0.0f};
 
     // ---- colour: rgb = max(sum_k sh_k Y_k(dir) + 0.5, 0), dir = (m - campos)/|.|
@@ -326,7 +325,7 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
             for (int k = 0; k < K; ++k) {
                 for (int c = 0; c < 3; ++c) {
                     const float d = Y[k] * graw[c];
-                    if constexpr (ACC) dsh_acc[k * 3 + c] += d;
+                    if constexpr (ACC) dsh_acc[(k * 3 + c) * kPrepThreads] += d;
                     else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
                 }
             }
@@ -344,10 +343,10 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
                 float acc = 0.0f;
                 for (int c = 0; c < 3; ++c) {
                     const float d = Y[k] * graw[c];
-                    if constexpr (ACC) dsh_acc[k * 3 + c] += d;
+                    if constexpr (ACC) dsh_acc[(k * 3 + c) * kPrepThreads] += d;
                     else dsh_g[(k * 3 + c) * n + i] = vis ? d : 0.0f;
                     // a Gaussian the view does not see skips the read (result unused)
-                    acc += (vis ? sh_g[(k * 3 + c) * n + i] : 0.0f) * graw[c];
+                    acc += (vis ? sh_g[(k * 3 + c) * n + i + reload] : 0.0f) * graw[c];
                 }
                 w[k] = acc;
             }
@@ -359,6 +358,11 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
         dm[1] += (gdy - dy * dot) / len;
         dm[2] += (gdz - dz * dot) / len;
     }
+
+    // the projection, after the colour so that their registers do not overlap
+    Proj p;
+    if constexpr (!ACC) p = Proj{};      // lanes the view does not see compute too (and discard)
+    project(cam, m, s, q, p);
 
     // ---- conic (A, B, C) = (c, -b, a) / det  ->  (a, b, c)
     const float a = p.a, b = p.b, c = p.c;
@@ -447,7 +451,7 @@ __device__ __forceinline__ void preprocess_grad_one(const CamDev& cam, const flo
 // and select zero at the stores, so every store instruction covers the
 // whole wavefront.
 template <int DEG>
-__global__ void __launch_bounds__(256) preprocess_bwd_kernel(
+__global__ void __launch_bounds__(kPrepThreads) preprocess_bwd_kernel(
     tgs_gaussians g, PrepViews views, tgs_grads out, float* __restrict__ pos_stat,
     float* __restrict__ col_stat, uint8_t* __restrict__ visible) {
     const int64_t n = g.n;
@@ -456,20 +460,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int kc = g.sh_coeffs;
     const PrepView& pv = views.v[0];
-    // after a one-view forward its flags word and Jacobian rows replace the
-    // record, the tile count and the SH coefficients
+    // the forward's flags word; after a one-view forward its Jacobian rows
+    // replace the SH coefficients
     const bool use_jac = pv.nonfinite && *jac_current(pv) != 0u;
     const float* jr = jac_rows(pv, n);
-    uint32_t flags;
-    bool vis;
-    if (use_jac) {
-        flags = __float_as_uint(jr[9 * n + i]);
-        vis = (flags & kHasTiles) && !(flags & kCulled);
-    } else {
-        const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
-        flags = __float_as_uint(r2.w);
-        vis = pv.touched[i] > 0 && !(flags & kCulled);
-    }
+    const uint32_t flags = __float_as_uint(jr[9 * n + i]);
+    const bool vis = (flags & kHasTiles) && !(flags & kCulled);
     float gr[kGrad2d];
     for (int k = 0; k < kGrad2d; ++k) gr[k] = vis ? pv.g2d[i * kGrad2d + k] : 0.0f;
     // parameters only of Gaussians the view sees: the others' gradients and
@@ -498,7 +494,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
 // One thread per Gaussian, several views: the gradients of every view are
 // summed in registers (in view order) and written once.
 template <int DEG>
-__global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
+__global__ void __launch_bounds__(kPrepThreads) preprocess_bwd_multi_kernel(
     tgs_gaussians g, PrepViews views, tgs_grads out, float* __restrict__ pos_stat,
     float* __restrict__ col_stat, uint8_t* __restrict__ visible) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -508,8 +504,11 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
     const int kc = g.sh_coeffs;
     float dm[3] = {0.0f, 0.0f, 0.0f}, ds[3] = {0.0f, 0.0f, 0.0f};
     float dq[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dop = 0.0f;
-    float dsh[K * 3];
-    for (int k = 0; k < K * 3; ++k) dsh[k] = 0.0f;
+    // the SH gradients summed over the views, in LDS (a column per thread):
+    // in registers they left room for one wavefront per SIMD
+    __shared__ float s_dsh[K * 3][kPrepThreads];
+    float* dsh = &s_dsh[0][threadIdx.x];
+    for (int k = 0; k < K * 3; ++k) dsh[k * kPrepThreads] = 0.0f;
     float pos = 0.0f, col = 0.0f;
     uint32_t nvis = 0;
     float m[3], s[3], q[4];
@@ -518,9 +517,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
     for (int k = 0; k < 4; ++k) q[k] = g.quats[k * n + i];
     for (int v = 0; v < views.count; ++v) {
         const PrepView& pv = views.v[v];
-        const float4 r2 = reinterpret_cast<const float4*>(pv.rec + i)[2];
-        const uint32_t flags = __float_as_uint(r2.w);
-        if (!(pv.touched[i] > 0 && !(flags & kCulled))) {
+        const uint32_t flags = __float_as_uint(jac_rows(pv, n)[9 * n + i]);   // the forward's
+        if (!((flags & kHasTiles) && !(flags & kCulled))) {
             // this view's own statistics, when asked for: zero where unseen
             if (pv.pos_out) pv.pos_out[i] = 0.0f;
             if (pv.col_out) pv.col_out[i] = 0.0f;
@@ -530,8 +528,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
         float gr[kGrad2d];
         for (int k = 0; k < kGrad2d; ++k) gr[k] = pv.g2d[i * kGrad2d + k];
         float vm[3], vs[3], vq[4];
+        // v >> 30 is 0 for every view, but not a constant: the coefficients
+        // are read again for each view (from the caches) instead of being
+        // held in 48 registers across the loop, which would leave room for
+        // only two wavefronts per SIMD
         preprocess_grad_one<DEG, true>(pv.cam, m, s, q, g.sh, nullptr, nullptr, n, i, flags, gr,
-                                       vm, vs, vq, dsh);
+                                       vm, vs, vq, dsh, true, int64_t(v >> 30));
         for (int k = 0; k < 3; ++k) dm[k] += vm[k];
         for (int k = 0; k < 3; ++k) ds[k] += vs[k];
         for (int k = 0; k < 4; ++k) dq[k] += vq[k];
@@ -551,7 +553,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_multi_kernel(
     for (int k = 0; k < 3; ++k) out.scales[k * n + i] = ds[k];
     for (int k = 0; k < 4; ++k) out.quats[k * n + i] = dq[k];
     out.opacities[i] = dop;
-    for (int k = 0; k < K * 3; ++k) out.sh[k * n + i] = dsh[k];
+    for (int k = 0; k < K * 3; ++k) out.sh[k * n + i] = dsh[k * kPrepThreads];
     for (int k = K * 3; k < kc * 3; ++k) out.sh[k * n + i] = 0.0f;
     if (pos_stat) pos_stat[i] = pos;
     if (col_stat) col_stat[i] = col;
@@ -572,7 +574,7 @@ void launch_fwd(const tgs_gaussians& g, const PrepViews& views, hipStream_t s) {
 template <bool MULTI>
 void launch_bwd(const tgs_gaussians& g, const PrepViews& views, const tgs_grads& out,
                 float* pos_stat, float* col_stat, uint8_t* visible, hipStream_t s) {
-    const dim3 block(256), nb(unsigned((g.n + 255) / 256));
+    const dim3 block(kPrepThreads), nb(unsigned((g.n + kPrepThreads - 1) / kPrepThreads));
 #define TGS_BWD(D)                                                                                 \
     if (MULTI) preprocess_bwd_multi_kernel<D><<<nb, block, 0, s>>>(g, views, out, pos_stat, col_stat, visible); \
     else preprocess_bwd_kernel<D><<<nb, block, 0, s>>>(g, views, out, pos_stat, col_stat, visible)
