@@ -189,6 +189,24 @@ def _qfloor(r):
     return r["qfloor"]
 
 
+@pytest.mark.parametrize("deg", [0, 1, 2])
+def test_batch_gradients_other_sh_degrees(deg):
+    """The multi-view preprocess backward at SH degrees 0-2 (its sums of the
+    SH gradients over the views are kept in LDS, (deg + 1)^2 x 3 floats per
+    thread): the summed gradients and statistics equal the sums of the
+    single views' (Sec. 4.3 statistics included)."""
+    r = _setup(deg=deg, specs=SPECS[:3])
+    singles = r["singles"]
+    assert r["grads"]["sh"].shape[0] >= (deg + 1) ** 2
+    for name in PARAMS:
+        want = sum(s["grads"][name].to(F64) for s in singles)
+        grad_close(r["grads"][name], want, name=f"batch SH{deg} {name}",
+                   floor=_qfloor(r) if name == "quats" else None)
+    grad_close(r["pos"], sum(s["pos_stat"].to(F64) for s in singles), name=f"SH{deg} pos_stat")
+    grad_close(r["col"], sum(s["col_stat"].to(F64) for s in singles), name=f"SH{deg} col_stat")
+    assert torch.equal(r["vis"].to(torch.int64), sum(s["visible"].to(torch.int64) for s in singles))
+
+
 @pytest.mark.parametrize("lds_batch", [64, 128])
 def test_lds_batch_does_not_change_results(lds_batch):
     base = _setup()
