@@ -594,7 +594,7 @@ void launch_bwd(const tgs_gaussians& g, const PrepViews& views, const tgs_grads&
 __global__ void zero_nonfinite_kernel(PrepViews views) {
     const int v = int(threadIdx.x);
     if (v < views.count && views.v[v].nonfinite) *views.v[v].nonfinite = 0u;
-    // a one-view launch writes the backward's Jacobian and flags words
+    // a one-view launch writes the backward's Jacobian rows (every launch the flags word)
     if (v < views.count && views.v[v].nonfinite) *jac_current(views.v[v]) = views.count == 1 ? 1u : 0u;
 }
 
